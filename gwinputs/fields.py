@@ -1,0 +1,154 @@
+"""Seeded synthetic inputs: Fock matrices F^k, three-index tensors V^{k1,k2}(Q)
+and symmetric auxiliary-basis test matrices.
+
+Recipe (one reading of the workload specification, stated once here):
+
+* raw F^k = (A + A^H)/2, A_ij = (x + i y)/sqrt(2), x, y ~ N(0,1);
+* raw V^{k1,k2}_{ij}(Q) = (x + i y)/sqrt(2) / (1 + Q/8), Q counted from 0;
+* every raw draw comes from a Philox counter-based generator keyed by
+  (seed, tensor id, first momentum index), so any row can be regenerated alone;
+* the raw tensors are projected onto the subspace fixed by three commuting
+  projections: space-group averaging (with the orbital representation of
+  ``rep.BasisRep``; for V the auxiliary index rotates with the auxiliary
+  representation at q = k2 - k1), Hermitian pairing V^{k2,k1}(Q) = V^{k1,k2}(Q)^H,
+  and time reversal X^{-k} = X^{k*};
+* F is finally rescaled, F <- a F + b I, so that its eigenvalues over all k span
+  exactly [-2, 3] Ha.
+
+Arrays are torch tensors (complex128) on the requested device; the group
+averaging of V runs on the GPU when one is used, which keeps the
+4096-pair workload to seconds.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .crystals import Workload, crystal, kmap, minus_k, mesh_points, mesh_index
+from .rep import BasisRep
+
+TENSOR_F, TENSOR_V, TENSOR_AUXMAT = 1, 2, 3
+
+
+def _philox(seed: int, tensor: int, a: int, b: int = 0) -> np.random.Generator:
+    key = (seed << 64) | (tensor << 48) | (a << 24) | b
+    return np.random.Generator(np.random.Philox(key=key))
+
+
+def _cnormal(rng, shape):
+    z = rng.standard_normal(shape + (2,))
+    return (z[..., 0] + 1j * z[..., 1]) / np.sqrt(2.0)
+
+
+class Inputs:
+    """Holds the workload, its crystal and the two orbital representations."""
+
+    def __init__(self, wl: Workload, device="cpu"):
+        self.wl = wl
+        self.cr = crystal(wl.crystal)
+        self.n = wl.n
+        self.nk = wl.nk
+        self.device = torch.device(device)
+        self.ao = BasisRep(self.cr, wl.ao, wl.n)
+        self.aux = BasisRep(self.cr, wl.aux, wl.n)
+        self.kmap = kmap(self.cr, wl.n)                 # [op, k] -> alpha k
+        self.inv_kmap = np.argsort(self.kmap, axis=1)   # [op, k] -> alpha^{-1} k
+        self.mk = minus_k(wl.n)
+        pts = mesh_points(wl.n)
+        self.sub = mesh_index(pts[None, :, :] - pts[:, None, :], wl.n)  # sub[k1,k2] = k2-k1
+        self.h = len(self.cr.ops)
+
+    def _t(self, x):
+        return torch.as_tensor(x, dtype=torch.complex128, device=self.device)
+
+    # -- two-index quantities -------------------------------------------------
+    def _sym_two_index(self, rep: BasisRep, raw: np.ndarray) -> np.ndarray:
+        """Time reversal, then group averaging, of a [Nk, ..., n, n] array."""
+        X = 0.5 * (raw + raw[self.mk].conj())
+        out = np.zeros_like(X)
+        for a in range(self.h):
+            for k in range(self.nk):
+                p = self.inv_kmap[a, k]
+                O = rep.matrix(a, p)
+                out[k] += O @ X[p] @ O.conj().T
+        return out / self.h
+
+    def fock(self) -> torch.Tensor:
+        wl = self.wl
+        raw = np.stack([_cnormal(_philox(wl.seed, TENSOR_F, k), (wl.nao, wl.nao))
+                        for k in range(self.nk)])
+        raw = 0.5 * (raw + raw.conj().transpose(0, 2, 1))
+        F = self._sym_two_index(self.ao, raw)
+        F = 0.5 * (F + F.conj().transpose(0, 2, 1))
+        ev = np.linalg.eigvalsh(F)
+        lo, hi = ev.min(), ev.max()
+        a = 5.0 / (hi - lo)
+        F = a * F + (-2.0 - a * lo) * np.eye(wl.nao)[None]
+        return self._t(F)
+
+    def aux_matrices(self, ntau: int, scale: float = 0.05, qs=None) -> torch.Tensor:
+        """Symmetric Hermitian auxiliary-basis matrices X^q(tau_j), [Nk, ntau, naux, naux];
+        used as a stand-in screened interaction for contraction-only tests."""
+        wl = self.wl
+        raw = np.stack([np.stack([_cnormal(_philox(wl.seed, TENSOR_AUXMAT, q, j), (wl.naux, wl.naux))
+                                  for j in range(ntau)]) for q in range(self.nk)])
+        raw = 0.5 * (raw + raw.conj().swapaxes(-1, -2))
+        X = self._sym_two_index(self.aux, raw)
+        X = scale * 0.5 * (X + X.conj().swapaxes(-1, -2))
+        if qs is not None:
+            X = X[list(qs)]
+        return self._t(X)
+
+    # -- three-index tensor ---------------------------------------------------
+    def _raw_V(self) -> torch.Tensor:
+        wl = self.wl
+        scale = 1.0 / (1.0 + np.arange(wl.naux) / 8.0)
+        rows = []
+        for k1 in range(self.nk):
+            r = _cnormal(_philox(wl.seed, TENSOR_V, k1), (self.nk, wl.naux, wl.nao, wl.nao))
+            r *= scale[None, :, None, None]
+            rows.append(torch.as_tensor(r, dtype=torch.complex128).to(self.device))
+        return torch.stack(rows)
+
+    def _paired_V(self) -> torch.Tensor:
+        """Hermitian pairing and time reversal of the raw tensor, all pairs."""
+        raw = self._raw_V()
+        mk = torch.as_tensor(self.mk, device=self.device)
+        W = raw.clone()
+        W += raw.transpose(0, 1).conj().transpose(-1, -2)          # V^{k2,k1}(Q)^H
+        W += raw[mk][:, mk].conj()                                   # V^{-k1,-k2}(Q)^*
+        W += raw.transpose(0, 1)[mk][:, mk].transpose(-1, -2)        # V^{-k2,-k1}(Q)^T
+        del raw
+        return W * 0.25
+
+    def three_index(self, pairs, chunk: int = 256) -> torch.Tensor:
+        """Symmetric V^{k1,k2} for the given list of (k1, k2): [len(pairs), naux, nao, nao]."""
+        pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+        W = self._paired_V()
+        wl = self.wl
+        out = torch.zeros((len(pairs), wl.naux, wl.nao, wl.nao), dtype=torch.complex128,
+                          device=self.device)
+        for a in range(self.h):
+            Oao = self._t(np.stack([self.ao.matrix(a, k) for k in range(self.nk)]))
+            Oaux = self._t(np.stack([self.aux.matrix(a, q) for q in range(self.nk)]))
+            for c0 in range(0, len(pairs), chunk):
+                pc = pairs[c0:c0 + chunk]
+                p1 = self.inv_kmap[a, pc[:, 0]]
+                p2 = self.inv_kmap[a, pc[:, 1]]
+                q0 = self.sub[p1, p2]
+                Wsel = W[torch.as_tensor(p1, device=self.device), torch.as_tensor(p2, device=self.device)]
+                L = Oao[torch.as_tensor(p1, device=self.device)]
+                R = Oao[torch.as_tensor(p2, device=self.device)]
+                T = L[:, None] @ Wsel @ R.conj().transpose(-1, -2)[:, None]
+                X = Oaux[torch.as_tensor(q0, device=self.device)]
+                T = (X @ T.reshape(len(pc), wl.naux, wl.nao * wl.nao)).reshape(T.shape)
+                out[c0:c0 + chunk] += T
+        del W
+        return out / self.h
+
+    def three_index_full(self) -> torch.Tensor:
+        """V^{k1,k2} for every pair of the mesh: [Nk, Nk, naux, nao, nao]."""
+        nk = self.nk
+        pairs = [(a, b) for a in range(nk) for b in range(nk)]
+        V = self.three_index(pairs)
+        return V.reshape(nk, nk, *V.shape[1:])

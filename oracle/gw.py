@@ -1,0 +1,236 @@
+"""Plain FP64 CPU oracle for one finite-temperature GW iteration.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module.  It shares no code with the
+GPU library and never takes an input produced by it.
+
+Everything here works with full matrices over the full Brillouin zone and uses
+no symmetry at all.  Arrays (complex128, numpy):
+
+  F[k, i, j]                 Fock / one-body matrix H0 + Sigma_HF (held fixed)
+  V[k1, k2, Q, i, j]         density-fitted three-index tensor V^{k1,k2}_{ij}(Q)
+  G[k, t, i, j]              Green's function G^k(tau_t)
+  P0[q, t, Q, Q'], P[q, t, Q, Q']
+  S[k, t, i, j]              dynamic self-energy Sigma~^k(tau_t)
+
+k, q are linear indices of a Gamma-centred n^3 mesh (index (m0 n + m1) n + m2);
+sums and differences of momenta are reduced on the mesh.
+
+Readings of the paper used here (each also listed in the design notes):
+  * P0 carries an overall minus sign with G^k(beta - tau) in place of G^k(-tau)
+    (Sec. 4.1, eq. for P0; the fermionic antiperiodicity G(-tau) = -G(beta-tau)
+    turns the printed form into a positive-semidefinite P0, which would make
+    I - P0 singular), and an explicit spin factor s.
+  * tau grid: Chebyshev-Gauss-Lobatto nodes; Matsubara transforms through the
+    degree-(ntau-1) interpolating polynomial; the inverse transform is the
+    least-squares inverse over n >= 0 and the conjugate rows n < 0.
+  * nw = 2 ntau + 1 frequencies stored for n >= 0.
+  * S^k = identity (orthonormal synthetic basis).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# grids and transforms (Sec. 4.1: G(i w_n) = int_0^beta G(tau) e^{i w_n tau};
+# eq. P02P: bosonic frequencies Omega_n = 2 n pi / beta)
+
+
+def tau_grid(beta: float, ntau: int) -> np.ndarray:
+    """Chebyshev-Gauss-Lobatto nodes on [0, beta]; tau_0 = 0, tau_{ntau-1} = beta,
+    and tau_{ntau-1-j} = beta - tau_j."""
+    j = np.arange(ntau)
+    return 0.5 * beta * (1.0 - np.cos(np.pi * j / (ntau - 1)))
+
+
+def matsubara(beta: float, nw: int, boson: bool) -> np.ndarray:
+    n = np.arange(nw)
+    return (2 * n + (0 if boson else 1)) * np.pi / beta
+
+
+def _cheb_vander(x: np.ndarray, deg: int) -> np.ndarray:
+    return np.polynomial.chebyshev.chebvander(x, deg)
+
+
+def fourier_of_chebyshev(beta: float, ntau: int, nu: np.ndarray) -> np.ndarray:
+    """Fmat[n, l] = int_0^beta T_l(2 tau / beta - 1) exp(i nu_n tau) d tau, by
+    Gauss-Legendre quadrature with enough nodes to be exact to rounding."""
+    nq = int(2 * (ntau + nu.max() * beta / 2)) + 100
+    xq, wq = np.polynomial.legendre.leggauss(nq)
+    tq = 0.5 * beta * (xq + 1.0)
+    Tq = _cheb_vander(xq, ntau - 1)
+    return (np.exp(1j * np.outer(nu, tq)) * (0.5 * beta * wq)) @ Tq
+
+
+def transform_matrices(beta: float, ntau: int, nw: int, boson: bool):
+    """Returns (Tfwd, Binv, rows).
+
+    Tfwd[n, j]: X(i nu_n) = sum_j Tfwd[n, j] X(tau_j) for the polynomial through
+    the samples (n = 0 ... nw-1).
+    Binv[j, r]: the least-squares inverse of the stacked system
+    [X(i nu_n), n = 0..nw-1 ; X(-i nu_n) = X(i nu_n)^H, n in rows] -> X(tau_j);
+    for bosons the n = 0 row is not repeated in the conjugate half.
+    """
+    tau = tau_grid(beta, ntau)
+    x = 2.0 * tau / beta - 1.0
+    Vm = _cheb_vander(x, ntau - 1)                      # Vm[j, l] = T_l(x_j)
+    nu = matsubara(beta, nw, boson)
+    Fm = fourier_of_chebyshev(beta, ntau, nu)           # Fm[n, l]
+    Tfwd = np.linalg.solve(Vm.T, Fm.T).T                 # Fm @ inv(Vm)
+    conj_rows = np.arange(1, nw) if boson else np.arange(nw)
+    S = np.vstack([Fm, Fm[conj_rows].conj()])
+    Binv = Vm @ np.linalg.pinv(S)
+    return Tfwd, Binv, conj_rows
+
+
+def to_freq(X: np.ndarray, Tfwd: np.ndarray) -> np.ndarray:
+    """X[..., t, a, b] -> X[..., n, a, b]."""
+    return np.einsum("nt,...tab->...nab", Tfwd, X)
+
+
+def to_tau(Xw: np.ndarray, Binv: np.ndarray, conj_rows: np.ndarray) -> np.ndarray:
+    """Applies the least-squares inverse to the stacked data [X(i nu_n); X(i nu_n)^H]."""
+    nw = Xw.shape[-3]
+    stacked = np.concatenate([Xw, np.conj(np.swapaxes(Xw[..., conj_rows, :, :], -1, -2))],
+                             axis=-3)
+    return np.einsum("tr,...rab->...tab", Binv, stacked)
+
+
+# ----------------------------------------------------------------------------
+# free Green's function (spec closed form; Sec. 4.1 definition of G)
+
+
+def fermi_factor_parts(eps: np.ndarray, tau: np.ndarray, beta: float) -> np.ndarray:
+    """g[..., t, i] = exp(-eps tau) / (1 + exp(-beta eps)), evaluated without overflow
+    (for eps < 0 the equal form exp(eps (beta - tau)) / (1 + exp(beta eps)) is used)."""
+    e = eps[..., None, :]
+    t = tau[:, None]
+    ep = np.maximum(e, 0.0)
+    en = np.minimum(e, 0.0)
+    a = np.exp(-ep * t) / (1.0 + np.exp(-beta * ep))
+    b = np.exp(en * (beta - t)) / (1.0 + np.exp(beta * en))
+    return np.where(e >= 0, a, b)
+
+
+def g0_closed_form(F: np.ndarray, mu: float, beta: float, tau: np.ndarray) -> np.ndarray:
+    """G0^k(tau) = -U diag(exp(-e tau)/(1 + exp(-beta e))) U^H with F^k - mu = U diag(e) U^H."""
+    nao = F.shape[-1]
+    e, U = np.linalg.eigh(F - mu * np.eye(nao))
+    g = fermi_factor_parts(e, tau, beta)                 # [k, t, i]
+    return -np.einsum("kai,kti,kbi->ktab", U, g, U.conj())
+
+
+def free_count(F: np.ndarray, mu: float, beta: float, spin: float) -> float:
+    """(s / Nk) sum_k sum_i 1/(1 + exp(beta (e_i - mu))), the free electron count (Sec. 4.1, N_e)."""
+    e = np.linalg.eigvalsh(F) - mu
+    f = np.where(e >= 0, np.exp(-beta * np.abs(e)) / (1 + np.exp(-beta * np.abs(e))),
+                 1.0 / (1 + np.exp(-beta * np.abs(e))))
+    return spin * f.sum() / F.shape[0]
+
+
+# ----------------------------------------------------------------------------
+# contractions (eq. P0 and eq. sigma of Sec. 4.1)
+
+
+def polarization(G: np.ndarray, V: np.ndarray, add: np.ndarray, spin: float) -> np.ndarray:
+    """P0^q_{QQ'}(tau_j) = -(s/Nk) sum_k Tr[V^{k,k+q}(Q) G^{k+q}(tau_j) V^{k+q,k}(Q') G^k(beta - tau_j)]
+    with V^{k+q,k}(Q') = V^{k,k+q}(Q')^H and G^k(beta - tau_j) = G^k(tau_{ntau-1-j})."""
+    nk, nt, nao, _ = G.shape
+    naux = V.shape[2]
+    P0 = np.zeros((nk, nt, naux, naux), dtype=complex)
+    Grev = G[:, ::-1]
+    for q in range(nk):
+        for k in range(nk):
+            kq = add[k, q]
+            A = V[k, kq]                                         # [Q, a, b]
+            AH = np.conj(np.swapaxes(A, -1, -2))                 # V^{k+q,k}(Q') = A(Q')^H
+            X1 = A[None] @ G[kq][:, None]                        # [t, Q, a, b] = A(Q) G^{k+q}
+            X2 = AH[None] @ Grev[k][:, None]                     # [t, Q', b, a] = A(Q')^H G^k(b-t)
+            # Tr[X1(Q) X2(Q')] = sum_{ab} X1[Q,a,b] X2[Q',b,a]
+            X2t = np.swapaxes(X2, -1, -2).reshape(nt, naux, nao * nao)
+            P0[q] += X1.reshape(nt, naux, nao * nao) @ np.swapaxes(X2t, -1, -2)
+    return -(spin / nk) * P0
+
+
+def self_energy(G: np.ndarray, V: np.ndarray, P: np.ndarray, sub: np.ndarray) -> np.ndarray:
+    """Sigma~^k_{ij}(tau) = -(1/Nk) sum_q sum_{ab} sum_{QQ'} G^{k-q}_{ab}(tau) V^{k,k-q}_{ia}(Q)
+    P^q_{QQ'}(tau) V^{k-q,k}_{bj}(Q'), V^{k-q,k}(Q') = V^{k,k-q}(Q')^H.
+    sub[k, q] is the index of k - q."""
+    nk, nt, nao, _ = G.shape
+    naux = V.shape[2]
+    S = np.zeros((nk, nt, nao, nao), dtype=complex)
+    for k in range(nk):
+        for q in range(nk):
+            kmq = sub[k, q]
+            A = V[k, kmq]                                        # [Q, i, a]
+            X1 = A[None] @ G[kmq][:, None]                       # [t, Q, i, b]
+            Y = np.swapaxes(P[q], -1, -2) @ X1.reshape(nt, naux, nao * nao)   # sum_Q P[Q,Q'] X1[Q]
+            Y = Y.reshape(nt, naux, nao, nao)                    # [t, Q', i, b]
+            # sum_{Q', b} Y[Q', i, b] conj(A[Q', j, b])
+            Yf = np.swapaxes(Y, 1, 2).reshape(nt, nao, naux * nao)
+            Af = np.conj(np.swapaxes(A, 0, 1).reshape(nao, naux * nao))
+            S[k] += Yf @ Af.T
+    return -(1.0 / nk) * S
+
+
+# ----------------------------------------------------------------------------
+# screened interaction (eq. P02P) and Dyson equation (eq. dyson)
+
+
+def screened(P0: np.ndarray, beta: float, nw: int):
+    """P(i Omega_n) = [I - P0(i Omega_n)]^{-1} P0(i Omega_n), then back to tau.
+    Returns (P(tau), P0(i Omega), P(i Omega))."""
+    nk, nt, naux, _ = P0.shape
+    Tb, Bb, rows = transform_matrices(beta, nt, nw, boson=True)
+    P0w = to_freq(P0, Tb)
+    I = np.eye(naux)
+    Pw = np.linalg.solve(I - P0w, P0w)
+    return to_tau(Pw, Bb, rows), P0w, Pw
+
+
+def dyson(F: np.ndarray, Sigma: np.ndarray, mu: float, beta: float, nw: int):
+    """G(i w_n) = [(i w_n + mu) I - F - Sigma~(i w_n)]^{-1} (S = I), then back to tau.
+    Returns (G(tau), G(i w), Sigma~(i w))."""
+    nk, nt, nao, _ = Sigma.shape
+    Tf, Bf, rows = transform_matrices(beta, nt, nw, boson=False)
+    Sw = to_freq(Sigma, Tf)
+    w = matsubara(beta, nw, boson=False)
+    I = np.eye(nao)
+    A = (1j * w[:, None, None] + mu) * I[None] - F[:, None] - Sw
+    Gw = np.linalg.inv(A)
+    return to_tau(Gw, Bf, rows), Gw, Sw
+
+
+def particle_number(G: np.ndarray, spin: float) -> float:
+    """N_e = (s/Nk) sum_k Tr[gamma^k], gamma^k = G^k(tau = 0^-) = -G^k(beta) (S = I)."""
+    nk = G.shape[0]
+    return float(np.real(spin / nk * np.trace(-G[:, -1], axis1=-2, axis2=-1).sum()))
+
+
+def find_mu(F, Sigma, n_target, beta, nw, spin, steps=64):
+    """Bisection on the strictly increasing N(mu) over [min eps - 20, max eps + 20]."""
+    e = np.linalg.eigvalsh(F)
+    lo, hi = e.min() - 20.0, e.max() + 20.0
+    for _ in range(steps):
+        mid = 0.5 * (lo + hi)
+        G, _, _ = dyson(F, Sigma, mid, beta, nw)
+        if particle_number(G, spin) < n_target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+# ----------------------------------------------------------------------------
+# one iteration (Alg. 2 order: P0 -> P -> Sigma -> Dyson)
+
+
+def gw_iteration(F, V, G, mu, beta, nw, spin, add, sub, n_target=None, mu_steps=64):
+    """One GW iteration from G.  With n_target None, mu stays fixed."""
+    P0 = polarization(G, V, add, spin)
+    P, P0w, Pw = screened(P0, beta, nw)
+    Sigma = self_energy(G, V, P, sub)
+    if n_target is not None:
+        mu = find_mu(F, Sigma, n_target, beta, nw, spin, mu_steps)
+    Gn, Gw, Sw = dyson(F, Sigma, mu, beta, nw)
+    return dict(P0=P0, P=P, P0w=P0w, Pw=Pw, Sigma=Sigma, Sigmaw=Sw, G=Gn, Gw=Gw, mu=mu)

@@ -1,0 +1,359 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, brute-force index sums on tiny inputs, exact identities of the
+imaginary-time formalism, the group relation, and the irreducible-wedge counts
+printed in the paper's Table 2.  A test at the end plants plausible mistakes in
+copies of the oracle's contractions and checks that these pins catch them."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from gwinputs import (Inputs, workload, add_k, minus_k, kmap, crystal, cubic_point_group,
+                      in_td, mesh_points, mesh_index)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _herm(X):
+    return 0.5 * (X + np.conj(np.swapaxes(X, -1, -2)))
+
+
+def _sub_table(n):
+    add, mk = add_k(n), minus_k(n)
+    nk = n ** 3
+    return np.array([[add[k, mk[q]] for q in range(nk)] for k in range(nk)])
+
+
+# ----------------------------------------------------------------------------- P1
+
+def test_g0_closed_form_identities():
+    rng = np.random.default_rng(1)
+    nk, nao, beta = 3, 5, 40.0
+    A = rng.standard_normal((nk, nao, nao)) + 1j * rng.standard_normal((nk, nao, nao))
+    F = _herm(A)
+    tau = oracle.tau_grid(beta, 20)
+    G = oracle.g0_closed_form(F, 0.3, beta, tau)
+    I = np.eye(nao)
+    assert np.abs(G - np.conj(np.swapaxes(G, -1, -2))).max() < 1e-15
+    # G(0+) + G(beta-) = -I
+    assert np.abs(G[:, 0] + G[:, -1] + I).max() < 1e-14
+    # gamma = -G(beta) has the Fermi occupations as eigenvalues
+    occ = np.linalg.eigvalsh(-G[:, -1])
+    e = np.linalg.eigvalsh(F - 0.3 * I)
+    f = 1.0 / (1.0 + np.exp(beta * e))
+    assert np.abs(np.sort(occ, axis=-1) - np.sort(f, axis=-1)).max() < 1e-14
+    assert occ.min() > -1e-14 and occ.max() < 1 + 1e-14
+
+
+def test_g0_matches_matrix_exponential_route():
+    rng = np.random.default_rng(2)
+    nao, beta, mu = 4, 5.0, -0.1
+    A = rng.standard_normal((1, nao, nao)) + 1j * rng.standard_normal((1, nao, nao))
+    F = 0.5 * _herm(A)
+    tau = oracle.tau_grid(beta, 9)
+    G = oracle.g0_closed_form(F, mu, beta, tau)[0]
+    H = F[0] - mu * np.eye(nao)
+    Z = np.linalg.inv(np.eye(nao) + sla.expm(-beta * H))
+    for j, t in enumerate(tau):
+        ref = -sla.expm(-t * H) @ Z
+        assert np.abs(G[j] - ref).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------- P2
+
+def _tiny_inputs(seed=3, n=3, nao=2, naux=3, nt=4):
+    rng = np.random.default_rng(seed)
+    nk = n ** 3
+    V = (rng.standard_normal((nk, nk, naux, nao, nao))
+         + 1j * rng.standard_normal((nk, nk, naux, nao, nao)))
+    V = 0.5 * (V + np.conj(np.swapaxes(V.transpose(1, 0, 2, 3, 4), -1, -2)))  # V^{k2,k1} = V^{k1,k2 H}
+    G = _herm(rng.standard_normal((nk, nt, nao, nao)) + 1j * rng.standard_normal((nk, nt, nao, nao)))
+    P = _herm(rng.standard_normal((nk, nt, naux, naux)) + 1j * rng.standard_normal((nk, nt, naux, naux)))
+    return V, G, P
+
+
+def test_bruteforce_polarization():
+    n, s = 3, 2.0
+    V, G, _ = _tiny_inputs()
+    nk, nt, nao, _ = G.shape
+    naux = V.shape[2]
+    add = add_k(n)
+    ref = np.zeros((nk, nt, naux, naux), complex)
+    for q in range(nk):
+        for j in range(nt):
+            for Q in range(naux):
+                for Qp in range(naux):
+                    acc = 0j
+                    for k in range(nk):
+                        kq = add[k, q]
+                        for a in range(nao):
+                            for b in range(nao):
+                                for c in range(nao):
+                                    for d in range(nao):
+                                        acc += (V[k, kq, Q, d, a] * G[k, nt - 1 - j, c, d]
+                                                * G[kq, j, a, b] * V[kq, k, Qp, b, c])
+                    ref[q, j, Q, Qp] = -s / nk * acc
+    got = oracle.polarization(G, V, add, s)
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_bruteforce_self_energy():
+    n = 3
+    V, G, P = _tiny_inputs(seed=4)
+    nk, nt, nao, _ = G.shape
+    naux = V.shape[2]
+    sub = _sub_table(n)
+    ref = np.zeros((nk, nt, nao, nao), complex)
+    for k in range(nk):
+        for j in range(nt):
+            for i in range(nao):
+                for jj in range(nao):
+                    acc = 0j
+                    for q in range(nk):
+                        kmq = sub[k, q]
+                        for a in range(nao):
+                            for b in range(nao):
+                                for Q in range(naux):
+                                    for Qp in range(naux):
+                                        acc += (G[kmq, j, a, b] * V[k, kmq, Q, i, a]
+                                                * P[q, j, Q, Qp] * V[kmq, k, Qp, b, jj])
+                    ref[k, j, i, jj] = -acc / nk
+    got = oracle.self_energy(G, V, P, sub)
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+# ----------------------------------------------------------------------------- P3
+
+def _two_level(eps1, eps2, v, beta, s, nt):
+    F = np.diag([eps1, eps2]).astype(complex)[None]
+    V = np.zeros((1, 1, 1, 2, 2), complex)
+    V[0, 0, 0, 0, 1] = v
+    V[0, 0, 0, 1, 0] = np.conj(v)
+    tau = oracle.tau_grid(beta, nt)
+    G = oracle.g0_closed_form(F, 0.0, beta, tau)
+    P0 = oracle.polarization(G, V, np.zeros((1, 1), int), s)[0, :, 0, 0]
+    f1, f2 = 1 / (1 + np.exp(beta * eps1)), 1 / (1 + np.exp(beta * eps2))
+    dlt = eps2 - eps1
+    ref = -s * abs(v) ** 2 * (f1 * (1 - f2) * np.exp(-dlt * tau) + f2 * (1 - f1) * np.exp(dlt * tau))
+    return tau, P0, ref, f1, f2, dlt
+
+
+def test_two_level_polarization_closed_form():
+    beta, s, v = 10.0, 2.0, 0.7 - 0.2j
+    tau, P0, ref, f1, f2, dlt = _two_level(-0.3, 0.5, v, beta, s, 40)
+    assert np.abs(P0 - ref).max() < 1e-14
+    assert np.abs(P0 - P0[::-1]).max() < 1e-14          # tau -> beta - tau
+    Tb, _, _ = oracle.transform_matrices(beta, 40, 81, boson=True)
+    P0w = Tb @ P0
+    Om = oracle.matsubara(beta, 81, boson=True)
+    refw = -2 * s * abs(v) ** 2 * (f1 - f2) * dlt / (Om ** 2 + dlt ** 2)
+    assert np.abs(P0w - refw).max() < 1e-10
+    assert (P0w.real <= 1e-12).all()
+
+
+# ----------------------------------------------------------------------------- P12, P13
+
+def test_transform_exact_on_polynomials():
+    beta, nt, nw = 2.0, 12, 25
+    tau = oracle.tau_grid(beta, nt)
+    for boson in (False, True):
+        Tf, _, _ = oracle.transform_matrices(beta, nt, nw, boson)
+        nu = oracle.matsubara(beta, nw, boson)
+        for m in range(0, 6):
+            got = Tf @ tau ** m
+            ref = np.empty(nw, complex)
+            for i, w in enumerate(nu):
+                if w == 0:
+                    ref[i] = beta ** (m + 1) / (m + 1)
+                    continue
+                I = (np.exp(1j * w * beta) - 1) / (1j * w)
+                for p in range(1, m + 1):
+                    I = beta ** p * np.exp(1j * w * beta) / (1j * w) - p / (1j * w) * I
+                ref[i] = I
+            assert np.abs(got - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("boson", [False, True])
+def test_transform_round_trip(boson):
+    beta, nt = 100.0, 40
+    nw = 2 * nt + 1
+    rng = np.random.default_rng(5)
+    X = _herm(rng.standard_normal((nt, 3, 3)) + 1j * rng.standard_normal((nt, 3, 3)))
+    Tf, Bf, rows = oracle.transform_matrices(beta, nt, nw, boson)
+    back = oracle.to_tau(oracle.to_freq(X, Tf), Bf, rows)
+    assert np.abs(back - X).max() < 1e-11
+
+
+def test_dyson_free_limit_matches_closed_form_and_analytic_frequency():
+    rng = np.random.default_rng(6)
+    nao, beta, mu, nt = 4, 10.0, 0.2, 40
+    nw = 2 * nt + 1
+    F = 0.5 * _herm(rng.standard_normal((2, nao, nao)) + 1j * rng.standard_normal((2, nao, nao)))
+    tau = oracle.tau_grid(beta, nt)
+    G0 = oracle.g0_closed_form(F, mu, beta, tau)
+    Tf, _, _ = oracle.transform_matrices(beta, nt, nw, boson=False)
+    w = oracle.matsubara(beta, nw, boson=False)
+    Gw_ref = np.linalg.inv((1j * w[:, None, None] + mu) * np.eye(nao) - F[:, None])
+    assert np.abs(oracle.to_freq(G0, Tf) - Gw_ref).max() < 1e-8
+    G, Gw, _ = oracle.dyson(F, np.zeros((2, nt, nao, nao), complex), mu, beta, nw)
+    assert np.abs(Gw - Gw_ref).max() < 1e-15
+    assert np.abs(G - G0).max() < 1e-8
+
+
+# ----------------------------------------------------------------------------- P4-P6, P14, P15 on a workload
+
+@pytest.fixture(scope="module")
+def diamond_run():
+    wl = workload("small_diamond")
+    inp = Inputs(wl)
+    F = inp.fock().numpy()
+    V = inp.three_index_full().numpy()
+    tau = oracle.tau_grid(wl.beta, wl.ntau)
+    G0 = oracle.g0_closed_form(F, 0.0, wl.beta, tau)
+    add, sub = add_k(wl.n), _sub_table(wl.n)
+    nt = oracle.free_count(F, 0.0, wl.beta, wl.spin)
+    r = oracle.gw_iteration(F, V, G0, 0.0, wl.beta, wl.nw, wl.spin, add, sub, n_target=nt)
+    return dict(wl=wl, inp=inp, F=F, V=V, G0=G0, r=r, n_target=nt)
+
+
+def test_hermiticity(diamond_run):
+    r = diamond_run["r"]
+    for key in ("P0", "P", "Sigma", "G"):
+        X = r[key]
+        assert np.abs(X - np.conj(np.swapaxes(X, -1, -2))).max() < 1e-13 * np.abs(X).max(), key
+
+
+def test_bosonic_mirror_with_time_reversal(diamond_run):
+    r = diamond_run["r"]
+    for key in ("P0", "P"):
+        X = r[key]
+        assert np.abs(X - X[:, ::-1]).max() < 1e-12 * np.abs(X).max(), key
+
+
+def test_bosonic_mirror_without_time_reversal():
+    # P^q(beta - tau) = P^{-q}(tau)^T holds for any Hermitian-paired input
+    n, s = 3, 2.0
+    V, G, _ = _tiny_inputs(seed=8, nao=3, naux=4, nt=6)
+    add, mk = add_k(n), minus_k(n)
+    P0 = oracle.polarization(G, V, add, s)
+    assert np.abs(P0[:, ::-1] - np.swapaxes(P0[mk], -1, -2)).max() < 1e-13 * np.abs(P0).max()
+
+
+def test_group_relation(diamond_run):
+    inp, r = diamond_run["inp"], diamond_run["r"]
+    for a in range(inp.h):
+        for k in range(inp.nk):
+            ak = inp.kmap[a, k]
+            O = inp.ao.matrix(a, k)
+            Ob = inp.aux.matrix(a, k)
+            for key, M in (("Sigma", O), ("G", O), ("P", Ob), ("P0", Ob)):
+                X = r[key]
+                rot = M[None] @ X[k] @ M.conj().T[None]
+                assert np.abs(rot - X[ak]).max() < 1e-12 * np.abs(X).max(), (key, a, k)
+
+
+def test_screened_invariants(diamond_run):
+    r = diamond_run["r"]
+    P0w, Pw = r["P0w"], r["Pw"]
+    assert np.abs(P0w - np.conj(np.swapaxes(P0w, -1, -2))).max() < 1e-12
+    ev0 = np.linalg.eigvalsh(_herm(P0w))
+    assert ev0.max() < 1e-12
+    evP = np.linalg.eigvalsh(_herm(Pw))
+    assert evP.min() > -1.0 and evP.max() < 1e-12
+
+
+def test_particle_number_and_mu(diamond_run):
+    wl, F = diamond_run["wl"], diamond_run["F"]
+    nt = wl.ntau
+    Z = np.zeros((wl.nk, nt, wl.nao, wl.nao), complex)
+    Ns = []
+    for mu in (-0.5, -0.1, 0.0, 0.1, 0.5):
+        G, _, _ = oracle.dyson(F, Z, mu, wl.beta, wl.nw)
+        Ns.append(oracle.particle_number(G, wl.spin))
+    assert all(b > a for a, b in zip(Ns, Ns[1:]))
+    mu = oracle.find_mu(F, Z, Ns[2], wl.beta, wl.nw, wl.spin)
+    assert abs(mu) < 1e-12
+    r = diamond_run["r"]
+    assert abs(oracle.particle_number(r["G"], wl.spin) - diamond_run["n_target"]) < 1e-10
+
+
+# ----------------------------------------------------------------------------- Table 2 counts
+
+def _ibz_count(ops_frac, n):
+    pts = mesh_points(n)
+    seen = np.zeros(len(pts), bool)
+    count = 0
+    for k in range(len(pts)):
+        if seen[k]:
+            continue
+        count += 1
+        for W in ops_frac:
+            WiT = np.rint(np.linalg.inv(W).T).astype(np.int64)
+            seen[mesh_index(WiT @ pts[k], n)] = True
+    return count
+
+
+def test_table2_irreducible_counts():
+    gold = json.load(open(os.path.join(HERE, "golden", "table2_nik.json")))
+    oh = cubic_point_group()
+    A = crystal("rocksalt").lattice
+    Ai = np.linalg.inv(A)
+    frac = {"Oh": [np.rint(Ai @ R @ A).astype(np.int64) for R in oh],
+            "Td": [np.rint(Ai @ R @ A).astype(np.int64) for R in oh if in_td(R)]}
+    for g, d in gold["groups"].items():
+        for nkk, cnt in d["nik"].items():
+            assert _ibz_count(frac[d["point_group"]], int(nkk)) == cnt, (g, nkk)
+
+
+def test_workload_star_sizes():
+    cr = crystal("sc")
+    km = kmap(cr, 4)
+    sizes = sorted(len(set(km[:, k])) for k in range(64) if k == min(km[:, k]))
+    assert sizes == [1, 1, 3, 3, 6, 6, 8, 12, 12, 12]
+    cr = crystal("rocksalt")
+    km = kmap(cr, 6)
+    sizes = sorted(len(set(km[:, k])) for k in range(216) if k == min(km[:, k]))
+    assert sizes == [1, 3, 4, 6, 6, 8, 8, 12, 12, 12, 24, 24, 24, 24, 24, 24]
+
+
+# ----------------------------------------------------------------------------- planted mistakes
+
+def _mutant(func, old, new):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(func))
+    assert old in src
+    src = src.replace(old, new)
+    ns = dict(func.__globals__)
+    exec(compile(src, "<mutant>", "exec"), ns)
+    return ns[func.__name__]
+
+
+MUTATIONS = [
+    (oracle.polarization, "Grev = G[:, ::-1]", "Grev = G"),
+    (oracle.polarization, "return -(spin / nk) * P0", "return (spin / nk) * P0"),
+    (oracle.polarization, "AH = np.conj(np.swapaxes(A, -1, -2))", "AH = np.swapaxes(A, -1, -2)"),
+    (oracle.polarization, "kq = add[k, q]", "kq = add[q, q]"),
+    (oracle.self_energy, "Y = np.swapaxes(P[q], -1, -2) @", "Y = P[q] @"),
+    (oracle.self_energy, "kmq = sub[k, q]", "kmq = sub[q, k]"),
+    (oracle.self_energy, "Af = np.conj(", "Af = ("),
+]
+
+
+@pytest.mark.parametrize("func,old,new", MUTATIONS)
+def test_planted_mistakes_are_caught(func, old, new):
+    bad = _mutant(func, old, new)
+    n, s = 3, 2.0
+    V, G, P = _tiny_inputs(seed=11, nao=3, naux=4, nt=6)
+    if func is oracle.polarization:
+        good = oracle.polarization(G, V, add_k(n), s)
+        got = bad(G, V, add_k(n), s)
+    else:
+        good = oracle.self_energy(G, V, P, _sub_table(n))
+        got = bad(G, V, P, _sub_table(n))
+    # the brute-force pins above compare `good` with the printed index sums;
+    # a planted mistake must move the result far outside their tolerance
+    assert np.abs(got - good).max() > 1e-6 * np.abs(good).max()
