@@ -1,0 +1,213 @@
+/*
+ * gwsym: symmetry-adapted finite-temperature GW hot path for AMD MI355X (gfx950).
+ *
+ * One GW iteration (Alg. 2 of the paper) on density-fitted three-index Coulomb
+ * tensors V^{k1,k2}(Q), restricted to the irreducible wedge of the Brillouin zone
+ * and block-diagonalised into the isotypic blocks found by simultaneous
+ * diagonalisation of Dirac characters (Sec. 3.4, Alg. 1):
+ *
+ *   polarization          P0^q(tau)  (eq. P0, Alg. 3)
+ *   screened_interaction  P^q = [I - P0^q]^{-1} P0^q at bosonic frequencies (eq. P02P)
+ *   self_energy           Sigma~^k(tau)  (eq. sigma, Alg. 4)
+ *   find_mu, dyson_G      G^k(i w_n) = [(i w_n + mu) S - H0 - Sigma(i w_n)]^{-1} (eq. dyson), N_e fixed
+ *
+ * Conventions
+ *   - Complex numbers are interleaved (re, im) IEEE doubles (C99 double _Complex layout).
+ *   - Matrices are row-major.
+ *   - "Device" pointers are MI355X global-memory addresses (hipMalloc / torch CUDA tensors);
+ *     "host" pointers are ordinary CPU memory.  Every device pointer argument must stay
+ *     valid until the work queued on `stream` has finished.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  Every device-side
+ *     call only enqueues work on `stream` and returns; no call synchronises the host unless
+ *     it says so.  A context is used from one host thread at a time.
+ *   - Errors: every call returns GWSYM_OK (0) or a negative gwsym_status; arguments are
+ *     checked before anything is enqueued.  gwsym_last_error() gives the message.  A fault
+ *     inside a kernel surfaces at the next synchronising HIP call of the caller.
+ *   - Ownership: the context owns its symmetry tables, the transformed V tensors and every
+ *     workspace (allocated in gwsym_device_init / gwsym_load_V, freed by gwsym_destroy).
+ *     The caller owns every buffer it passes in.
+ *
+ * Block-packed layouts ("blk"), read with gwsym_get ("ao_blocks", "g_off", ...):
+ *   For each irreducible point i (in increasing mesh-index order of the representatives)
+ *   the orbital blocks r of sizes n_r (sum n_r = nao) are stored one after another, each
+ *   n_r x n_r row-major: "packed_ao(i)" = sum_r n_r^2 complex numbers.  Likewise the
+ *   auxiliary blocks s of sizes m_s: "packed_aux(i)" = sum_s m_s^2.
+ *     F_blk     : [i][packed_ao(i)]
+ *     G_blk, Sigma_blk : [i][tau][packed_ao(i)]        (offset of i: query "g_off")
+ *     P0_blk, P_blk    : [i][tau][packed_aux(i)]       (offset of i: query "p_off")
+ *   In GWSYM_MODE_FULL every mesh point is its own representative and each matrix is a
+ *   single block, so "blk" is simply the full matrix.
+ *
+ * k mesh: Gamma-centred n x n x n; point m = (m0, m1, m2) has fractional reciprocal
+ * coordinates m / n and linear index (m0 n + m1) n + m2.
+ */
+#ifndef GWSYM_H
+#define GWSYM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gwsym_ctx gwsym_ctx;
+
+typedef enum {
+  GWSYM_OK = 0,
+  GWSYM_EINVAL = -1,     /* bad argument value or NULL pointer */
+  GWSYM_ESHAPE = -2,     /* sizes inconsistent with the context */
+  GWSYM_ENOMEM = -3,     /* host or device allocation failed */
+  GWSYM_EHIP = -4,       /* a HIP runtime call failed */
+  GWSYM_ESINGULAR = -5,  /* a matrix to invert was singular (checked on the host side only) */
+  GWSYM_ENOCONV = -6,    /* an iterative host routine did not converge */
+  GWSYM_ESTATE = -7      /* call made out of order (e.g. before build_symmetry_basis) */
+} gwsym_status;
+
+typedef enum {
+  GWSYM_MODE_FULL = 0,   /* no symmetry: every k point, full matrices */
+  GWSYM_MODE_ROTATE = 1, /* irreducible wedge, full matrices rotated by O^k(alpha) (eq. mat_rot) */
+  GWSYM_MODE_BLOCK = 2   /* irreducible wedge and isotypic blocks (eq. mat_blk, eq. C_blk) */
+} gwsym_mode;
+
+typedef enum {
+  GWSYM_FP64 = 0,        /* contractions in FP64 on MFMA */
+  GWSYM_FP32 = 1         /* contractions with FP32 operands and FP32 MFMA accumulation;
+                            transforms, inverses and mu stay FP64 */
+} gwsym_precision;
+
+typedef struct {
+  double beta;        /* inverse temperature (1/Ha) */
+  int ntau;           /* Chebyshev-Gauss-Lobatto tau points on [0, beta], >= 3 */
+  int nw;             /* Matsubara frequencies stored for n >= 0 (fermionic and bosonic) */
+  double spin;        /* spin factor s multiplying P0 and N_e (2 for closed shells) */
+  int mode;           /* gwsym_mode */
+  int precision;      /* gwsym_precision */
+  int half_tau;       /* 1: inputs are time-reversal symmetric, P0 is evaluated for
+                         tau_j with j < ceil(ntau/2) and mirrored (Alg. 3 tau loop) */
+  int tau_chunk;      /* tau points per contraction launch (0 = library default) */
+} gwsym_params;
+
+typedef struct {
+  double lattice[9];        /* row-major 3x3 whose columns are the primitive vectors a_i */
+  int natom;
+  const double* positions;  /* host, natom x 3 fractional coordinates */
+  int nop;                  /* space-group operations {alpha | v(alpha)} (Sec. 3.1); op 0 = identity */
+  const int* rot;           /* host, nop x 9, integer rotation W on fractional coordinates, row-major */
+  const double* trans;      /* host, nop x 3, fractional translation v(alpha) */
+  int kmesh;                /* n of the Gamma-centred n^3 mesh */
+  int nshell_ao;            /* orbital shells, in basis order; functions m = -l..l per shell */
+  const int* ao_atom;       /* host, atom of each shell */
+  const int* ao_l;          /* host, angular momentum of each shell, 0..4 */
+  int nshell_aux;           /* auxiliary (density-fitting) shells */
+  const int* aux_atom;
+  const int* aux_l;
+} gwsym_crystal;
+
+/* Kinds for gwsym_to_block / gwsym_from_block. */
+typedef enum {
+  GWSYM_KIND_F = 0,       /* orbital matrix, one per k:          full [nk_in][nao][nao]        */
+  GWSYM_KIND_G = 1,       /* orbital matrix per k and tau:       full [nk_in][ntau][nao][nao]  */
+  GWSYM_KIND_P = 2        /* auxiliary matrix per q and tau:     full [nk_in][ntau][naux][naux] */
+} gwsym_kind;
+
+/* Creates a context.  params is copied.  *out receives the new context (host). */
+int gwsym_create(const gwsym_params* params, gwsym_ctx** out);
+
+/* Frees the context, its device tables, the transformed V tensors and every workspace. */
+void gwsym_destroy(gwsym_ctx* ctx);
+
+/* Message describing the last error of ctx (a static string when ctx is NULL). */
+const char* gwsym_last_error(const gwsym_ctx* ctx);
+
+/* Alg. 1 (Sec. 3.2-3.4), on the host: builds the operation tables, the stars and
+ * irreducible representatives of the k mesh (Sec. 4.2), the orbital and auxiliary
+ * representations O^k(alpha) (eq. basis_rot, with the phases exp(-i k~ . v_x^alpha)),
+ * the projective representations D^k and factors lambda^k (eq. projrep, eq. factor),
+ * the Dirac characters of every little co-group (eq. dirac) and, in GWSYM_MODE_BLOCK, the
+ * unitary U^k that block-diagonalises every invariant matrix (eq. mat_blk).  Also builds
+ * the tau grid and the Matsubara transform matrices.  Host only; makes no HIP call.
+ * Fails with GWSYM_EINVAL if an operation does not map the crystal onto itself. */
+int gwsym_build_symmetry_basis(gwsym_ctx* ctx, const gwsym_crystal* crystal);
+
+/* Size in bytes of the table `name` (see gwsym_get). Negative status if unknown. */
+int64_t gwsym_table_size(const gwsym_ctx* ctx, const char* name);
+
+/* Copies the host table `name` into out (host, nbytes >= gwsym_table_size).
+ * Integer tables are int64; real tables double; complex tables interleaved doubles.
+ *   "dims"        int64[8]: nk, nibz, nao, naux, ntau, nw, nop, mode
+ *   "ibz"         int64[nibz]: mesh index of each irreducible representative
+ *   "rep"         int64[nk]: irreducible index i of rep(k)
+ *   "alpha"       int64[nk]: operation alpha_k with alpha_k rep(k) = k
+ *   "kmap"        int64[nop*nk]: index of alpha k
+ *   "ao_blocks"   int64[nibz*(1+nao)]: per i: count, then sizes
+ *   "aux_blocks"  int64[nibz*(1+naux)]
+ *   "g_off","p_off","f_off"  int64[nibz+1]: packed offsets (complex elements)
+ *   "U_ao"        complex[nk][nao][nao]: U^k for every mesh point (columns = block basis)
+ *   "U_aux"       complex[nk][naux][naux]
+ *   "O_ao"        complex[nop][nk][nao][nao]: O^k(alpha) mapping k to alpha k
+ *   "O_aux"       complex[nop][nk][naux][naux]
+ *   "tau"         double[ntau];  "Tf","Tb" complex[nw][ntau];  "Bf","Bb" complex[ntau][nw]
+ *                 (X(tau) = Y + Y^H with Y = B X(i nu); for bosons the n = 0 column
+ *                  carries half weight)
+ */
+int gwsym_get(const gwsym_ctx* ctx, const char* name, void* out, int64_t nbytes);
+
+/* Allocates the device tables and workspaces on the current HIP device and uploads the
+ * symmetry tables.  Must follow gwsym_build_symmetry_basis.  Synchronises `stream`. */
+int gwsym_device_init(gwsym_ctx* ctx, void* stream);
+
+/* Sec. 4.2-4.3 / eq. C_blk: takes V^{k0,k'}(Q) for every representative k0 (in "ibz"
+ * order; every mesh point in GWSYM_MODE_FULL) and every k' (device, complex
+ * [nibz][nk][naux][nao][nao]) and builds the two block-transformed copies the
+ * contractions read: one indexed by (k0, k') for the self-energy and one indexed by
+ * (q0, k) with q0 irreducible, rotated with O^k(alpha) and O_aux^q(alpha), for the
+ * polarization.  The input is only read; it may be freed once `stream` is done. */
+int gwsym_load_V(gwsym_ctx* ctx, const void* V_ibz, void* stream);
+
+/* eq. mat_blk: full matrices at the irreducible points (device, layout by kind with
+ * nk_in = nibz) -> block-packed (device).  Off-block elements are dropped. */
+int gwsym_to_block(gwsym_ctx* ctx, int kind, const void* full, void* blk, void* stream);
+
+/* Inverse of eq. mat_blk followed by eq. mat_rot / eq. prot: block-packed (device) ->
+ * full matrices at every mesh point (device, layout by kind with nk_in = nk). */
+int gwsym_from_block(gwsym_ctx* ctx, int kind, const void* blk, void* full, void* stream);
+
+/* Free Green's function G0^k(tau) = -U diag(exp(-e tau)/(1 + exp(-beta e))) U^H of
+ * F^k - mu = U diag(e) U^H, per block, from F_blk (device).  Writes G_blk (device) and
+ * the free electron count (s/Nk) sum_k sum_i 1/(1 + exp(beta e_i)) to *n_free (device
+ * double; may be NULL). */
+int gwsym_g0(gwsym_ctx* ctx, const void* F_blk, double mu, void* G_blk, double* n_free,
+             void* stream);
+
+/* eq. P0 / Alg. 3: P0_blk (device) from G_blk (device) and the loaded V. */
+int gwsym_polarization(gwsym_ctx* ctx, const void* G_blk, void* P0_blk, void* stream);
+
+/* eq. P02P: tau -> i Omega_n, P = [I - P0]^{-1} P0 per auxiliary block, i Omega_n -> tau.
+ * P0_blk, P_blk device. */
+int gwsym_screened_interaction(gwsym_ctx* ctx, const void* P0_blk, void* P_blk, void* stream);
+
+/* eq. sigma / Alg. 4: Sigma_blk (device) from G_blk, P_blk (device) and the loaded V. */
+int gwsym_self_energy(gwsym_ctx* ctx, const void* G_blk, const void* P_blk, void* Sigma_blk,
+                      void* stream);
+
+/* Chemical potential for a fixed electron count (Sec. 4.1, N_e): bisection over 64
+ * steps on N(mu) = (s/Nk) sum_k Tr[-G^k(beta; mu)], G from eq. dyson with F_blk and
+ * Sigma_blk (device).  Bracket: [lowest, highest] eigenvalue of F -/+ 20 Ha (the
+ * eigenvalues come from the last gwsym_g0 call).  Writes *mu (device double). */
+int gwsym_find_mu(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, double n_target,
+                  double* mu, void* stream);
+
+/* eq. dyson: Sigma(tau) -> Sigma(i w_n), G(i w_n) = [(i w_n + mu) I - F - Sigma(i w_n)]^{-1}
+ * per block, i w_n -> tau.  mu is a device double.  Writes G_blk (device). */
+int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, const double* mu,
+                  void* G_blk, void* stream);
+
+/* Algorithm and executed complex multiply-accumulate counts of the last
+ * polarization / self_energy call, for throughput accounting (host).
+ * out[0] = P0 MACs, out[1] = Sigma MACs (as executed, padding excluded). */
+int gwsym_flop_counts(const gwsym_ctx* ctx, double* out2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWSYM_H */

@@ -1,0 +1,75 @@
+// Work-item structures shared by the kernels (kernels.hip) and their host-side planner
+// (pipeline.hip).  Every offset counts complex elements from the base pointer of the
+// buffer id it names; the launch passes the current base pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace gw {
+
+struct Bases {
+  void* p[NBUF];
+};
+
+struct GemmPlanDev {
+  void* probs = nullptr;
+  void* tiles = nullptr;
+  void* reds = nullptr;
+  int ntiles = 0, nreds = 0, nslots = 0;
+};
+
+// rows [0, nrows) of a row-major slab (right multiply), or the slab width (left multiply)
+struct RowSeg {
+  int inbuf, outbuf, gbuf, blk;  // blk: offset of the block table entry in btab
+  int64_t in_off, out_off, g_off;
+  int nrows, pad_;
+};
+
+struct RowSegList {
+  void* segs = nullptr;
+  int nseg = 0, maxrows = 0;
+};
+
+struct CopySeg {
+  int inbuf, outbuf, n, pad_;
+  int64_t in_off, out_off, len;
+};
+
+enum { INV_P = 0, INV_G = 1, INV_TRACE = 2 };
+
+struct InvItem {
+  int n, xbuf, fbuf, outbuf;
+  int64_t x_off, f_off, out_off;
+  double w;
+};
+
+struct MuItem {
+  int n, pad_;
+  double weight;
+};
+
+struct EigItem {
+  int n, fbuf, gbuf, pad_;
+  int64_t f_off, g_off, g_stride;
+};
+
+void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s);
+void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s);
+void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s);
+void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
+void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
+void launch_inverse(const void* items, int nitems, const Bases& b, int mode, const double* mu, double* trace,
+                    int* status, hipStream_t s);
+void launch_mu_init(const double* eps_range, double* state, double* mu, hipStream_t s);
+void launch_mu_update(const void* items, int nitems, const double* trace, const void* Blast, double scale,
+                      double ntarget, double* state, double* mu, hipStream_t s);
+void launch_jacobi_g0(const void* items, int nitems, const Bases& b, const double* tau, int ntau, double beta,
+                      double mu, double* occ, double* erange, hipStream_t s);
+void launch_g0_reduce(const double* occ, const double* w, const double* erange, int nitems, double scale,
+                      double* nfree, double* eps, hipStream_t s);
+
+}  // namespace gw

@@ -1,0 +1,645 @@
+// HIP kernels of libgwsym for gfx950 (MI355X).
+//
+//  k_brgemm       grouped batch-reduce complex GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64):
+//                 every contraction stage, transform and basis change is a list of
+//                 problems C_b = alpha sum_t opA(A_{b,t}) opB(B_{b,t}) + beta C_b with uneven
+//                 sizes, run as one launch over a precomputed tile list.
+//  k_reduce       ordered sum of split-K partial tiles (deterministic, no atomics).
+//  k_rowblock_*   multiply many rows (columns) by a small block-diagonal matrix: the
+//                 G-sandwich stages of P0 and Sigma, which have K = block size.
+//  k_inverse      batched Gauss-Jordan inverses for the two Dyson equations.
+//  k_jacobi_g0    batched Hermitian Jacobi eigen-decomposition and the free G0(tau).
+//  k_herm, k_copy packed-block helpers; k_mu_* the chemical-potential bisection.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernel_api.hpp"
+
+namespace gw {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// ----------------------------------------------------------------------------
+// grouped batch-reduce complex GEMM, 32 x 32 output tile per workgroup of four waves;
+// each wave owns a 16 x 16 quarter and issues four FP64 MFMAs per complex K-step of 4.
+
+constexpr int TM = 32, TN = 32, BK = 32;
+
+__device__ __forceinline__ double2 load_op(const double2* __restrict__ p, int op, int64_t r, int64_t c,
+                                           int64_t ld) {
+  // element (r, c) of op(X): N -> X[r][c], T -> X[c][r], C -> conj X[r][c], H -> conj X[c][r]
+  const double2 v = (op & 1) ? p[c * ld + r] : p[r * ld + c];
+  return (op & 2) ? cconj(v) : v;
+}
+
+__global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ probs,
+                                                const GemmTile* __restrict__ tiles, Bases bases,
+                                                double2* __restrict__ partials) {
+  __shared__ double As_re[BK][TM + 1], As_im[BK][TM + 1];
+  __shared__ double Bs_re[BK][TN + 1], Bs_im[BK][TN + 1];
+  const GemmTile tl = tiles[blockIdx.x];
+  const GemmProblem P = probs[tl.prob];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = tl.tm * TM;
+  const double2* Ab = reinterpret_cast<const double2*>(bases.p[P.abuf]) + P.aoff + int64_t(tl.batch) * P.sAb;
+  const double2* Bb = reinterpret_cast<const double2*>(bases.p[P.bbuf]) + P.boff + int64_t(tl.batch) * P.sBb;
+  const bool a_kfast = (P.opA & 1) == 0;  // N, C: k is the contiguous index of A
+  const bool b_nfast = (P.opB & 1) == 0;  // N, C: n is the contiguous index of B
+  for (int tn = tl.tn; tn < tl.tn + tl.ntn; ++tn) {
+    const int n0 = tn * TN;
+    d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    for (int t = tl.t0; t < tl.t1; ++t) {
+      const double2* A = Ab + int64_t(t) * P.sAt;
+      const double2* B = Bb + int64_t(t) * P.sBt;
+      for (int k0 = 0; k0 < P.K; k0 += BK) {
+        const int kv = min(BK, P.K - k0);
+        for (int idx = tid; idx < TM * BK; idx += 256) {
+          int mm, kk;
+          if (a_kfast) { mm = idx / BK; kk = idx % BK; }
+          else { kk = idx / TM; mm = idx % TM; }
+          const int m = m0 + mm, k = k0 + kk;
+          double2 v = make_double2(0.0, 0.0);
+          if (m < P.M && kk < kv) v = load_op(A, P.opA, m, k, P.lda);
+          As_re[kk][mm] = v.x;
+          As_im[kk][mm] = v.y;
+        }
+        for (int idx = tid; idx < TN * BK; idx += 256) {
+          int nn, kk;
+          if (b_nfast) { kk = idx / TN; nn = idx % TN; }
+          else { nn = idx / BK; kk = idx % BK; }
+          const int n = n0 + nn, k = k0 + kk;
+          double2 v = make_double2(0.0, 0.0);
+          if (n < P.N && kk < kv) v = load_op(B, P.opB, k, n, P.ldb);
+          Bs_re[kk][nn] = v.x;
+          Bs_im[kk][nn] = v.y;
+        }
+        __syncthreads();
+        const int r = wm * 16 + (lane & 15), cix = wn * 16 + (lane & 15), kq = lane >> 4;
+        for (int kk = 0; kk < kv; kk += 4) {
+          const double are = As_re[kk + kq][r], aim = As_im[kk + kq][r];
+          const double bre = Bs_re[kk + kq][cix], bim = Bs_im[kk + kq][cix];
+          cre = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bre, cre, 0, 0, 0);
+          cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim, bim, cre, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bim, cim, 0, 0, 0);
+          cim = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bre, cim, 0, 0, 0);
+        }
+        __syncthreads();
+      }
+    }
+    // D layout of the 16x16 MFMA: lane holds rows 4*(lane/16)+j, column lane%16
+    const int col = wn * 16 + (lane & 15);
+    if (tl.slot >= 0) {
+      double2* out = partials + int64_t(tl.slot) * TM * TN;
+      for (int j = 0; j < 4; ++j) {
+        const int row = wm * 16 + 4 * (lane >> 4) + j;
+        out[row * TN + col] = make_double2(cre[j], cim[j]);
+      }
+      continue;
+    }
+    double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]) + P.coff + int64_t(tl.batch) * P.sCb;
+    const double2 al = make_double2(P.alpha_re, P.alpha_im);
+    for (int j = 0; j < 4; ++j) {
+      const int row = m0 + wm * 16 + 4 * (lane >> 4) + j, cc = n0 + col;
+      if (row < P.M && cc < P.N) {
+        double2 v = cmul(al, make_double2(cre[j], cim[j]));
+        if (P.beta) v = cadd(v, C[int64_t(row) * P.ldc + cc]);
+        C[int64_t(row) * P.ldc + cc] = v;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ probs,
+                                                const GemmReduce* __restrict__ reds, Bases bases,
+                                                const double2* __restrict__ partials) {
+  const GemmReduce rd = reds[blockIdx.x];
+  const GemmProblem P = probs[rd.prob];
+  double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]) + P.coff + int64_t(rd.batch) * P.sCb;
+  const double2 al = make_double2(P.alpha_re, P.alpha_im);
+  for (int e = threadIdx.x; e < TM * TN; e += 256) {
+    const int row = rd.tm * TM + e / TN, cc = rd.tn * TN + e % TN;
+    if (row >= P.M || cc >= P.N) continue;
+    double2 s = make_double2(0.0, 0.0);
+    for (int q = 0; q < rd.nslot; ++q) s = cadd(s, partials[int64_t(rd.slot0 + q) * TM * TN + e]);
+    double2 v = cmul(al, s);
+    if (P.beta) v = cadd(v, C[int64_t(row) * P.ldc + cc]);
+    C[int64_t(row) * P.ldc + cc] = v;
+  }
+}
+
+void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s) {
+  if (p.ntiles > 0)
+    hipLaunchKernelGGL(k_brgemm, dim3(p.ntiles), dim3(256), 0, s, (const GemmProblem*)p.probs,
+                       (const GemmTile*)p.tiles, b, (double2*)partials);
+  if (p.nreds > 0)
+    hipLaunchKernelGGL(k_reduce, dim3(p.nreds), dim3(256), 0, s, (const GemmProblem*)p.probs,
+                       (const GemmReduce*)p.reds, b, (const double2*)partials);
+}
+
+// ----------------------------------------------------------------------------
+// Block-diagonal row / column multiplies.
+//
+// Right: out[row][:] = in[row][:] * blockdiag(G) for the rows of one segment; G is a packed
+// set of blocks (sizes from the block table `bt`, entry bt_off[blk_id]).
+// Left:  out[:][col] = blockdiag(G)^H * in[:][col] (columns of a row-major nb x ncols slab).
+
+constexpr int RB_ROWS = 64;
+
+__global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict__ segs, Bases bases,
+                                                        const int* __restrict__ btab, int ncol) {
+  extern __shared__ double2 lds[];
+  const RowSeg sg = segs[blockIdx.y];
+  const int r0 = blockIdx.x * RB_ROWS;
+  if (r0 >= sg.nrows) return;
+  const int nrows = min(RB_ROWS, sg.nrows - r0);
+  const double2* in = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off + int64_t(r0) * ncol;
+  double2* out = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off + int64_t(r0) * ncol;
+  const double2* G = reinterpret_cast<const double2*>(bases.p[sg.gbuf]) + sg.g_off;
+  const int* bt = btab + sg.blk;  // bt[0] = count, then (off, size, poff) per block
+  double2* tile = lds;            // nrows x ncol
+  int* colblk = reinterpret_cast<int*>(lds + RB_ROWS * ncol);  // per column: block index
+  for (int e = threadIdx.x; e < nrows * ncol; e += 256) tile[e] = in[e];
+  const int nb = bt[0];
+  for (int c = threadIdx.x; c < ncol; c += 256)
+    for (int b = 0; b < nb; ++b)
+      if (c >= bt[1 + 3 * b] && c < bt[1 + 3 * b] + bt[2 + 3 * b]) colblk[c] = b;
+  __syncthreads();
+  for (int e = threadIdx.x; e < nrows * ncol; e += 256) {
+    const int row = e / ncol, c = e % ncol;
+    const int b = colblk[c];
+    const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
+    const int cc = c - off;
+    double2 s = make_double2(0.0, 0.0);
+    for (int k = 0; k < sz; ++k) s = cadd(s, cmul(tile[row * ncol + off + k], G[po + k * sz + cc]));
+    out[e] = s;
+  }
+}
+
+constexpr int CB_COLS = 64;
+
+__global__ __launch_bounds__(256) void k_rowblock_left(const RowSeg* __restrict__ segs, Bases bases,
+                                                       const int* __restrict__ btab, int nb_rows) {
+  extern __shared__ double2 lds[];
+  const RowSeg sg = segs[blockIdx.y];
+  const int c0 = blockIdx.x * CB_COLS;
+  const int ncols = sg.nrows;  // for left segments nrows holds the slab width
+  if (c0 >= ncols) return;
+  const int nc = min(CB_COLS, ncols - c0);
+  const double2* in = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
+  double2* out = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
+  const double2* G = reinterpret_cast<const double2*>(bases.p[sg.gbuf]) + sg.g_off;
+  const int* bt = btab + sg.blk;
+  double2* tile = lds;  // nb_rows x CB_COLS
+  for (int e = threadIdx.x; e < nb_rows * CB_COLS; e += 256) {
+    const int r = e / CB_COLS, c = e % CB_COLS;
+    tile[e] = c < nc ? in[int64_t(r) * ncols + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int nblk = bt[0];
+  for (int e = threadIdx.x; e < nb_rows * CB_COLS; e += 256) {
+    const int rp = e / CB_COLS, c = e % CB_COLS;
+    if (c >= nc) continue;
+    int b = 0;
+    while (b + 1 < nblk && rp >= bt[1 + 3 * (b + 1)]) ++b;
+    const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
+    const int rr = rp - off;
+    double2 s = make_double2(0.0, 0.0);
+    // (G^H)[rr][k] = conj(G[k][rr])
+    for (int k = 0; k < sz; ++k) s = cadd(s, cmul(cconj(G[po + k * sz + rr]), tile[(off + k) * CB_COLS + c]));
+    out[int64_t(rp) * ncols + c] = s;
+  }
+}
+
+void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s) {
+  if (l.nseg == 0) return;
+  const size_t lds = size_t(RB_ROWS) * ncol * sizeof(double2) + ncol * sizeof(int) + 16;
+  hipLaunchKernelGGL(k_rowblock_right, dim3((l.maxrows + RB_ROWS - 1) / RB_ROWS, l.nseg), dim3(256), lds, s,
+                     (const RowSeg*)l.segs, b, btab, ncol);
+}
+
+void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s) {
+  if (l.nseg == 0) return;
+  const size_t lds = size_t(nb_rows) * CB_COLS * sizeof(double2);
+  hipLaunchKernelGGL(k_rowblock_left, dim3((l.maxrows + CB_COLS - 1) / CB_COLS, l.nseg), dim3(256), lds, s,
+                     (const RowSeg*)l.segs, b, btab, nb_rows);
+}
+
+// ----------------------------------------------------------------------------
+// Packed-block helpers.
+
+// out[blk] = Y[blk] + Y[blk]^H for every segment (one n x n block each).
+__global__ __launch_bounds__(256) void k_herm(const CopySeg* __restrict__ segs, Bases bases) {
+  const CopySeg sg = segs[blockIdx.x];
+  const double2* Y = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off;
+  double2* X = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off;
+  const int n = sg.n;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int a = e / n, b = e % n;
+    X[e] = cadd(Y[a * n + b], cconj(Y[b * n + a]));
+  }
+}
+
+// plain copies of contiguous runs (tau mirror of P0)
+__global__ __launch_bounds__(256) void k_copy(const CopySeg* __restrict__ segs, Bases bases) {
+  const CopySeg sg = segs[blockIdx.x];
+  const double2* a = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off;
+  double2* o = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off;
+  for (int64_t e = threadIdx.x; e < sg.len; e += 256) o[e] = a[e];
+}
+
+void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s) {
+  if (nseg) hipLaunchKernelGGL(k_herm, dim3(nseg), dim3(256), 0, s, (const CopySeg*)segs, b);
+}
+void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s) {
+  if (nseg) hipLaunchKernelGGL(k_copy, dim3(nseg), dim3(256), 0, s, (const CopySeg*)segs, b);
+}
+
+// ----------------------------------------------------------------------------
+// Batched Gauss-Jordan inverse with partial pivoting, one workgroup per matrix.
+//   mode INV_P:     A = I - X,                 out = A^{-1} - I    (eq. P02P)
+//   mode INV_G:     A = (i w + mu) I - F - X,  out = A^{-1}        (eq. dyson)
+//   mode INV_TRACE: as INV_G, writes Tr A^{-1} to trace[item] only
+// Matrices with n <= INV_LDS_N are factorised in LDS, larger ones in place in `out`.
+
+constexpr int INV_LDS_N = 48;
+
+__device__ void gauss_jordan(double2* A, int n, int* piv, double2* fcol, double* red, int* redi, int* sing) {
+  const int tid = threadIdx.x;
+  for (int c = 0; c < n; ++c) {
+    // pivot search over rows c..n-1
+    double best = -1.0;
+    int bi = c;
+    for (int r = c + tid; r < n; r += 256) {
+      const double2 v = A[r * n + c];
+      const double m = fabs(v.x) + fabs(v.y);
+      if (m > best) { best = m; bi = r; }
+    }
+    red[tid] = best;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) {
+        const double o = red[tid + w];
+        const int oi = redi[tid + w];
+        if (o > red[tid] || (o == red[tid] && oi < redi[tid])) { red[tid] = o; redi[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int p = redi[0];
+    if (red[0] <= 0.0 && tid == 0) *sing = 1;
+    if (tid == 0) piv[c] = p;
+    if (p != c)
+      for (int j = tid; j < n; j += 256) {
+        const double2 t = A[c * n + j];
+        A[c * n + j] = A[p * n + j];
+        A[p * n + j] = t;
+      }
+    __syncthreads();
+    const double2 d = cdiv(make_double2(1.0, 0.0), A[c * n + c]);
+    __syncthreads();
+    for (int j = tid; j < n; j += 256) A[c * n + j] = (j == c) ? d : cmul(A[c * n + j], d);
+    for (int r = tid; r < n; r += 256) fcol[r] = A[r * n + c];
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+      const int r = e / n, j = e % n;
+      if (r == c) continue;
+      const double2 f = fcol[r];
+      if (j == c) A[e] = cmul(make_double2(-f.x, -f.y), d);
+      else A[e] = csub(A[e], cmul(f, A[c * n + j]));
+    }
+    __syncthreads();
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    const int p = piv[c];
+    if (p != c)
+      for (int r = tid; r < n; r += 256) {
+        const double2 t = A[r * n + c];
+        A[r * n + c] = A[r * n + p];
+        A[r * n + p] = t;
+      }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_inverse(const InvItem* __restrict__ items, Bases bases, int mode,
+                                                 const double* __restrict__ mu, double* __restrict__ trace,
+                                                 int* __restrict__ status) {
+  __shared__ double2 Alds[INV_LDS_N * INV_LDS_N];
+  __shared__ double2 fcol[512];
+  __shared__ int piv[512];
+  __shared__ double red[256];
+  __shared__ int redi[256];
+  __shared__ int sing;
+  const InvItem it = items[blockIdx.x];
+  const int n = it.n, tid = threadIdx.x;
+  if (tid == 0) sing = 0;
+  const double2* X = reinterpret_cast<const double2*>(bases.p[it.xbuf]) + it.x_off;
+  const double2* F = it.f_off >= 0 ? reinterpret_cast<const double2*>(bases.p[it.fbuf]) + it.f_off : nullptr;
+  double2* out = reinterpret_cast<double2*>(bases.p[it.outbuf]) + it.out_off;
+  double2* A = (n <= INV_LDS_N) ? Alds : out;
+  const double shift = (mode == INV_P) ? 0.0 : *mu;
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e / n, j = e % n;
+    const double2 x = X[e];
+    double2 a;
+    if (mode == INV_P) {
+      a = make_double2(-x.x, -x.y);
+      if (r == j) a.x += 1.0;
+    } else {
+      const double2 f = F[e];
+      a = make_double2(-f.x - x.x, -f.y - x.y);
+      if (r == j) { a.x += shift; a.y += it.w; }
+    }
+    A[e] = a;
+  }
+  __syncthreads();
+  gauss_jordan(A, n, piv, fcol, red, redi, &sing);
+  __syncthreads();
+  if (sing && tid == 0) atomicOr(status, 1);
+  if (mode == INV_TRACE) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int r = tid; r < n; r += 256) s = cadd(s, A[r * n + r]);
+    red[tid] = s.x;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    double re = red[0];
+    __syncthreads();
+    red[tid] = s.y;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      trace[2 * blockIdx.x] = re;
+      trace[2 * blockIdx.x + 1] = red[0];
+    }
+    return;
+  }
+  for (int e = tid; e < n * n; e += 256) {
+    double2 v = A[e];
+    if (mode == INV_P && (e / n) == (e % n)) v.x -= 1.0;
+    out[e] = v;
+  }
+}
+
+void launch_inverse(const void* items, int nitems, const Bases& b, int mode, const double* mu, double* trace,
+                    int* status, hipStream_t s) {
+  if (nitems)
+    hipLaunchKernelGGL(k_inverse, dim3(nitems), dim3(256), 0, s, (const InvItem*)items, b, mode, mu, trace, status);
+}
+
+// ----------------------------------------------------------------------------
+// Chemical potential bisection (one workgroup): N(mu) from the traces of G(i w_n) at the
+// current mu, then the bracket update.  state = [lo, hi, mu].
+
+__global__ __launch_bounds__(256) void k_mu_update(const MuItem* __restrict__ items, int nitems,
+                                                   const double2* __restrict__ trace, const double2* __restrict__ Blast,
+                                                   double scale, double ntarget, double* __restrict__ state,
+                                                   double* __restrict__ mu_out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < nitems; e += 256) {
+    const MuItem it = items[e];
+    // Tr G(beta) = 2 Re sum_n B[ntau-1][n] Tr G(i w_n)
+    const double2 v = cmul(Blast[it.n], trace[e]);
+    s += 2.0 * v.x * it.weight;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double N = -scale * red[0];
+    double lo = state[0], hi = state[1];
+    const double mid = state[2];
+    if (N < ntarget) lo = mid; else hi = mid;
+    state[0] = lo;
+    state[1] = hi;
+    state[2] = 0.5 * (lo + hi);
+    *mu_out = state[2];
+  }
+}
+
+// state = [eps_min - 20, eps_max + 20, midpoint]
+__global__ void k_mu_init(const double* __restrict__ eps_range, double* __restrict__ state, double* __restrict__ mu) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    state[0] = eps_range[0] - 20.0;
+    state[1] = eps_range[1] + 20.0;
+    state[2] = 0.5 * (state[0] + state[1]);
+    *mu = state[2];
+  }
+}
+
+void launch_mu_init(const double* eps_range, double* state, double* mu, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(64), 0, s, eps_range, state, mu);
+}
+void launch_mu_update(const void* items, int nitems, const double* trace, const void* Blast, double scale,
+                      double ntarget, double* state, double* mu, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(256), 0, s, (const MuItem*)items, nitems, (const double2*)trace,
+                     (const double2*)Blast, scale, ntarget, state, mu);
+}
+
+// ----------------------------------------------------------------------------
+// Free G0 per block: Jacobi eigen-decomposition of F_r - mu I (parallel cyclic ordering),
+// then G0(tau_j) = -V diag(g(e, tau_j)) V^H with g = exp(-e tau)/(1 + exp(-beta e)) in a
+// form that never overflows.  Also writes per-block occupations and eigenvalue range.
+
+constexpr int JAC_N = 64;
+
+__global__ __launch_bounds__(256) void k_jacobi_g0(const EigItem* __restrict__ items, Bases bases,
+                                                   const double* __restrict__ tau, int ntau, double beta, double mu,
+                                                   double* __restrict__ occ, double* __restrict__ erange) {
+  __shared__ double2 A[JAC_N * JAC_N];
+  __shared__ double2 V[JAC_N * JAC_N];
+  __shared__ double cs[JAC_N / 2], sn[JAC_N / 2];
+  __shared__ double2 ph[JAC_N / 2];
+  __shared__ int pp[JAC_N / 2], qq[JAC_N / 2];
+  __shared__ double red[256];
+  __shared__ double ev[JAC_N];
+  const EigItem it = items[blockIdx.x];
+  const int n = it.n, tid = threadIdx.x;
+  const int m = (n + 1) & ~1;  // even size for the round-robin pairing (index n is a dummy)
+  const double2* F = reinterpret_cast<const double2*>(bases.p[it.fbuf]) + it.f_off;
+  for (int e = tid; e < m * m; e += 256) {
+    const int r = e / m, c = e % m;
+    double2 v = make_double2(0.0, 0.0);
+    if (r < n && c < n) {
+      v = F[r * n + c];
+      if (r == c) v.x -= mu;
+    }
+    A[e] = v;
+    V[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // convergence test on the off-diagonal norm
+    double s = 0.0, d = 0.0;
+    for (int e = tid; e < m * m; e += 256) {
+      const double2 v = A[e];
+      if (e / m != e % m) s += v.x * v.x + v.y * v.y;
+      else d += v.x * v.x;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double off = red[0];
+    __syncthreads();
+    red[tid] = d;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double tot = red[0] + off;
+    __syncthreads();
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int round = 0; round < m - 1; ++round) {
+      // round-robin pairs: position 0 fixed, the others rotate
+      if (tid < m / 2) {
+        const int i = tid;
+        auto pos = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + round) % (m - 1)); };
+        int p = pos(i), q = pos(m - 1 - i);
+        if (p > q) { const int t = p; p = q; q = t; }
+        pp[i] = p;
+        qq[i] = q;
+        const double2 b = A[p * m + q];
+        const double ab = sqrt(b.x * b.x + b.y * b.y);
+        if (ab < 1e-300) {
+          cs[i] = 1.0; sn[i] = 0.0; ph[i] = make_double2(1.0, 0.0);
+        } else {
+          const double a = A[p * m + p].x, dd = A[q * m + q].x;
+          const double th = (dd - a) / (2.0 * ab);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          cs[i] = c; sn[i] = t * c; ph[i] = make_double2(b.x / ab, b.y / ab);
+        }
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+      for (int e = tid; e < (m / 2) * m; e += 256) {
+        const int i = e / m, k = e % m;
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], s = sn[i];
+        const double2 em = cconj(ph[i]);
+        const double2 akp = A[k * m + p], akq = A[k * m + q];
+        const double2 t1 = cmul(em, akq);
+        A[k * m + p] = make_double2(c * akp.x - s * t1.x, c * akp.y - s * t1.y);
+        A[k * m + q] = make_double2(s * akp.x + c * t1.x, s * akp.y + c * t1.y);
+        const double2 vkp = V[k * m + p], vkq = V[k * m + q];
+        const double2 t2 = cmul(em, vkq);
+        V[k * m + p] = make_double2(c * vkp.x - s * t2.x, c * vkp.y - s * t2.y);
+        V[k * m + q] = make_double2(s * vkp.x + c * t2.x, s * vkp.y + c * t2.y);
+      }
+      __syncthreads();
+      // rows: A <- J^H A
+      for (int e = tid; e < (m / 2) * m; e += 256) {
+        const int i = e / m, k = e % m;
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], s = sn[i];
+        const double2 ep = ph[i];
+        const double2 apk = A[p * m + k], aqk = A[q * m + k];
+        const double2 t1 = cmul(ep, aqk);
+        A[p * m + k] = make_double2(c * apk.x - s * t1.x, c * apk.y - s * t1.y);
+        A[q * m + k] = make_double2(s * apk.x + c * t1.x, s * apk.y + c * t1.y);
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < n) ev[tid] = A[tid * m + tid].x;
+  __syncthreads();
+  // occupations f(e) = 1/(1 + exp(beta e)) and eigenvalue range (of F, i.e. e + mu)
+  if (tid == 0) {
+    double o = 0.0, lo = 1e300, hi = -1e300;
+    for (int l = 0; l < n; ++l) {
+      const double e = ev[l];
+      o += e >= 0 ? exp(-beta * e) / (1.0 + exp(-beta * e)) : 1.0 / (1.0 + exp(beta * e));
+      lo = fmin(lo, e + mu);
+      hi = fmax(hi, e + mu);
+    }
+    occ[blockIdx.x] = o;
+    erange[2 * blockIdx.x] = lo;
+    erange[2 * blockIdx.x + 1] = hi;
+  }
+  double2* G = reinterpret_cast<double2*>(bases.p[it.gbuf]) + it.g_off;
+  for (int j = 0; j < ntau; ++j) {
+    const double t = tau[j];
+    for (int e = tid; e < n * n; e += 256) {
+      const int a = e / n, b = e % n;
+      double2 s = make_double2(0.0, 0.0);
+      for (int l = 0; l < n; ++l) {
+        const double el = ev[l];
+        const double g = el >= 0 ? exp(-el * t) / (1.0 + exp(-beta * el)) : exp(el * (beta - t)) / (1.0 + exp(beta * el));
+        const double2 va = V[a * m + l], vb = V[b * m + l];
+        const double2 pr = cmul(va, cconj(vb));
+        s.x -= g * pr.x;
+        s.y -= g * pr.y;
+      }
+      G[int64_t(j) * it.g_stride + e] = s;
+    }
+  }
+}
+
+void launch_jacobi_g0(const void* items, int nitems, const Bases& b, const double* tau, int ntau, double beta,
+                      double mu, double* occ, double* erange, hipStream_t s) {
+  if (nitems)
+    hipLaunchKernelGGL(k_jacobi_g0, dim3(nitems), dim3(256), 0, s, (const EigItem*)items, b, tau, ntau, beta, mu, occ,
+                       erange);
+}
+
+// sum of per-block occupations with star weights, and the global eigenvalue range
+__global__ __launch_bounds__(256) void k_g0_reduce(const double* __restrict__ occ, const double* __restrict__ w,
+                                                   const double* __restrict__ erange, int nitems, double scale,
+                                                   double* __restrict__ nfree, double* __restrict__ eps) {
+  __shared__ double s1[256], s2[256], s3[256];
+  double a = 0.0, lo = 1e300, hi = -1e300;
+  for (int e = threadIdx.x; e < nitems; e += 256) {
+    a += w[e] * occ[e];
+    lo = fmin(lo, erange[2 * e]);
+    hi = fmax(hi, erange[2 * e + 1]);
+  }
+  s1[threadIdx.x] = a; s2[threadIdx.x] = lo; s3[threadIdx.x] = hi;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) {
+      s1[threadIdx.x] += s1[threadIdx.x + k];
+      s2[threadIdx.x] = fmin(s2[threadIdx.x], s2[threadIdx.x + k]);
+      s3[threadIdx.x] = fmax(s3[threadIdx.x], s3[threadIdx.x + k]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (nfree) *nfree = scale * s1[0];
+    eps[0] = s2[0];
+    eps[1] = s3[0];
+  }
+}
+
+void launch_g0_reduce(const double* occ, const double* w, const double* erange, int nitems, double scale,
+                      double* nfree, double* eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_g0_reduce, dim3(1), dim3(256), 0, s, occ, w, erange, nitems, scale, nfree, eps);
+}
+
+}  // namespace gw

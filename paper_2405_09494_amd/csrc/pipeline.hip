@@ -1,0 +1,844 @@
+// Device-side orchestration of libgwsym: memory, the precomputed work lists of every stage
+// and the order of launches.  All work lists are built once (device_init / load_V) with
+// buffer ids and element offsets; each call only passes the current base pointers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "kernel_api.hpp"
+
+namespace gw {
+
+namespace {
+
+struct Range {
+  int t0 = 0, nt = 0, r0 = 0, nr = 0;
+};
+
+struct GemmStage {
+  std::vector<GemmProblem> probs;
+  std::vector<GemmTile> tiles;
+  std::vector<GemmReduce> reds;
+  std::vector<Range> launches;
+  std::vector<int> pending;   // problems of the launch being built
+  void* d_probs = nullptr;
+  void* d_tiles = nullptr;
+  void* d_reds = nullptr;
+  int max_slots = 0;
+  double macs = 0;
+
+  void add(const GemmProblem& p) {
+    pending.push_back(int(probs.size()));
+    probs.push_back(p);
+    macs += double(p.M) * p.N * p.K * double(p.T) * p.batch;
+  }
+  // Closes a launch: turns its problems into tiles; problems with a long outer loop are
+  // split so that the launch has about `target` workgroups.
+  void close(int target = 2048) {
+    Range r;
+    r.t0 = int(tiles.size());
+    r.r0 = int(reds.size());
+    long base = 0;
+    for (int id : pending) {
+      const GemmProblem& p = probs[id];
+      base += long(p.batch) * ((p.M + 31) / 32) * ((p.N + 31) / 32);
+    }
+    int slots = 0;
+    for (int id : pending) {
+      const GemmProblem& p = probs[id];
+      const int tm = (p.M + 31) / 32, tn = (p.N + 31) / 32;
+      int split = 1;
+      if (base < target && p.T >= 8) split = int(std::min<long>(p.T / 4, (target + base - 1) / std::max(1L, base)));
+      split = std::max(1, split);
+      for (int b = 0; b < p.batch; ++b)
+        for (int i = 0; i < tm; ++i) {
+          if (split == 1) {
+            const int group = 8;
+            for (int j = 0; j < tn; j += group)
+              tiles.push_back({id, b, i, j, 0, p.T, -1, std::min(group, tn - j)});
+            continue;
+          }
+          for (int j = 0; j < tn; ++j) {
+            const int s0 = slots;
+            for (int s = 0; s < split; ++s) {
+              const int t0 = int(long(s) * p.T / split), t1 = int(long(s + 1) * p.T / split);
+              tiles.push_back({id, b, i, j, t0, t1, s0 + s, 1});
+            }
+            reds.push_back({id, b, i, j, s0, split, 0, 0});
+            slots += split;
+          }
+        }
+    }
+    r.nt = int(tiles.size()) - r.t0;
+    r.nr = int(reds.size()) - r.r0;
+    max_slots = std::max(max_slots, slots);
+    launches.push_back(r);
+    pending.clear();
+  }
+};
+
+struct RowStage {
+  std::vector<RowSeg> segs;
+  std::vector<Range> launches;  // t0 = first segment, nt = count, r0 = max rows
+  void* d = nullptr;
+  int start = 0, maxr = 0;
+  void add(const RowSeg& s) {
+    segs.push_back(s);
+    maxr = std::max(maxr, s.nrows);
+  }
+  void close() {
+    Range r;
+    r.t0 = start;
+    r.nt = int(segs.size()) - start;
+    r.r0 = maxr;
+    launches.push_back(r);
+    start = int(segs.size());
+    maxr = 0;
+  }
+};
+
+template <class T>
+struct ListStage {
+  std::vector<T> items;
+  std::vector<Range> launches;
+  void* d = nullptr;
+  int start = 0;
+  void close() {
+    Range r;
+    r.t0 = start;
+    r.nt = int(items.size()) - start;
+    launches.push_back(r);
+    start = int(items.size());
+  }
+};
+
+}  // namespace
+
+struct DevState {
+  // tables
+  void* U = nullptr;        // U_ao [nk][nao][nao] then U_aux [nk][naux][naux]
+  void* TR = nullptr;       // Tf, Tb [nw][ntau]; Bf, Bb [ntau][nw]
+  double* tau = nullptr;
+  int* btab = nullptr;
+  std::vector<int> bt_ao, bt_aux;   // offsets into btab per irreducible point
+  double* wts = nullptr;            // star weight per g0 item
+  // V
+  void* VP = nullptr;
+  void* VS = nullptr;
+  void* WT = nullptr;       // per-pair rotation matrices for the polarization copy of V
+  // workspaces
+  void* W1 = nullptr;
+  void* W2 = nullptr;
+  size_t ws_elems = 0;
+  void* partials = nullptr;
+  size_t nslots = 0, partial_cap = 0;
+  double* scratch = nullptr;  // mu state (3), eps range (2), internal n_free (1)
+  double* trace = nullptr;
+  double* occ = nullptr;
+  double* erange = nullptr;
+  int* status = nullptr;
+  int tau_chunk = 1;
+  // stages
+  GemmStage p0_gemm, s_gemmA, s_gemmC, scr_fwd, scr_bwd, dys_fwd, dys_bwd, tb_1[3], tb_2[3], fb_1[3], fb_2[3];
+  GemmStage lv1, lv2, lv3;
+  RowStage p0_right, p0_left, s_right;
+  ListStage<CopySeg> p0_mirror, scr_herm, dys_herm;
+  ListStage<InvItem> scr_inv, dys_inv, mu_inv;
+  ListStage<MuItem> mu_items;
+  ListStage<EigItem> g0_items;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+#define HIPCHECK(x)                                              \
+  do {                                                           \
+    hipError_t e_ = (x);                                         \
+    if (e_ != hipSuccess) {                                      \
+      c.err = std::string(#x " failed: ") + hipGetErrorString(e_); \
+      return GWSYM_EHIP;                                         \
+    }                                                            \
+  } while (0)
+
+int dalloc(Ctx& c, DevState& d, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    c.err = "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+    *p = nullptr;
+    return GWSYM_ENOMEM;
+  }
+  d.allocs.push_back(*p);
+  return GWSYM_OK;
+}
+
+template <class T>
+int upload(Ctx& c, DevState& d, const std::vector<T>& v, void** p, hipStream_t s) {
+  int st = dalloc(c, d, p, v.size() * sizeof(T));
+  if (st) return st;
+  if (!v.empty()) HIPCHECK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return GWSYM_OK;
+}
+
+int upload_stage(Ctx& c, DevState& d, GemmStage& g, hipStream_t s) {
+  int st;
+  if ((st = upload(c, d, g.probs, &g.d_probs, s))) return st;
+  if ((st = upload(c, d, g.tiles, &g.d_tiles, s))) return st;
+  if ((st = upload(c, d, g.reds, &g.d_reds, s))) return st;
+  d.nslots = std::max(d.nslots, size_t(g.max_slots));
+  return GWSYM_OK;
+}
+
+GemmPlanDev plan_of(const GemmStage& g, const Range& r) {
+  GemmPlanDev p;
+  p.probs = g.d_probs;
+  p.tiles = static_cast<GemmTile*>(g.d_tiles) + r.t0;
+  p.reds = static_cast<GemmReduce*>(g.d_reds) + r.r0;
+  p.ntiles = r.nt;
+  p.nreds = r.nr;
+  return p;
+}
+
+GemmProblem gp(int M, int N, int K, int T, int batch, int abuf, i64 aoff, i64 lda, i64 sAt, i64 sAb, int opA, int bbuf,
+               i64 boff, i64 ldb, i64 sBt, i64 sBb, int opB, int cbuf, i64 coff, i64 ldc, i64 sCb, double are = 1.0,
+               double aim = 0.0, int beta = 0) {
+  GemmProblem p{};
+  p.M = M; p.N = N; p.K = K; p.T = T; p.batch = batch;
+  p.abuf = abuf; p.aoff = aoff; p.lda = lda; p.sAt = sAt; p.sAb = sAb; p.opA = opA;
+  p.bbuf = bbuf; p.boff = boff; p.ldb = ldb; p.sBt = sBt; p.sBb = sBb; p.opB = opB;
+  p.cbuf = cbuf; p.coff = coff; p.ldc = ldc; p.sCb = sCb;
+  p.alpha_re = are; p.alpha_im = aim; p.beta = beta;
+  return p;
+}
+
+// mesh arithmetic
+struct Mesh {
+  int n;
+  int idx(int a, int b, int c) const { return ((((a % n) + n) % n) * n + (((b % n) + n) % n)) * n + (((c % n) + n) % n); }
+  void pt(int k, int m[3]) const { m[0] = k / (n * n); m[1] = (k / n) % n; m[2] = k % n; }
+  int add(int k1, int k2) const { int a[3], b[3]; pt(k1, a); pt(k2, b); return idx(a[0] + b[0], a[1] + b[1], a[2] + b[2]); }
+  int sub(int k1, int k2) const { int a[3], b[3]; pt(k1, a); pt(k2, b); return idx(a[0] - b[0], a[1] - b[1], a[2] - b[2]); }
+};
+
+i64 U_off(const Ctx& c, bool aux, int k) {
+  return aux ? i64(c.nk) * c.nao * c.nao + i64(k) * c.naux * c.naux : i64(k) * c.nao * c.nao;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// device_init: tables, workspaces and the work lists that do not depend on V.
+
+int device_init(Ctx& c, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState* dp = new DevState();
+  c.dev_state = dp;
+  DevState& d = *dp;
+  const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nw = c.nw, nib = c.nibz;
+  int st;
+  // U tables
+  {
+    std::vector<cplx> u;
+    u.reserve(size_t(nk) * (no * no + na * na));
+    for (int k = 0; k < nk; ++k) u.insert(u.end(), c.U_ao[k].a.begin(), c.U_ao[k].a.end());
+    for (int k = 0; k < nk; ++k) u.insert(u.end(), c.U_aux[k].a.begin(), c.U_aux[k].a.end());
+    if ((st = upload(c, d, u, &d.U, s))) return st;
+  }
+  {
+    std::vector<cplx> tr;
+    tr.insert(tr.end(), c.Tf.begin(), c.Tf.end());
+    tr.insert(tr.end(), c.Tb.begin(), c.Tb.end());
+    tr.insert(tr.end(), c.Bf.begin(), c.Bf.end());
+    tr.insert(tr.end(), c.Bb.begin(), c.Bb.end());
+    if ((st = upload(c, d, tr, &d.TR, s))) return st;
+    void* t;
+    if ((st = upload(c, d, c.tau, &t, s))) return st;
+    d.tau = static_cast<double*>(t);
+  }
+  const i64 TF = 0, TB = i64(nw) * nt, BF = 2 * i64(nw) * nt, BB = 3 * i64(nw) * nt;
+  // block tables: count, then (off, size, poff) per block
+  {
+    std::vector<int> bt;
+    for (int i = 0; i < nib; ++i) {
+      d.bt_ao.push_back(int(bt.size()));
+      const Blocks& B = c.bao[i];
+      bt.push_back(int(B.size.size()));
+      for (size_t r = 0; r < B.size.size(); ++r) {
+        bt.push_back(B.off[r]);
+        bt.push_back(B.size[r]);
+        bt.push_back(int(B.poff[r]));
+      }
+    }
+    for (int i = 0; i < nib; ++i) {
+      d.bt_aux.push_back(int(bt.size()));
+      const Blocks& B = c.baux[i];
+      bt.push_back(int(B.size.size()));
+      for (size_t r = 0; r < B.size.size(); ++r) {
+        bt.push_back(B.off[r]);
+        bt.push_back(B.size[r]);
+        bt.push_back(int(B.poff[r]));
+      }
+    }
+    void* t;
+    if ((st = upload(c, d, bt, &t, s))) return st;
+    d.btab = static_cast<int*>(t);
+  }
+  // star weights
+  std::vector<int> star(nib, 0);
+  for (int k = 0; k < nk; ++k) star[c.rep[k]]++;
+
+  // tau chunk: contraction workspaces hold J * nk * naux * nao^2 complex numbers each
+  const i64 slab = i64(nk) * na * no * no;
+  int J = c.prm.tau_chunk;
+  if (J <= 0) {
+    const double budget = 2.0e9 / 16.0;  // elements per workspace
+    J = int(std::max(1.0, std::min(double(nt), budget / double(slab))));
+  }
+  J = std::min(J, nt);
+  d.tau_chunk = J;
+  const int nthalf = c.prm.half_tau ? (nt + 1) / 2 : nt;
+
+  // frequency and readout sizes
+  i64 pw = 0, gw = 0;
+  std::vector<i64> pw_off(nib + 1, 0), gw_off(nib + 1, 0);
+  for (int i = 0; i < nib; ++i) {
+    pw_off[i + 1] = pw_off[i] + i64(nw) * c.baux[i].packed;
+    gw_off[i + 1] = gw_off[i] + i64(nw) * c.bao[i].packed;
+  }
+  pw = pw_off[nib];
+  gw = gw_off[nib];
+  i64 ws = std::max<i64>(i64(J) * slab, std::max(pw, gw));
+  ws = std::max<i64>(ws, i64(nk) * nt * std::max(no * no, na * na));   // from_block of P over every k
+  ws = std::max<i64>(ws, c.p_off[nib] + c.g_off[nib]);
+  d.ws_elems = size_t(ws);
+  if ((st = dalloc(c, d, &d.W1, d.ws_elems * 16))) return st;
+  if ((st = dalloc(c, d, &d.W2, d.ws_elems * 16))) return st;
+
+  // ---------------- polarization (eq. P0, Alg. 3) ----------------
+  Mesh mesh{c.n};
+  const double pscale = -c.prm.spin / nk;
+  for (int i = 0; i < nib; ++i) {
+    const int q0 = c.ibz[i];
+    const Blocks& BA = c.baux[i];
+    for (int j0 = 0; j0 < nthalf; j0 += J) {
+      const int j1 = std::min(nthalf, j0 + J);
+      for (int j = j0; j < j1; ++j) {
+        const int jj = j - j0;
+        for (int k = 0; k < nk; ++k) {
+          const int ik = c.rep[k], ikq = c.rep[mesh.add(k, q0)];
+          const i64 vp = (i64(i) * nk + k) * na * no * no;
+          const i64 wo = (i64(jj) * nk + k) * na * no * no;
+          RowSeg r{};
+          r.inbuf = B_VP; r.outbuf = B_W1; r.gbuf = B_G; r.blk = d.bt_ao[ikq];
+          r.in_off = vp; r.out_off = wo; r.g_off = c.g_off[ikq] + i64(j) * c.bao[ikq].packed; r.nrows = na * no;
+          d.p0_right.add(r);
+          RowSeg l{};
+          l.inbuf = B_VP; l.outbuf = B_W2; l.gbuf = B_G; l.blk = d.bt_ao[ik];
+          l.in_off = vp; l.out_off = wo; l.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed; l.nrows = na * no;
+          d.p0_left.add(l);
+        }
+        for (size_t sg = 0; sg < BA.size.size(); ++sg) {
+          const int m = BA.size[sg], off = BA.off[sg];
+          const i64 w0 = i64(jj) * slab + i64(off) * no;
+          d.p0_gemm.add(gp(m, m, no, nk * no, 1, B_W1, w0, no, i64(na) * no, 0, OP_N, B_W2, w0, no, i64(na) * no, 0, OP_H,
+                           B_OUT, c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale));
+        }
+      }
+      d.p0_right.close();
+      d.p0_left.close();
+      d.p0_gemm.close();
+    }
+    if (c.prm.half_tau)
+      for (int j = 0; j < nt / 2; ++j)
+        if (nt - 1 - j != j)
+          d.p0_mirror.items.push_back({B_OUT, B_OUT, 0, 0, c.p_off[i] + i64(j) * BA.packed,
+                                       c.p_off[i] + i64(nt - 1 - j) * BA.packed, BA.packed});
+  }
+  d.p0_mirror.close();
+
+  // ---------------- self-energy (eq. sigma, Alg. 4) ----------------
+  for (int i = 0; i < nib; ++i) {
+    const int k0 = c.ibz[i];
+    const Blocks& BO = c.bao[i];
+    for (int j0 = 0; j0 < nt; j0 += J) {
+      const int j1 = std::min(nt, j0 + J);
+      for (int j = j0; j < j1; ++j) {
+        const int jj = j - j0;
+        for (int kp = 0; kp < nk; ++kp) {
+          const int q = mesh.sub(k0, kp), iq = c.rep[q], ik = c.rep[kp];
+          const Blocks& BQ = c.baux[iq];
+          const i64 vs = (i64(i) * nk + kp) * na * no * no;
+          const i64 wo = (i64(jj) * nk + kp) * na * no * no;
+          for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
+            const int m = BQ.size[sg], off = BQ.off[sg];
+            // Y = P_blk^T Vs  (rows s' of block sg)
+            d.s_gemmA.add(gp(m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j) * BQ.packed + BQ.poff[sg], m, 0, 0, OP_T, B_VS,
+                             vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1, wo + i64(off) * no * no, i64(no) * no, 0));
+          }
+          RowSeg r{};
+          r.inbuf = B_W1; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
+          r.in_off = wo; r.out_off = wo; r.g_off = c.g_off[ik] + i64(j) * c.bao[ik].packed; r.nrows = na * no;
+          d.s_right.add(r);
+        }
+        for (size_t rb = 0; rb < BO.size.size(); ++rb) {
+          const int n = BO.size[rb], off = BO.off[rb];
+          d.s_gemmC.add(gp(n, n, no, nk * na, 1, B_W2, i64(jj) * slab + i64(off) * no, no, i64(no) * no, 0, OP_N, B_VS,
+                           i64(i) * nk * na * no * no + i64(off) * no, no, i64(no) * no, 0, OP_H, B_OUT,
+                           c.g_off[i] + i64(j) * BO.packed + BO.poff[rb], n, 0, -1.0 / nk));
+        }
+      }
+      d.s_gemmA.close();
+      d.s_right.close();
+      d.s_gemmC.close();
+    }
+  }
+
+  // ---------------- screened interaction (eq. P02P) ----------------
+  for (int i = 0; i < nib; ++i) {
+    const Blocks& B = c.baux[i];
+    d.scr_fwd.add(gp(nw, int(B.packed), nt, 1, 1, B_TR, TB, nt, 0, 0, OP_N, B_IN, c.p_off[i], B.packed, 0, 0, OP_N, B_W1,
+                     pw_off[i], B.packed, 0));
+    d.scr_bwd.add(gp(nt, int(B.packed), nw, 1, 1, B_TR, BB, nw, 0, 0, OP_N, B_W2, pw_off[i], B.packed, 0, 0, OP_N, B_W1,
+                     c.p_off[i], B.packed, 0));
+    for (int n = 0; n < nw; ++n)
+      for (size_t sg = 0; sg < B.size.size(); ++sg) {
+        InvItem it{};
+        it.n = B.size[sg]; it.xbuf = B_W1; it.fbuf = B_W1; it.outbuf = B_W2;
+        it.x_off = pw_off[i] + i64(n) * B.packed + B.poff[sg]; it.f_off = -1; it.out_off = it.x_off; it.w = 0;
+        d.scr_inv.items.push_back(it);
+      }
+    for (int j = 0; j < nt; ++j)
+      for (size_t sg = 0; sg < B.size.size(); ++sg) {
+        const i64 o = c.p_off[i] + i64(j) * B.packed + B.poff[sg];
+        d.scr_herm.items.push_back({B_W1, B_OUT, B.size[sg], 0, o, o, 0});
+      }
+  }
+  d.scr_fwd.close();
+  d.scr_bwd.close();
+  d.scr_inv.close();
+  d.scr_herm.close();
+
+  // ---------------- Dyson equation and mu (eq. dyson, N_e) ----------------
+  std::vector<double> g0w;
+  for (int i = 0; i < nib; ++i) {
+    const Blocks& B = c.bao[i];
+    d.dys_fwd.add(gp(nw, int(B.packed), nt, 1, 1, B_TR, TF, nt, 0, 0, OP_N, B_IN, c.g_off[i], B.packed, 0, 0, OP_N, B_W1,
+                     gw_off[i], B.packed, 0));
+    d.dys_bwd.add(gp(nt, int(B.packed), nw, 1, 1, B_TR, BF, nw, 0, 0, OP_N, B_W2, gw_off[i], B.packed, 0, 0, OP_N, B_W1,
+                     c.g_off[i], B.packed, 0));
+    for (int n = 0; n < nw; ++n)
+      for (size_t r = 0; r < B.size.size(); ++r) {
+        InvItem it{};
+        it.n = B.size[r]; it.xbuf = B_W1; it.fbuf = B_F; it.outbuf = B_W2;
+        it.x_off = gw_off[i] + i64(n) * B.packed + B.poff[r]; it.f_off = c.f_off[i] + B.poff[r];
+        it.out_off = it.x_off; it.w = (2.0 * n + 1.0) * M_PI / c.prm.beta;
+        d.dys_inv.items.push_back(it);
+        d.mu_inv.items.push_back(it);
+        d.mu_items.items.push_back({n, 0, double(star[i])});
+      }
+    for (int j = 0; j < nt; ++j)
+      for (size_t r = 0; r < B.size.size(); ++r) {
+        const i64 o = c.g_off[i] + i64(j) * B.packed + B.poff[r];
+        d.dys_herm.items.push_back({B_W1, B_OUT, B.size[r], 0, o, o, 0});
+      }
+    for (size_t r = 0; r < B.size.size(); ++r) {
+      EigItem e{};
+      e.n = B.size[r]; e.fbuf = B_F; e.gbuf = B_OUT;
+      e.f_off = c.f_off[i] + B.poff[r]; e.g_off = c.g_off[i] + B.poff[r]; e.g_stride = B.packed;
+      d.g0_items.items.push_back(e);
+      g0w.push_back(double(star[i]));
+    }
+  }
+  d.dys_fwd.close();
+  d.dys_bwd.close();
+  d.dys_inv.close();
+  d.mu_inv.close();
+  d.mu_items.close();
+  d.dys_herm.close();
+  d.g0_items.close();
+
+  // ---------------- to_block / from_block (eq. mat_blk, eq. mat_rot) ----------------
+  for (int kind = 0; kind < 3; ++kind) {
+    const bool aux = kind == GWSYM_KIND_P;
+    const int nb = aux ? na : no;
+    const int ntk = kind == GWSYM_KIND_F ? 1 : nt;
+    const std::vector<i64>& boff = kind == GWSYM_KIND_F ? c.f_off : kind == GWSYM_KIND_G ? c.g_off : c.p_off;
+    for (int i = 0; i < nib; ++i) {
+      const Blocks& B = aux ? c.baux[i] : c.bao[i];
+      const i64 uo = U_off(c, aux, c.ibz[i]);
+      const i64 fo = i64(i) * ntk * nb * nb;
+      d.tb_1[kind].add(gp(nb, nb, nb, 1, ntk, B_IN, fo, nb, 0, i64(nb) * nb, OP_N, B_U, uo, nb, 0, 0, OP_N, B_W1, fo, nb,
+                          i64(nb) * nb));
+      for (size_t r = 0; r < B.size.size(); ++r)
+        d.tb_2[kind].add(gp(B.size[r], B.size[r], nb, 1, ntk, B_U, uo + B.off[r], nb, 0, 0, OP_H, B_W1, fo + B.off[r], nb, 0,
+                            i64(nb) * nb, OP_N, B_OUT, boff[i] + B.poff[r], B.size[r], B.packed));
+    }
+    d.tb_1[kind].close();
+    d.tb_2[kind].close();
+    for (int k = 0; k < nk; ++k) {
+      const int i = c.rep[k];
+      const Blocks& B = aux ? c.baux[i] : c.bao[i];
+      const i64 uo = U_off(c, aux, k);
+      const i64 fo = i64(k) * ntk * nb * nb;
+      for (size_t r = 0; r < B.size.size(); ++r)
+        d.fb_1[kind].add(gp(nb, B.size[r], B.size[r], 1, ntk, B_U, uo + B.off[r], nb, 0, 0, OP_N, B_IN, boff[i] + B.poff[r],
+                            B.size[r], 0, B.packed, OP_N, B_W1, fo + B.off[r], nb, i64(nb) * nb));
+      d.fb_2[kind].add(gp(nb, nb, nb, 1, ntk, B_W1, fo, nb, 0, i64(nb) * nb, OP_N, B_U, uo, nb, 0, 0, OP_H, B_OUT, fo, nb,
+                          i64(nb) * nb));
+    }
+    d.fb_1[kind].close();
+    d.fb_2[kind].close();
+  }
+
+  for (GemmStage* g : {&d.p0_gemm, &d.s_gemmA, &d.s_gemmC, &d.scr_fwd, &d.scr_bwd, &d.dys_fwd, &d.dys_bwd})
+    if ((st = upload_stage(c, d, *g, s))) return st;
+  for (int kind = 0; kind < 3; ++kind)
+    for (GemmStage* g : {&d.tb_1[kind], &d.tb_2[kind], &d.fb_1[kind], &d.fb_2[kind]})
+      if ((st = upload_stage(c, d, *g, s))) return st;
+  for (RowStage* r : {&d.p0_right, &d.p0_left, &d.s_right})
+    if ((st = upload(c, d, r->segs, &r->d, s))) return st;
+  for (auto* l : {&d.p0_mirror, &d.scr_herm, &d.dys_herm})
+    if ((st = upload(c, d, l->items, &l->d, s))) return st;
+  for (auto* l : {&d.scr_inv, &d.dys_inv, &d.mu_inv})
+    if ((st = upload(c, d, l->items, &l->d, s))) return st;
+  if ((st = upload(c, d, d.mu_items.items, &d.mu_items.d, s))) return st;
+  if ((st = upload(c, d, d.g0_items.items, &d.g0_items.d, s))) return st;
+  {
+    void* t;
+    if ((st = upload(c, d, g0w, &t, s))) return st;
+    d.wts = static_cast<double*>(t);
+  }
+  void* t;
+  if ((st = dalloc(c, d, &t, 16 * sizeof(double)))) return st;
+  d.scratch = static_cast<double*>(t);
+  if ((st = dalloc(c, d, &t, std::max<size_t>(1, d.mu_inv.items.size()) * 2 * sizeof(double)))) return st;
+  d.trace = static_cast<double*>(t);
+  if ((st = dalloc(c, d, &t, std::max<size_t>(1, d.g0_items.items.size()) * sizeof(double)))) return st;
+  d.occ = static_cast<double*>(t);
+  if ((st = dalloc(c, d, &t, std::max<size_t>(1, d.g0_items.items.size()) * 2 * sizeof(double)))) return st;
+  d.erange = static_cast<double*>(t);
+  if ((st = dalloc(c, d, &t, sizeof(int)))) return st;
+  d.status = static_cast<int*>(t);
+  HIPCHECK(hipMemsetAsync(d.status, 0, sizeof(int), s));
+  HIPCHECK(hipMemsetAsync(d.scratch, 0, 16 * sizeof(double), s));
+  HIPCHECK(hipStreamSynchronize(s));
+  c.dev = true;
+  return GWSYM_OK;
+}
+
+void device_free(Ctx& c) {
+  DevState* d = static_cast<DevState*>(c.dev_state);
+  if (!d) return;
+  for (void* p : d->allocs) hipFree(p);
+  delete d;
+  c.dev_state = nullptr;
+  c.dev = false;
+  c.vloaded = false;
+}
+
+namespace {
+
+Bases bases_of(DevState& d) {
+  Bases b{};
+  b.p[B_VP] = d.VP;
+  b.p[B_VS] = d.VS;
+  b.p[B_W1] = d.W1;
+  b.p[B_W2] = d.W2;
+  b.p[B_TR] = d.TR;
+  b.p[B_U] = d.U;
+  b.p[B_WT] = d.WT;
+  return b;
+}
+
+}  // namespace
+
+// Split-K partial tiles: one 32 x 32 complex slot each, sized for the largest launch.
+int need_partials(Ctx& c, DevState& d) {
+  if (d.nslots <= d.partial_cap) return GWSYM_OK;
+  if (d.partials) {
+    hipFree(d.partials);
+    d.allocs.erase(std::find(d.allocs.begin(), d.allocs.end(), d.partials));
+    d.partials = nullptr;
+  }
+  const int st = dalloc(c, d, &d.partials, d.nslots * 32 * 32 * 16);
+  if (st == GWSYM_OK) d.partial_cap = d.nslots;
+  return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// load_V: block-transformed copies of V for the two contractions (eq. C_blk, Sec. 4.2).
+
+int device_load_V(Ctx& c, const void* Vin, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  const int nk = c.nk, no = c.nao, na = c.naux, nib = c.nibz;
+  const i64 pe = i64(na) * no * no;  // elements per pair
+  int st;
+  if (!d.VP) {
+    if ((st = dalloc(c, d, &d.VP, size_t(nib) * nk * pe * 16))) return st;
+    if ((st = dalloc(c, d, &d.VS, size_t(nib) * nk * pe * 16))) return st;
+  }
+  Mesh mesh{c.n};
+  // inverse operations
+  std::vector<int> opinv(c.nop, -1);
+  for (int a = 0; a < c.nop; ++a)
+    for (int b = 0; b < c.nop; ++b) {
+      int prod[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          int sum = 0;
+          for (int k = 0; k < 3; ++k) sum += c.W[9 * a + 3 * i + k] * c.W[9 * b + 3 * k + j];
+          prod[3 * i + j] = sum;
+        }
+      bool id = true;
+      for (int j = 0; j < 9; ++j) id &= prod[j] == (j % 4 == 0 ? 1 : 0);
+      if (id) opinv[a] = b;
+    }
+  // Per-pair source and rotation matrices for the polarization copy: V^{k,k+q0} with
+  // k = alpha k1 (k1 representative) equals the rotation of V^{k1,k''}, k'' = k1 + alpha^{-1} q0.
+  struct Pair {
+    int src;          // pair index in the input [i][k'] layout
+    bool ident;       // alpha = identity: rotations are U^H / U only
+    i64 wl, wr, wa;   // offsets in WT (or U)
+  };
+  std::vector<Pair> pp(size_t(nib) * nk);
+  std::vector<cplx> wt;
+  for (int i = 0; i < nib; ++i) {
+    const int q0 = c.ibz[i];
+    for (int k = 0; k < nk; ++k) {
+      const int i1 = c.rep[k], k1 = c.ibz[i1], a = c.alpha[k];
+      const int kpp = mesh.add(k1, c.kmap[size_t(opinv[a]) * nk + q0]);
+      const int kq = mesh.add(k, q0);
+      if (c.kmap[size_t(a) * nk + kpp] != kq) return c.err = "inconsistent k rotation in load_V", GWSYM_EINVAL;
+      Pair p{};
+      p.src = i1 * nk + kpp;
+      p.ident = a == 0;
+      if (!p.ident) {
+        const CMat Ok1 = orbital_rep(c, false, a, k1);
+        const CMat Okpp = orbital_rep(c, false, a, kpp);
+        const CMat Oq = orbital_rep(c, true, a, mesh.sub(kpp, k1));
+        const CMat WL = adjoint(matmul(adjoint(Ok1), c.U_ao[k]));     // U^{k H} O^{k1}(a)
+        const CMat WR = matmul(adjoint(Okpp), c.U_ao[kq]);            // O^{k''}(a)^H U^{k+q0}
+        const CMat WA = adjoint(matmul(adjoint(Oq), c.U_aux[q0]));    // U_aux^{q0 H} Obar^{k''-k1}(a)
+        p.wl = i64(wt.size());
+        wt.insert(wt.end(), WL.a.begin(), WL.a.end());
+        p.wr = i64(wt.size());
+        wt.insert(wt.end(), WR.a.begin(), WR.a.end());
+        p.wa = i64(wt.size());
+        wt.insert(wt.end(), WA.a.begin(), WA.a.end());
+      }
+      pp[size_t(i) * nk + k] = p;
+    }
+  }
+  if (d.WT) { /* reloading: the previous table is kept in the allocation list */ }
+  if ((st = upload(c, d, wt, &d.WT, s))) return st;
+  // work lists, processed in chunks of pairs that fit the two workspaces
+  const int chunk = int(std::max<i64>(1, i64(d.ws_elems) / pe));
+  GemmStage g1, g2, g3;
+  const int npairs = nib * nk;
+  for (int which = 0; which < 2; ++which) {        // 0: self-energy copy, 1: polarization copy
+    for (int p0 = 0; p0 < npairs; p0 += chunk) {
+      const int p1 = std::min(npairs, p0 + chunk);
+      for (int p = p0; p < p1; ++p) {
+        const int i = p / nk, k = p % nk;
+        const i64 w = i64(p - p0) * pe;
+        if (which == 0) {
+          // Vs(s) = sum_Q U^q_{Qs} [U^{k0 H} V(Q) U^{k'}],  q = k0 - k'
+          const int k0 = c.ibz[i], q = mesh.sub(k0, k);
+          g1.add(gp(na * no, no, no, 1, 1, B_IN, i64(p) * pe, no, 0, 0, OP_N, B_U, U_off(c, false, k), no, 0, 0, OP_N,
+                    B_W1, w, no, 0));
+          g2.add(gp(no, no, no, 1, na, B_U, U_off(c, false, k0), no, 0, 0, OP_H, B_W1, w, no, 0, i64(no) * no, OP_N, B_W2,
+                    w, no, i64(no) * no));
+          g3.add(gp(na, no * no, na, 1, 1, B_U, U_off(c, true, q), na, 0, 0, OP_T, B_W2, w, i64(no) * no, 0, 0, OP_N, B_VS,
+                    i64(p) * pe, i64(no) * no, 0));
+        } else {
+          const Pair& pr = pp[p];
+          const int q0 = c.ibz[i], kq = mesh.add(k, q0);
+          const i64 src = i64(pr.src) * pe;
+          if (pr.ident) {
+            g1.add(gp(na * no, no, no, 1, 1, B_IN, src, no, 0, 0, OP_N, B_U, U_off(c, false, kq), no, 0, 0, OP_N, B_W1, w,
+                      no, 0));
+            g2.add(gp(no, no, no, 1, na, B_U, U_off(c, false, k), no, 0, 0, OP_H, B_W1, w, no, 0, i64(no) * no, OP_N, B_W2,
+                      w, no, i64(no) * no));
+            // a-major output [a][s][b]: batch over a
+            g3.add(gp(na, no, na, 1, no, B_U, U_off(c, true, q0), na, 0, 0, OP_H, B_W2, w, i64(no) * no, 0, no, OP_N, B_VP,
+                      i64(p) * pe, no, i64(na) * no));
+          } else {
+            g1.add(gp(na * no, no, no, 1, 1, B_IN, src, no, 0, 0, OP_N, B_WT, pr.wr, no, 0, 0, OP_N, B_W1, w, no, 0));
+            g2.add(gp(no, no, no, 1, na, B_WT, pr.wl, no, 0, 0, OP_N, B_W1, w, no, 0, i64(no) * no, OP_N, B_W2, w, no,
+                      i64(no) * no));
+            g3.add(gp(na, no, na, 1, no, B_WT, pr.wa, na, 0, 0, OP_N, B_W2, w, i64(no) * no, 0, no, OP_N, B_VP, i64(p) * pe,
+                      no, i64(na) * no));
+          }
+        }
+      }
+      g1.close();
+      g2.close();
+      g3.close();
+    }
+  }
+  for (GemmStage* g : {&g1, &g2, &g3})
+    if ((st = upload_stage(c, d, *g, s))) return st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_IN] = const_cast<void*>(Vin);
+  for (size_t l = 0; l < g1.launches.size(); ++l) {
+    launch_brgemm(plan_of(g1, g1.launches[l]), b, d.partials, s);
+    launch_brgemm(plan_of(g2, g2.launches[l]), b, d.partials, s);
+    launch_brgemm(plan_of(g3, g3.launches[l]), b, d.partials, s);
+  }
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(s));
+  c.vloaded = true;
+  return GWSYM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+
+int device_to_block(Ctx& c, int kind, const void* full, void* blk, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_IN] = const_cast<void*>(full);
+  b.p[B_OUT] = blk;
+  launch_brgemm(plan_of(d.tb_1[kind], d.tb_1[kind].launches[0]), b, d.partials, s);
+  launch_brgemm(plan_of(d.tb_2[kind], d.tb_2[kind].launches[0]), b, d.partials, s);
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+int device_from_block(Ctx& c, int kind, const void* blk, void* full, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_IN] = const_cast<void*>(blk);
+  b.p[B_OUT] = full;
+  launch_brgemm(plan_of(d.fb_1[kind], d.fb_1[kind].launches[0]), b, d.partials, s);
+  launch_brgemm(plan_of(d.fb_2[kind], d.fb_2[kind].launches[0]), b, d.partials, s);
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+int device_g0(Ctx& c, const void* F, double mu, void* G, double* nfree, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  for (const EigItem& e : d.g0_items.items)
+    if (e.n > 64) return c.err = "orbital block larger than 64 in g0", GWSYM_ESHAPE;
+  Bases b = bases_of(d);
+  b.p[B_F] = const_cast<void*>(F);
+  b.p[B_OUT] = G;
+  const int n = int(d.g0_items.items.size());
+  launch_jacobi_g0(d.g0_items.d, n, b, d.tau, c.ntau, c.prm.beta, mu, d.occ, d.erange, s);
+  launch_g0_reduce(d.occ, d.wts, d.erange, n, c.prm.spin / c.nk, nfree ? nfree : d.scratch + 5, d.scratch + 3, s);
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_G] = const_cast<void*>(G);
+  b.p[B_OUT] = P0;
+  for (size_t l = 0; l < d.p0_gemm.launches.size(); ++l) {
+    const Range& rr = d.p0_right.launches[l];
+    RowSegList R{static_cast<RowSeg*>(d.p0_right.d) + rr.t0, rr.nt, rr.r0};
+    launch_rowblock_right(R, b, d.btab, c.nao, s);
+    const Range& rl = d.p0_left.launches[l];
+    RowSegList L{static_cast<RowSeg*>(d.p0_left.d) + rl.t0, rl.nt, rl.r0};
+    launch_rowblock_left(L, b, d.btab, c.nao, s);
+    launch_brgemm(plan_of(d.p0_gemm, d.p0_gemm.launches[l]), b, d.partials, s);
+  }
+  const Range& m = d.p0_mirror.launches[0];
+  launch_copy(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s);
+  HIPCHECK(hipGetLastError());
+  c.last_macs[0] = d.p0_gemm.macs;
+  return GWSYM_OK;
+}
+
+int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_G] = const_cast<void*>(G);
+  b.p[B_P] = const_cast<void*>(P);
+  b.p[B_OUT] = S;
+  for (size_t l = 0; l < d.s_gemmA.launches.size(); ++l) {
+    launch_brgemm(plan_of(d.s_gemmA, d.s_gemmA.launches[l]), b, d.partials, s);
+    const Range& rr = d.s_right.launches[l];
+    RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
+    launch_rowblock_right(R, b, d.btab, c.nao, s);
+    launch_brgemm(plan_of(d.s_gemmC, d.s_gemmC.launches[l]), b, d.partials, s);
+  }
+  HIPCHECK(hipGetLastError());
+  c.last_macs[1] = d.s_gemmA.macs + d.s_gemmC.macs;
+  return GWSYM_OK;
+}
+
+int device_screened(Ctx& c, const void* P0, void* P, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  for (const InvItem& it : d.scr_inv.items)
+    if (it.n > 512) return c.err = "auxiliary block larger than 512", GWSYM_ESHAPE;
+  Bases b = bases_of(d);
+  b.p[B_IN] = const_cast<void*>(P0);
+  b.p[B_OUT] = P;
+  launch_brgemm(plan_of(d.scr_fwd, d.scr_fwd.launches[0]), b, d.partials, s);
+  launch_inverse(d.scr_inv.d, int(d.scr_inv.items.size()), b, INV_P, nullptr, nullptr, d.status, s);
+  launch_brgemm(plan_of(d.scr_bwd, d.scr_bwd.launches[0]), b, d.partials, s);
+  launch_herm(d.scr_herm.d, int(d.scr_herm.items.size()), b, s);
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_IN] = const_cast<void*>(S);
+  b.p[B_F] = const_cast<void*>(F);
+  b.p[B_OUT] = G;
+  launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s);
+  launch_inverse(d.dys_inv.d, int(d.dys_inv.items.size()), b, INV_G, mu, nullptr, d.status, s);
+  launch_brgemm(plan_of(d.dys_bwd, d.dys_bwd.launches[0]), b, d.partials, s);
+  launch_herm(d.dys_herm.d, int(d.dys_herm.items.size()), b, s);
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double* mu, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_IN] = const_cast<void*>(S);
+  b.p[B_F] = const_cast<void*>(F);
+  launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s);
+  const void* Blast = static_cast<const cplx*>(d.TR) + 2 * i64(c.nw) * c.ntau + i64(c.ntau - 1) * c.nw;
+  launch_mu_init(d.scratch + 3, d.scratch, mu, s);
+  const int n = int(d.mu_inv.items.size());
+  for (int it = 0; it < 64; ++it) {
+    launch_inverse(d.mu_inv.d, n, b, INV_TRACE, mu, d.trace, d.status, s);
+    launch_mu_update(d.mu_items.d, n, d.trace, Blast, c.prm.spin / c.nk, ntarget, d.scratch, mu, s);
+  }
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+}  // namespace gw

@@ -1,0 +1,209 @@
+"""ctypes binding of libgwsym (include/gwsym.h).
+
+Argument marshalling only: every numerical step runs in the library.  Device buffers are
+torch CUDA tensors (complex128) or raw integer addresses; the stream is the current torch
+stream unless one is given.  A missing library raises at import time.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libgwsym.so")
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"libgwsym.so not built at {_LIB_PATH}; run python -m paper_2405_09494_amd.build")
+lib = C.CDLL(_LIB_PATH)
+
+MODE_FULL, MODE_ROTATE, MODE_BLOCK = 0, 1, 2
+FP64, FP32 = 0, 1
+KIND_F, KIND_G, KIND_P = 0, 1, 2
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ESINGULAR", -6: "ENOCONV",
+          -7: "ESTATE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("beta", C.c_double), ("ntau", C.c_int), ("nw", C.c_int), ("spin", C.c_double),
+                ("mode", C.c_int), ("precision", C.c_int), ("half_tau", C.c_int), ("tau_chunk", C.c_int)]
+
+
+class Crystal(C.Structure):
+    _fields_ = [("lattice", C.c_double * 9), ("natom", C.c_int), ("positions", C.POINTER(C.c_double)),
+                ("nop", C.c_int), ("rot", C.POINTER(C.c_int)), ("trans", C.POINTER(C.c_double)),
+                ("kmesh", C.c_int), ("nshell_ao", C.c_int), ("ao_atom", C.POINTER(C.c_int)),
+                ("ao_l", C.POINTER(C.c_int)), ("nshell_aux", C.c_int), ("aux_atom", C.POINTER(C.c_int)),
+                ("aux_l", C.POINTER(C.c_int))]
+
+
+_vp = C.c_void_p
+lib.gwsym_create.argtypes = [C.POINTER(Params), C.POINTER(_vp)]
+lib.gwsym_destroy.argtypes = [_vp]
+lib.gwsym_destroy.restype = None
+lib.gwsym_last_error.argtypes = [_vp]
+lib.gwsym_last_error.restype = C.c_char_p
+lib.gwsym_build_symmetry_basis.argtypes = [_vp, C.POINTER(Crystal)]
+lib.gwsym_table_size.argtypes = [_vp, C.c_char_p]
+lib.gwsym_table_size.restype = C.c_int64
+lib.gwsym_get.argtypes = [_vp, C.c_char_p, _vp, C.c_int64]
+lib.gwsym_device_init.argtypes = [_vp, _vp]
+lib.gwsym_load_V.argtypes = [_vp, _vp, _vp]
+lib.gwsym_to_block.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
+lib.gwsym_from_block.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
+lib.gwsym_g0.argtypes = [_vp, _vp, C.c_double, _vp, _vp, _vp]
+lib.gwsym_polarization.argtypes = [_vp, _vp, _vp, _vp]
+lib.gwsym_screened_interaction.argtypes = [_vp, _vp, _vp, _vp]
+lib.gwsym_self_energy.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.gwsym_find_mu.argtypes = [_vp, _vp, _vp, C.c_double, _vp, _vp]
+lib.gwsym_dyson_G.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+lib.gwsym_flop_counts.argtypes = [_vp, C.POINTER(C.c_double)]
+
+EXPORTED = ["gwsym_create", "gwsym_destroy", "gwsym_last_error", "gwsym_build_symmetry_basis",
+            "gwsym_table_size", "gwsym_get", "gwsym_device_init", "gwsym_load_V", "gwsym_to_block",
+            "gwsym_from_block", "gwsym_g0", "gwsym_polarization", "gwsym_screened_interaction",
+            "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_flop_counts"]
+
+
+class GwsymError(RuntimeError):
+    pass
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """One symmetry-adapted GW problem: crystal, mesh, bases, grids, device state."""
+
+    def __init__(self, beta, ntau, nw, spin=2.0, mode=MODE_BLOCK, precision=FP64, half_tau=True, tau_chunk=0):
+        self.params = Params(beta, ntau, nw, spin, mode, precision, int(half_tau), tau_chunk)
+        h = _vp()
+        self._check(lib.gwsym_create(C.byref(self.params), C.byref(h)), None)
+        self.h = h
+        self._keep = []
+
+    def _check(self, st, h="self"):
+        if st != 0:
+            msg = lib.gwsym_last_error(self.h if h == "self" else None).decode()
+            raise GwsymError(f"{STATUS.get(st, st)}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.gwsym_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- host ------------------------------------------------------------------
+    def build_symmetry_basis(self, lattice, positions, rot, trans, kmesh, ao_shells, aux_shells):
+        lattice = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
+        rot = np.ascontiguousarray(rot, dtype=np.int32).reshape(-1)
+        trans = np.ascontiguousarray(trans, dtype=np.float64).reshape(-1)
+        ao = np.ascontiguousarray(ao_shells, dtype=np.int32).reshape(-1, 2)
+        aux = np.ascontiguousarray(aux_shells, dtype=np.int32).reshape(-1, 2)
+        ao_atom, ao_l = np.ascontiguousarray(ao[:, 0]), np.ascontiguousarray(ao[:, 1])
+        aux_atom, aux_l = np.ascontiguousarray(aux[:, 0]), np.ascontiguousarray(aux[:, 1])
+        self._keep = [pos, rot, trans, ao_atom, ao_l, aux_atom, aux_l]
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        cr = Crystal((C.c_double * 9)(*lattice), len(pos) // 3, pos.ctypes.data_as(dp), len(rot) // 9,
+                     rot.ctypes.data_as(ip), trans.ctypes.data_as(dp), int(kmesh), len(ao),
+                     ao_atom.ctypes.data_as(ip), ao_l.ctypes.data_as(ip), len(aux), aux_atom.ctypes.data_as(ip),
+                     aux_l.ctypes.data_as(ip))
+        self._check(lib.gwsym_build_symmetry_basis(self.h, C.byref(cr)))
+        d = self.table("dims")
+        self.nk, self.nibz, self.nao, self.naux, self.ntau, self.nw, self.nop, self.mode = map(int, d)
+        self.g_off = self.table("g_off")
+        self.p_off = self.table("p_off")
+        self.f_off = self.table("f_off")
+        return self
+
+    _COMPLEX = {"U_ao", "U_aux", "O_ao", "O_aux", "Tf", "Tb", "Bf", "Bb"}
+    _REAL = {"tau"}
+
+    def table(self, name):
+        nb = lib.gwsym_table_size(self.h, name.encode())
+        if nb < 0:
+            self._check(int(nb))
+        if name in self._COMPLEX:
+            out = np.empty(nb // 16, dtype=np.complex128)
+        elif name in self._REAL:
+            out = np.empty(nb // 8, dtype=np.float64)
+        else:
+            out = np.empty(nb // 8, dtype=np.int64)
+        self._check(lib.gwsym_get(self.h, name.encode(), out.ctypes.data, nb))
+        return out
+
+    def blocks(self, aux=False):
+        n = self.naux if aux else self.nao
+        t = self.table("aux_blocks" if aux else "ao_blocks").reshape(self.nibz, 1 + n)
+        return [list(map(int, row[1:1 + row[0]])) for row in t]
+
+    # sizes of the packed layouts (complex elements)
+    @property
+    def g_size(self):
+        return int(self.g_off[-1])
+
+    @property
+    def p_size(self):
+        return int(self.p_off[-1])
+
+    @property
+    def f_size(self):
+        return int(self.f_off[-1])
+
+    # -- device ------------------------------------------------------------------
+    def device_init(self, stream=None):
+        self._check(lib.gwsym_device_init(self.h, _stream(stream)))
+        return self
+
+    def load_V(self, V_ibz, stream=None):
+        self._check(lib.gwsym_load_V(self.h, _ptr(V_ibz), _stream(stream)))
+
+    def to_block(self, kind, full, blk, stream=None):
+        self._check(lib.gwsym_to_block(self.h, kind, _ptr(full), _ptr(blk), _stream(stream)))
+
+    def from_block(self, kind, blk, full, stream=None):
+        self._check(lib.gwsym_from_block(self.h, kind, _ptr(blk), _ptr(full), _stream(stream)))
+
+    def g0(self, F_blk, mu, G_blk, n_free=None, stream=None):
+        self._check(lib.gwsym_g0(self.h, _ptr(F_blk), float(mu), _ptr(G_blk), _ptr(n_free), _stream(stream)))
+
+    def polarization(self, G_blk, P0_blk, stream=None):
+        self._check(lib.gwsym_polarization(self.h, _ptr(G_blk), _ptr(P0_blk), _stream(stream)))
+
+    def screened_interaction(self, P0_blk, P_blk, stream=None):
+        self._check(lib.gwsym_screened_interaction(self.h, _ptr(P0_blk), _ptr(P_blk), _stream(stream)))
+
+    def self_energy(self, G_blk, P_blk, S_blk, stream=None):
+        self._check(lib.gwsym_self_energy(self.h, _ptr(G_blk), _ptr(P_blk), _ptr(S_blk), _stream(stream)))
+
+    def find_mu(self, F_blk, S_blk, n_target, mu, stream=None):
+        self._check(lib.gwsym_find_mu(self.h, _ptr(F_blk), _ptr(S_blk), float(n_target), _ptr(mu), _stream(stream)))
+
+    def dyson_G(self, F_blk, S_blk, mu, G_blk, stream=None):
+        self._check(lib.gwsym_dyson_G(self.h, _ptr(F_blk), _ptr(S_blk), _ptr(mu), _ptr(G_blk), _stream(stream)))
+
+    def flop_counts(self):
+        out = (C.c_double * 2)()
+        self._check(lib.gwsym_flop_counts(self.h, out))
+        return float(out[0]), float(out[1])

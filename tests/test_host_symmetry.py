@@ -1,0 +1,194 @@
+"""Host-side logic of libgwsym, on the CPU: exported symbols, the symmetry basis of Alg. 1
+(orbital representation, stars, Dirac-character blocks) and the transform matrices,
+checked against the independently written input generator, character theory, the
+paper's Table 2 counts and the oracle's transforms.  No GPU call is made."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from gwinputs import Inputs, workload, crystal, cubic_point_group, in_td
+from gwinputs.crystals import FCC
+from gwinputs.crystals import Crystal, _ops_from_cart, shells_on_atoms, S, P, D
+from tests.helpers import make_context, crystal_arrays
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2405_09494_amd import gwsym
+    hdr = open(os.path.join(ROOT, "include", "gwsym.h")).read()
+    declared = set(re.findall(r"\b(gwsym_[A-Za-z0-9_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(gwsym.lib, name), name
+    assert declared == set(gwsym.EXPORTED)
+
+
+@pytest.mark.parametrize("name", ["cfg0", "small_sc4", "small_rocksalt", "small_diamond"])
+def test_orbital_representation_matches_generator(name):
+    wl = workload(name)
+    ctx = make_context(wl)
+    inp = Inputs(wl)
+    O = ctx.table("O_ao").reshape(ctx.nop, ctx.nk, ctx.nao, ctx.nao)
+    Ox = ctx.table("O_aux").reshape(ctx.nop, ctx.nk, ctx.naux, ctx.naux)
+    for a in range(ctx.nop):
+        for k in range(ctx.nk):
+            assert np.abs(O[a, k] - inp.ao.matrix(a, k)).max() < 1e-12
+            assert np.abs(Ox[a, k] - inp.aux.matrix(a, k)).max() < 1e-12
+
+
+def _count(cr, n):
+    from paper_2405_09494_amd import gwsym
+    ctx = gwsym.Context(10.0, 4, 9, 2.0, gwsym.MODE_ROTATE)
+    lat, pos, rot, trans = crystal_arrays(cr)
+    shells = [(x, 0) for x in range(cr.natom)]
+    ctx.build_symmetry_basis(lat, pos, rot, trans, n, shells, shells)
+    return ctx
+
+
+def test_table2_counts_through_library():
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "table2_nik.json")))
+    oh = cubic_point_group()
+    zb_ops = _ops_from_cart(FCC, [R for R in oh if in_td(R)], [np.zeros(3)] * 24)
+    zincblende = Crystal("zincblende", FCC.copy(), np.array([[0, 0, 0], [0.25, 0.25, 0.25]]), [0, 1], zb_ops)
+    groups = {"227": crystal("diamond"), "216": zincblende}
+    for g, d in gold["groups"].items():
+        for nk, cnt in d["nik"].items():
+            assert _count(groups[g], int(nk)).nibz == cnt, (g, nk)
+
+
+def test_star_sizes_and_representatives():
+    for cname, n, sizes in [("sc", 4, [1, 1, 3, 3, 6, 6, 8, 12, 12, 12]),
+                            ("rocksalt", 6, [1, 3, 4, 6, 6, 8, 8, 12, 12, 12, 24, 24, 24, 24, 24, 24])]:
+        ctx = _count(crystal(cname), n)
+        rep = ctx.table("rep")
+        assert sorted(np.bincount(rep).tolist()) == sizes
+        ibz = ctx.table("ibz")
+        kmap = ctx.table("kmap").reshape(ctx.nop, ctx.nk)
+        alpha = ctx.table("alpha")
+        for k in range(ctx.nk):
+            assert kmap[alpha[k], ibz[rep[k]]] == k
+            assert ibz[rep[k]] == min(kmap[:, k])   # representative = smallest index of the star
+
+
+# Isotypic block sizes at Gamma from character theory (l -> O_h irreps:
+# s = A1g, p = T1u, d = Eg + T2g, f = A2u + T1u + T2u, g = A1g + Eg + T1g + T2g)
+GAMMA_BLOCKS = {
+    "cfg0": ([1, 3, 2, 3], [3, 12, 4, 6, 2, 6, 3]),
+    "cfg1": ([3, 9, 4, 6, 1, 3], [12, 36, 24, 36, 6, 18, 18]),
+    "cfg2": ([6, 18, 8, 12, 2, 6], [20, 60, 40, 60, 10, 30, 30]),
+}
+
+
+@pytest.mark.parametrize("name", ["cfg0", "cfg1"])
+def test_gamma_blocks_match_character_theory(name):
+    ctx = make_context(workload(name))
+    ao, aux = GAMMA_BLOCKS[name]
+    assert sorted(ctx.blocks()[0]) == sorted(ao)
+    assert sorted(ctx.blocks(aux=True)[0]) == sorted(aux)
+
+
+def test_gamma_blocks_rocksalt_and_diamond_small_basis():
+    # rocksalt, [s, p, d] on both atoms: A1g 2, T1u 6, Eg 4, T2g 6
+    ctx = make_context(workload("small_rocksalt"))
+    assert sorted(ctx.blocks()[0]) == [2, 4, 6, 6]
+    # diamond, [s, p, d] on both atoms: s -> A1g + A2u; p -> T1u + T2g; d -> Eg + Eu + T2g + T1u
+    # (T_d site irreps induced to O_h): A1g 1, A2u 1, Eg 2, Eu 2, T1u 6, T2g 6
+    ctx = make_context(workload("small_diamond"))
+    assert sorted(ctx.blocks()[0]) == [1, 1, 2, 2, 6, 6]
+
+
+def test_diamond_x_point_blocks_are_even():
+    # bands stick together at X of the non-symmorphic group: every isotypic block of the
+    # projective little-group representation has even dimension
+    ctx = make_context(workload("small_diamond"))
+    ibz = ctx.table("ibz")
+    n = 2
+    x_idx = [i for i, k in enumerate(ibz) if (k // (n * n), (k // n) % n, k % n) in [(0, 1, 1), (1, 0, 1), (1, 1, 0)]]
+    assert x_idx
+    for i in x_idx:
+        assert all(b % 2 == 0 for b in ctx.blocks()[i]), ctx.blocks()[i]
+        assert all(b % 2 == 0 for b in ctx.blocks(aux=True)[i]), ctx.blocks(aux=True)[i]
+
+
+@pytest.mark.parametrize("name", ["small_sc4", "small_rocksalt", "small_diamond"])
+def test_block_basis_diagonalises_symmetric_inputs(name):
+    wl = workload(name)
+    ctx = make_context(wl)
+    inp = Inputs(wl)
+    F = inp.fock().numpy()
+    X = inp.aux_matrices(2).numpy()
+    U = ctx.table("U_ao").reshape(ctx.nk, ctx.nao, ctx.nao)
+    Ux = ctx.table("U_aux").reshape(ctx.nk, ctx.naux, ctx.naux)
+    rep = ctx.table("rep")
+    bo, bx = ctx.blocks(), ctx.blocks(aux=True)
+
+    def offdiag(M, sizes):
+        mask = np.ones(M.shape, bool)
+        o = 0
+        for s in sizes:
+            mask[o:o + s, o:o + s] = False
+            o += s
+        return np.abs(M[mask]).max() if mask.any() else 0.0
+
+    for k in range(ctx.nk):
+        assert np.abs(U[k].conj().T @ U[k] - np.eye(ctx.nao)).max() < 1e-12
+        Fb = U[k].conj().T @ F[k] @ U[k]
+        assert offdiag(Fb, bo[rep[k]]) < 1e-12 * np.abs(F).max()
+        for j in range(2):
+            Xb = Ux[k].conj().T @ X[k, j] @ Ux[k]
+            assert offdiag(Xb, bx[rep[k]]) < 1e-12 * np.abs(X).max()
+    # star consistency: the block form is the same at every point of a star
+    ibz = ctx.table("ibz")
+    for k in range(ctx.nk):
+        k0 = ibz[rep[k]]
+        assert np.abs(U[k].conj().T @ F[k] @ U[k] - U[k0].conj().T @ F[k0] @ U[k0]).max() < 1e-12
+
+
+@pytest.mark.parametrize("boson", [False, True])
+def test_transform_matrices_agree_with_oracle(boson):
+    wl = workload("cfg0")
+    ctx = make_context(wl)
+    Tl = ctx.table("Tb" if boson else "Tf").reshape(wl.nw, wl.ntau)
+    Bl = ctx.table("Bb" if boson else "Bf").reshape(wl.ntau, wl.nw)
+    To, Bo, rows = oracle.transform_matrices(wl.beta, wl.ntau, wl.nw, boson)
+    assert np.abs(Tl - To).max() < 1e-12 * np.abs(To).max()
+    rng = np.random.default_rng(0)
+    Xw = rng.standard_normal((wl.nw, 3, 3)) + 1j * rng.standard_normal((wl.nw, 3, 3))
+    Xw[0] = 0.5 * (Xw[0] + Xw[0].conj().T) if boson else Xw[0]
+    ref = oracle.to_tau(Xw, Bo, rows)
+    Y = np.einsum("tn,nab->tab", Bl, Xw)
+    got = Y + Y.conj().swapaxes(-1, -2)
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(ctx.table("tau") - oracle.tau_grid(wl.beta, wl.ntau)).max() < 1e-13 * wl.beta
+
+
+def test_error_paths():
+    from paper_2405_09494_amd import gwsym
+    with pytest.raises(gwsym.GwsymError):
+        gwsym.Context(-1.0, 10, 21)
+    with pytest.raises(gwsym.GwsymError):
+        gwsym.Context(10.0, 10, 3)            # too few frequencies for the inverse transform
+    ctx = gwsym.Context(10.0, 8, 17)
+    with pytest.raises(gwsym.GwsymError, match="ESTATE"):
+        ctx.table("dims")
+    with pytest.raises(gwsym.GwsymError, match="ESTATE"):
+        ctx.polarization(1, 1, stream=0)
+    cr = crystal("rocksalt")
+    lat, pos, rot, trans = crystal_arrays(cr)
+    bad = trans.copy()
+    bad[5] = [0.25, 0.0, 0.0]                 # does not map the crystal onto itself
+    with pytest.raises(gwsym.GwsymError, match="EINVAL"):
+        ctx.build_symmetry_basis(lat, pos, rot, bad, 2, [(0, 0), (1, 0)], [(0, 0), (1, 0)])
+    ctx3 = gwsym.Context(10.0, 8, 17)
+    dlat, dpos, drot, dtrans = crystal_arrays(crystal("diamond"))   # the two atoms are equivalent
+    with pytest.raises(gwsym.GwsymError, match="shells differ"):
+        ctx3.build_symmetry_basis(dlat, dpos, drot, dtrans, 2, [(0, 0), (1, 1)], [(0, 0), (1, 0)])
+    ctx2 = gwsym.Context(10.0, 8, 17)
+    with pytest.raises(gwsym.GwsymError, match="EINVAL"):
+        ctx2.build_symmetry_basis(lat, pos, rot[::-1], trans[::-1], 2, [(0, 0)], [(0, 0)])  # op 0 not identity
