@@ -207,6 +207,19 @@ int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, cons
  * out[0] = P0 MACs, out[1] = Sigma MACs (as executed, padding excluded). */
 int gwsym_flop_counts(const gwsym_ctx* ctx, double* out2);
 
+/* Live timing of the launches the context enqueues, with HIP events recorded on the
+ * launch stream around every launch (enable != 0) or not at all (enable = 0, default).
+ * Classes: 0 polarization contraction (grouped GEMM), 1 self-energy auxiliary contraction,
+ * 2 self-energy orbital contraction, 3 block-diagonal row multiply, 4 block-diagonal column
+ * multiply, 5 Matsubara transforms, 6 batched inverses, 7 other. */
+int gwsym_profile(gwsym_ctx* ctx, int enable);
+
+/* Waits for the recorded events and returns, per class (arrays of 8, host): total
+ * milliseconds, number of launches, complex multiply-accumulates requested by those
+ * launches and, for the block-diagonal multiplies, the algorithmic bytes they read and
+ * write, since the previous read; then clears the record. */
+int gwsym_profile_read(gwsym_ctx* ctx, double* ms, int64_t* launches, double* macs, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -173,6 +173,32 @@ def self_energy(G: np.ndarray, V: np.ndarray, P: np.ndarray, sub: np.ndarray) ->
     return -(1.0 / nk) * S
 
 
+def polarization_unit(G: np.ndarray, Vq: np.ndarray, add: np.ndarray, q: int, j: int, spin: float) -> np.ndarray:
+    """One output of eq. P0: P0^q_{QQ'}(tau_j), with Vq[k] = V^{k,k+q} for every k."""
+    nk, nt, nao, _ = G.shape
+    naux = Vq.shape[1]
+    acc = np.zeros((naux, naux), dtype=complex)
+    for k in range(nk):
+        A = Vq[k]
+        X1 = (A @ G[add[k, q], j]).reshape(naux, nao * nao)
+        X2 = np.conj(np.swapaxes(A, -1, -2)) @ G[k, nt - 1 - j]
+        acc += X1 @ np.swapaxes(X2, -1, -2).reshape(naux, nao * nao).T
+    return -(spin / nk) * acc
+
+
+def self_energy_unit(G: np.ndarray, Vk: np.ndarray, P: np.ndarray, sub: np.ndarray, k: int, j: int) -> np.ndarray:
+    """One output of eq. sigma: Sigma~^k(tau_j), with Vk[q] = V^{k,k-q} and P[q] = P^q(tau_j)."""
+    nk, nt, nao, _ = G.shape
+    naux = Vk.shape[1]
+    acc = np.zeros((nao, nao), dtype=complex)
+    for q in range(nk):
+        A = Vk[q]
+        X1 = A @ G[sub[k, q], j]
+        Y = (P[q].T @ X1.reshape(naux, nao * nao)).reshape(naux, nao, nao)
+        acc += np.swapaxes(Y, 0, 1).reshape(nao, naux * nao) @ np.conj(np.swapaxes(A, 0, 1).reshape(nao, naux * nao)).T
+    return -(1.0 / nk) * acc
+
+
 # ----------------------------------------------------------------------------
 # screened interaction (eq. P02P) and Dyson equation (eq. dyson)
 

@@ -239,6 +239,19 @@ int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, cons
   return device_dyson(ctx->c, F_blk, Sigma_blk, mu, G_blk, stream);
 }
 
+int gwsym_profile(gwsym_ctx* ctx, int enable) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.dev, GWSYM_ESTATE, "gwsym_device_init must come first");
+  return device_profile(ctx->c, enable);
+}
+
+int gwsym_profile_read(gwsym_ctx* ctx, double* ms, int64_t* launches, double* macs, double* bytes) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.dev, GWSYM_ESTATE, "gwsym_device_init must come first");
+  NEED(ms && launches && macs && bytes, GWSYM_EINVAL, "NULL buffer");
+  return device_profile_read(ctx->c, ms, launches, macs, bytes);
+}
+
 int gwsym_flop_counts(const gwsym_ctx* ctx, double* out2) {
   if (!ctx || !out2) return GWSYM_EINVAL;
   out2[0] = ctx->c.last_macs[0];

@@ -91,7 +91,7 @@ struct GemmPlan {
 
 // Buffer ids used in GemmProblem::abuf/bbuf/cbuf; the launch passes the base pointers.
 enum Buf : int {
-  B_VP = 0, B_VS, B_G, B_P, B_W1, B_W2, B_OUT, B_TR, B_IN, B_U, B_WT, B_F, NBUF
+  B_VP = 0, B_VS, B_G, B_P, B_W1, B_W2, B_OUT, B_TR, B_IN, B_U, B_WT, B_F, B_SCR, NBUF
 };
 
 struct Ctx {
@@ -156,5 +156,7 @@ int device_screened(Ctx& c, const void* P0, void* P, void* stream);
 int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stream);
 int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double* mu, void* stream);
 int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream);
+int device_profile(Ctx& c, int enable);
+int device_profile_read(Ctx& c, double* ms, int64_t* launches, double* macs, double* bytes);
 
 }  // namespace gw

@@ -57,18 +57,23 @@ struct EigItem {
   int64_t f_off, g_off, g_stride;
 };
 
-void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s);
+// tag: 0 generic, 1 polarization contraction, 2 self-energy auxiliary contraction,
+// 3 self-energy orbital contraction (separate kernel names in profiles)
+void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag = 0);
 void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s);
 void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s);
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
+void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_inverse(const void* items, int nitems, const Bases& b, int mode, const double* mu, double* trace,
                     int* status, hipStream_t s);
 void launch_mu_init(const double* eps_range, double* state, double* mu, hipStream_t s);
 void launch_mu_update(const void* items, int nitems, const double* trace, const void* Blast, double scale,
                       double ntarget, double* state, double* mu, hipStream_t s);
+// largest orbital block for the free G0 (the Jacobi matrix stays under 64 KB of LDS)
+constexpr int JAC_N = 60;
 void launch_jacobi_g0(const void* items, int nitems, const Bases& b, const double* tau, int ntau, double beta,
-                      double mu, double* occ, double* erange, hipStream_t s);
+                      double mu, double* occ, double* erange, void* vwork, hipStream_t s);
 void launch_g0_reduce(const double* occ, const double* w, const double* erange, int nitems, double scale,
                       double* nfree, double* eps, hipStream_t s);
 

@@ -45,6 +45,8 @@ __device__ __forceinline__ double2 load_op(const double2* __restrict__ p, int op
   return (op & 2) ? cconj(v) : v;
 }
 
+// TAG only separates the stages in profiles (P0, Sigma aux / orbital contractions, others).
+template <int TAG>
 __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ probs,
                                                 const GemmTile* __restrict__ tiles, Bases bases,
                                                 double2* __restrict__ partials) {
@@ -100,12 +102,12 @@ __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ 
         __syncthreads();
       }
     }
-    // D layout of the 16x16 MFMA: lane holds rows 4*(lane/16)+j, column lane%16
+    // FP64 16x16 MFMA result layout: register j of lane l holds row l/16 + 4 j, column l%16
     const int col = wn * 16 + (lane & 15);
     if (tl.slot >= 0) {
       double2* out = partials + int64_t(tl.slot) * TM * TN;
       for (int j = 0; j < 4; ++j) {
-        const int row = wm * 16 + 4 * (lane >> 4) + j;
+        const int row = wm * 16 + (lane >> 4) + 4 * j;
         out[row * TN + col] = make_double2(cre[j], cim[j]);
       }
       continue;
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ 
     double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]) + P.coff + int64_t(tl.batch) * P.sCb;
     const double2 al = make_double2(P.alpha_re, P.alpha_im);
     for (int j = 0; j < 4; ++j) {
-      const int row = m0 + wm * 16 + 4 * (lane >> 4) + j, cc = n0 + col;
+      const int row = m0 + wm * 16 + (lane >> 4) + 4 * j, cc = n0 + col;
       if (row < P.M && cc < P.N) {
         double2 v = cmul(al, make_double2(cre[j], cim[j]));
         if (P.beta) v = cadd(v, C[int64_t(row) * P.ldc + cc]);
@@ -141,10 +143,18 @@ __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ 
   }
 }
 
-void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s) {
-  if (p.ntiles > 0)
-    hipLaunchKernelGGL(k_brgemm, dim3(p.ntiles), dim3(256), 0, s, (const GemmProblem*)p.probs,
-                       (const GemmTile*)p.tiles, b, (double2*)partials);
+void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag) {
+  if (p.ntiles > 0) {
+    const dim3 g(p.ntiles), t(256);
+    const GemmProblem* pr = (const GemmProblem*)p.probs;
+    const GemmTile* tl = (const GemmTile*)p.tiles;
+    switch (tag) {
+      case 1: hipLaunchKernelGGL(k_brgemm<1>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
+      case 2: hipLaunchKernelGGL(k_brgemm<2>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
+      case 3: hipLaunchKernelGGL(k_brgemm<3>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
+      default: hipLaunchKernelGGL(k_brgemm<0>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
+    }
+  }
   if (p.nreds > 0)
     hipLaunchKernelGGL(k_reduce, dim3(p.nreds), dim3(256), 0, s, (const GemmProblem*)p.probs,
                        (const GemmReduce*)p.reds, b, (const double2*)partials);
@@ -259,6 +269,19 @@ __global__ __launch_bounds__(256) void k_copy(const CopySeg* __restrict__ segs, 
   const double2* a = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off;
   double2* o = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off;
   for (int64_t e = threadIdx.x; e < sg.len; e += 256) o[e] = a[e];
+}
+
+// gather an n x n block with leading dimension len into a contiguous n x n block
+__global__ __launch_bounds__(256) void k_pack(const CopySeg* __restrict__ segs, Bases bases) {
+  const CopySeg sg = segs[blockIdx.x];
+  const double2* a = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off;
+  double2* o = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off;
+  const int n = sg.n;
+  for (int e = threadIdx.x; e < n * n; e += 256) o[e] = a[int64_t(e / n) * sg.len + e % n];
+}
+
+void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s) {
+  if (nseg) hipLaunchKernelGGL(k_pack, dim3(nseg), dim3(256), 0, s, (const CopySeg*)segs, b);
 }
 
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s) {
@@ -464,21 +487,18 @@ void launch_mu_update(const void* items, int nitems, const double* trace, const 
 // then G0(tau_j) = -V diag(g(e, tau_j)) V^H with g = exp(-e tau)/(1 + exp(-beta e)) in a
 // form that never overflows.  Also writes per-block occupations and eigenvalue range.
 
-constexpr int JAC_N = 64;
-
+// A (at most JAC_N x JAC_N) lives in LDS; the eigenvector matrix V lives in a global
+// workspace slice of JAC_N * JAC_N per item, so that the workgroup stays under 64 KB of LDS.
 __global__ __launch_bounds__(256) void k_jacobi_g0(const EigItem* __restrict__ items, Bases bases,
                                                    const double* __restrict__ tau, int ntau, double beta, double mu,
-                                                   double* __restrict__ occ, double* __restrict__ erange) {
+                                                   double* __restrict__ occ, double* __restrict__ erange,
+                                                   double2* __restrict__ vwork) {
   __shared__ double2 A[JAC_N * JAC_N];
-  __shared__ double2 V[JAC_N * JAC_N];
-  __shared__ double cs[JAC_N / 2], sn[JAC_N / 2];
-  __shared__ double2 ph[JAC_N / 2];
-  __shared__ int pp[JAC_N / 2], qq[JAC_N / 2];
-  __shared__ double red[256];
   __shared__ double ev[JAC_N];
   const EigItem it = items[blockIdx.x];
   const int n = it.n, tid = threadIdx.x;
   const int m = (n + 1) & ~1;  // even size for the round-robin pairing (index n is a dummy)
+  double2* V = vwork + int64_t(blockIdx.x) * JAC_N * JAC_N;
   const double2* F = reinterpret_cast<const double2*>(bases.p[it.fbuf]) + it.f_off;
   for (int e = tid; e < m * m; e += 256) {
     const int r = e / m, c = e % m;
@@ -491,83 +511,51 @@ __global__ __launch_bounds__(256) void k_jacobi_g0(const EigItem* __restrict__ i
     V[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // convergence test on the off-diagonal norm
-    double s = 0.0, d = 0.0;
-    for (int e = tid; e < m * m; e += 256) {
-      const double2 v = A[e];
-      if (e / m != e % m) s += v.x * v.x + v.y * v.y;
-      else d += v.x * v.x;
-    }
-    red[tid] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double off = red[0];
-    __syncthreads();
-    red[tid] = d;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double tot = red[0] + off;
-    __syncthreads();
-    if (off <= 1e-32 * tot || off == 0.0) break;
-    for (int round = 0; round < m - 1; ++round) {
-      // round-robin pairs: position 0 fixed, the others rotate
-      if (tid < m / 2) {
-        const int i = tid;
-        auto pos = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + round) % (m - 1)); };
-        int p = pos(i), q = pos(m - 1 - i);
-        if (p > q) { const int t = p; p = q; q = t; }
-        pp[i] = p;
-        qq[i] = q;
-        const double2 b = A[p * m + q];
-        const double ab = sqrt(b.x * b.x + b.y * b.y);
-        if (ab < 1e-300) {
-          cs[i] = 1.0; sn[i] = 0.0; ph[i] = make_double2(1.0, 0.0);
-        } else {
+  // Cyclic Jacobi by one lane (blocks are small and G0 is computed once): each rotation
+  // removes the phase of the pivot A_pq with diag(1, e^{-i phi}) and then applies the real
+  // rotation that zeroes it, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]], A <- J^H A J, V <- V J.
+  if (tid == 0) {
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      double off = 0.0, tot = 0.0;
+      for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) {
+          const double2 v = A[r * m + c];
+          const double w = v.x * v.x + v.y * v.y;
+          tot += w;
+          if (r != c) off += w;
+        }
+      if (off <= 1e-34 * tot) break;
+      for (int p = 0; p < m; ++p)
+        for (int q = p + 1; q < m; ++q) {
+          const double2 b = A[p * m + q];
+          const double ab = sqrt(b.x * b.x + b.y * b.y);
+          if (ab < 1e-300) continue;
+          const double2 ep = make_double2(b.x / ab, b.y / ab), em = cconj(ep);
           const double a = A[p * m + p].x, dd = A[q * m + q].x;
           const double th = (dd - a) / (2.0 * ab);
           const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          cs[i] = c; sn[i] = t * c; ph[i] = make_double2(b.x / ab, b.y / ab);
+          const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+          for (int k = 0; k < m; ++k) {
+            const double2 akp = A[k * m + p], t1 = cmul(em, A[k * m + q]);
+            A[k * m + p] = make_double2(c * akp.x - s * t1.x, c * akp.y - s * t1.y);
+            A[k * m + q] = make_double2(s * akp.x + c * t1.x, s * akp.y + c * t1.y);
+            const double2 vkp = V[k * m + p], t2 = cmul(em, V[k * m + q]);
+            V[k * m + p] = make_double2(c * vkp.x - s * t2.x, c * vkp.y - s * t2.y);
+            V[k * m + q] = make_double2(s * vkp.x + c * t2.x, s * vkp.y + c * t2.y);
+          }
+          for (int k = 0; k < m; ++k) {
+            const double2 apk = A[p * m + k], t1 = cmul(ep, A[q * m + k]);
+            A[p * m + k] = make_double2(c * apk.x - s * t1.x, c * apk.y - s * t1.y);
+            A[q * m + k] = make_double2(s * apk.x + c * t1.x, s * apk.y + c * t1.y);
+          }
+          A[p * m + q] = make_double2(0.0, 0.0);
+          A[q * m + p] = make_double2(0.0, 0.0);
+          A[p * m + p].y = 0.0;
+          A[q * m + q].y = 0.0;
         }
-      }
-      __syncthreads();
-      // columns: A <- A J, V <- V J, J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
-      for (int e = tid; e < (m / 2) * m; e += 256) {
-        const int i = e / m, k = e % m;
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        const double2 em = cconj(ph[i]);
-        const double2 akp = A[k * m + p], akq = A[k * m + q];
-        const double2 t1 = cmul(em, akq);
-        A[k * m + p] = make_double2(c * akp.x - s * t1.x, c * akp.y - s * t1.y);
-        A[k * m + q] = make_double2(s * akp.x + c * t1.x, s * akp.y + c * t1.y);
-        const double2 vkp = V[k * m + p], vkq = V[k * m + q];
-        const double2 t2 = cmul(em, vkq);
-        V[k * m + p] = make_double2(c * vkp.x - s * t2.x, c * vkp.y - s * t2.y);
-        V[k * m + q] = make_double2(s * vkp.x + c * t2.x, s * vkp.y + c * t2.y);
-      }
-      __syncthreads();
-      // rows: A <- J^H A
-      for (int e = tid; e < (m / 2) * m; e += 256) {
-        const int i = e / m, k = e % m;
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        const double2 ep = ph[i];
-        const double2 apk = A[p * m + k], aqk = A[q * m + k];
-        const double2 t1 = cmul(ep, aqk);
-        A[p * m + k] = make_double2(c * apk.x - s * t1.x, c * apk.y - s * t1.y);
-        A[q * m + k] = make_double2(s * apk.x + c * t1.x, s * apk.y + c * t1.y);
-      }
-      __syncthreads();
     }
   }
+  __syncthreads();
   if (tid < n) ev[tid] = A[tid * m + tid].x;
   __syncthreads();
   // occupations f(e) = 1/(1 + exp(beta e)) and eigenvalue range (of F, i.e. e + mu)
@@ -603,10 +591,10 @@ __global__ __launch_bounds__(256) void k_jacobi_g0(const EigItem* __restrict__ i
 }
 
 void launch_jacobi_g0(const void* items, int nitems, const Bases& b, const double* tau, int ntau, double beta,
-                      double mu, double* occ, double* erange, hipStream_t s) {
+                      double mu, double* occ, double* erange, void* vwork, hipStream_t s) {
   if (nitems)
     hipLaunchKernelGGL(k_jacobi_g0, dim3(nitems), dim3(256), 0, s, (const EigItem*)items, b, tau, ntau, beta, mu, occ,
-                       erange);
+                       erange, (double2*)vwork);
 }
 
 // sum of per-block occupations with star weights, and the global eigenvalue range

@@ -16,6 +16,8 @@ namespace {
 
 struct Range {
   int t0 = 0, nt = 0, r0 = 0, nr = 0;
+  double macs = 0;   // complex multiply-accumulates requested by the launch
+  double bytes = 0;  // algorithmic bytes moved (memory-bound launches)
 };
 
 struct GemmStage {
@@ -30,11 +32,16 @@ struct GemmStage {
   int max_slots = 0;
   double macs = 0;
 
-  void add(const GemmProblem& p) {
+  // algo_macs: the multiply-accumulates the algorithm needs when the problem computes more
+  // (e.g. zero off-diagonal blocks); by default the problem's own M N K T batch.
+  void add(const GemmProblem& p, double algo_macs = -1.0) {
     pending.push_back(int(probs.size()));
     probs.push_back(p);
-    macs += double(p.M) * p.N * p.K * double(p.T) * p.batch;
+    const double m = algo_macs >= 0 ? algo_macs : double(p.M) * p.N * p.K * double(p.T) * p.batch;
+    macs += m;
+    pending_macs += m;
   }
+  double pending_macs = 0;
   // Closes a launch: turns its problems into tiles; problems with a long outer loop are
   // split so that the launch has about `target` workgroups.
   void close(int target = 2048) {
@@ -46,6 +53,8 @@ struct GemmStage {
       const GemmProblem& p = probs[id];
       base += long(p.batch) * ((p.M + 31) / 32) * ((p.N + 31) / 32);
     }
+    r.macs = pending_macs;
+    pending_macs = 0;
     int slots = 0;
     for (int id : pending) {
       const GemmProblem& p = probs[id];
@@ -85,19 +94,39 @@ struct RowStage {
   std::vector<Range> launches;  // t0 = first segment, nt = count, r0 = max rows
   void* d = nullptr;
   int start = 0, maxr = 0;
-  void add(const RowSeg& s) {
+  double macs = 0, bytes = 0;
+  // m: complex MACs; the slab is read and written once: 32 bytes per complex element
+  void add(const RowSeg& s, double m, double elems) {
     segs.push_back(s);
     maxr = std::max(maxr, s.nrows);
+    macs += m;
+    bytes += 32.0 * elems;
   }
   void close() {
     Range r;
     r.t0 = start;
     r.nt = int(segs.size()) - start;
     r.r0 = maxr;
+    r.macs = macs;
+    r.bytes = bytes;
     launches.push_back(r);
     start = int(segs.size());
     maxr = 0;
+    macs = 0;
+    bytes = 0;
   }
+};
+
+// Live per-class timing with HIP events on the launch stream (enabled on request).
+enum ProfClass { PC_P0 = 0, PC_SA, PC_SC, PC_RIGHT, PC_LEFT, PC_XFORM, PC_INV, PC_OTHER, PC_N };
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> recs;
+  double macs[PC_N] = {};
+  double bytes[PC_N] = {};
 };
 
 template <class T>
@@ -139,17 +168,20 @@ struct DevState {
   double* trace = nullptr;
   double* occ = nullptr;
   double* erange = nullptr;
+  void* vwork = nullptr;     // Jacobi eigenvectors, JAC_N^2 complex per g0 item
   int* status = nullptr;
   int tau_chunk = 1;
   // stages
   GemmStage p0_gemm, s_gemmA, s_gemmC, scr_fwd, scr_bwd, dys_fwd, dys_bwd, tb_1[3], tb_2[3], fb_1[3], fb_2[3];
   GemmStage lv1, lv2, lv3;
   RowStage p0_right, p0_left, s_right;
-  ListStage<CopySeg> p0_mirror, scr_herm, dys_herm;
+  ListStage<CopySeg> p0_mirror, scr_herm, dys_herm, s_pack;
+  void* SCR = nullptr;      // full nao x nao self-energy products of one tau chunk
   ListStage<InvItem> scr_inv, dys_inv, mu_inv;
   ListStage<MuItem> mu_items;
   ListStage<EigItem> g0_items;
   std::vector<void*> allocs;
+  Prof prof;
 };
 
 namespace {
@@ -316,9 +348,13 @@ int device_init(Ctx& c, void* stream) {
   d.ws_elems = size_t(ws);
   if ((st = dalloc(c, d, &d.W1, d.ws_elems * 16))) return st;
   if ((st = dalloc(c, d, &d.W2, d.ws_elems * 16))) return st;
+  if ((st = dalloc(c, d, &d.SCR, size_t(J) * no * no * 16))) return st;
 
   // ---------------- polarization (eq. P0, Alg. 3) ----------------
   Mesh mesh{c.n};
+  std::vector<double> sumsq_ao(nib, 0.0);  // sum of squared orbital block sizes
+  for (int i = 0; i < nib; ++i)
+    for (int sz : c.bao[i].size) sumsq_ao[i] += double(sz) * sz;
   const double pscale = -c.prm.spin / nk;
   for (int i = 0; i < nib; ++i) {
     const int q0 = c.ibz[i];
@@ -334,11 +370,11 @@ int device_init(Ctx& c, void* stream) {
           RowSeg r{};
           r.inbuf = B_VP; r.outbuf = B_W1; r.gbuf = B_G; r.blk = d.bt_ao[ikq];
           r.in_off = vp; r.out_off = wo; r.g_off = c.g_off[ikq] + i64(j) * c.bao[ikq].packed; r.nrows = na * no;
-          d.p0_right.add(r);
+          d.p0_right.add(r, double(na) * no * sumsq_ao[ikq], double(na) * no * no);
           RowSeg l{};
           l.inbuf = B_VP; l.outbuf = B_W2; l.gbuf = B_G; l.blk = d.bt_ao[ik];
           l.in_off = vp; l.out_off = wo; l.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed; l.nrows = na * no;
-          d.p0_left.add(l);
+          d.p0_left.add(l, double(na) * no * sumsq_ao[ik], double(na) * no * no);
         }
         for (size_t sg = 0; sg < BA.size.size(); ++sg) {
           const int m = BA.size[sg], off = BA.off[sg];
@@ -381,18 +417,24 @@ int device_init(Ctx& c, void* stream) {
           RowSeg r{};
           r.inbuf = B_W1; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
           r.in_off = wo; r.out_off = wo; r.g_off = c.g_off[ik] + i64(j) * c.bao[ik].packed; r.nrows = na * no;
-          d.s_right.add(r);
+          d.s_right.add(r, double(na) * no * sumsq_ao[ik], double(na) * no * no);
         }
+        // All orbital blocks of k0 in one product (one tile per 32 x 32 of nao x nao), then the
+        // diagonal blocks are gathered into Sigma_blk; only the block work is counted.
+        d.s_gemmC.add(gp(no, no, no, nk * na, 1, B_W2, i64(jj) * slab, no, i64(no) * no, 0, OP_N, B_VS,
+                         i64(i) * nk * na * no * no, no, i64(no) * no, 0, OP_H, B_SCR, i64(jj) * no * no, no, 0,
+                         -1.0 / nk),
+                      sumsq_ao[i] * no * double(nk) * na);
         for (size_t rb = 0; rb < BO.size.size(); ++rb) {
           const int n = BO.size[rb], off = BO.off[rb];
-          d.s_gemmC.add(gp(n, n, no, nk * na, 1, B_W2, i64(jj) * slab + i64(off) * no, no, i64(no) * no, 0, OP_N, B_VS,
-                           i64(i) * nk * na * no * no + i64(off) * no, no, i64(no) * no, 0, OP_H, B_OUT,
-                           c.g_off[i] + i64(j) * BO.packed + BO.poff[rb], n, 0, -1.0 / nk));
+          d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(jj) * no * no + i64(off) * no + off,
+                                    c.g_off[i] + i64(j) * BO.packed + BO.poff[rb], no});
         }
       }
       d.s_gemmA.close();
       d.s_right.close();
       d.s_gemmC.close();
+      d.s_pack.close();
     }
   }
 
@@ -500,7 +542,7 @@ int device_init(Ctx& c, void* stream) {
       if ((st = upload_stage(c, d, *g, s))) return st;
   for (RowStage* r : {&d.p0_right, &d.p0_left, &d.s_right})
     if ((st = upload(c, d, r->segs, &r->d, s))) return st;
-  for (auto* l : {&d.p0_mirror, &d.scr_herm, &d.dys_herm})
+  for (auto* l : {&d.p0_mirror, &d.scr_herm, &d.dys_herm, &d.s_pack})
     if ((st = upload(c, d, l->items, &l->d, s))) return st;
   for (auto* l : {&d.scr_inv, &d.dys_inv, &d.mu_inv})
     if ((st = upload(c, d, l->items, &l->d, s))) return st;
@@ -520,6 +562,7 @@ int device_init(Ctx& c, void* stream) {
   d.occ = static_cast<double*>(t);
   if ((st = dalloc(c, d, &t, std::max<size_t>(1, d.g0_items.items.size()) * 2 * sizeof(double)))) return st;
   d.erange = static_cast<double*>(t);
+  if ((st = dalloc(c, d, &d.vwork, std::max<size_t>(1, d.g0_items.items.size()) * JAC_N * JAC_N * 16))) return st;
   if ((st = dalloc(c, d, &t, sizeof(int)))) return st;
   d.status = static_cast<int*>(t);
   HIPCHECK(hipMemsetAsync(d.status, 0, sizeof(int), s));
@@ -532,6 +575,7 @@ int device_init(Ctx& c, void* stream) {
 void device_free(Ctx& c) {
   DevState* d = static_cast<DevState*>(c.dev_state);
   if (!d) return;
+  for (hipEvent_t e : d->prof.pool) hipEventDestroy(e);
   for (void* p : d->allocs) hipFree(p);
   delete d;
   c.dev_state = nullptr;
@@ -540,6 +584,31 @@ void device_free(Ctx& c) {
 }
 
 namespace {
+
+template <class F>
+void timed(DevState& d, hipStream_t s, int cls, double macs, F f, double bytes = 0) {
+  Prof& p = d.prof;
+  if (!p.on) {
+    f();
+    return;
+  }
+  while (p.pool.size() < p.used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      f();
+      return;
+    }
+    p.pool.push_back(e);
+  }
+  const size_t i = p.used;
+  p.used += 2;
+  hipEventRecord(p.pool[i], s);
+  f();
+  hipEventRecord(p.pool[i + 1], s);
+  p.recs.push_back({cls, i});
+  p.macs[cls] += macs;
+  p.bytes[cls] += bytes;
+}
 
 Bases bases_of(DevState& d) {
   Bases b{};
@@ -550,6 +619,7 @@ Bases bases_of(DevState& d) {
   b.p[B_TR] = d.TR;
   b.p[B_U] = d.U;
   b.p[B_WT] = d.WT;
+  b.p[B_SCR] = d.SCR;
   return b;
 }
 
@@ -730,12 +800,12 @@ int device_g0(Ctx& c, const void* F, double mu, void* G, double* nfree, void* st
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevState& d = *static_cast<DevState*>(c.dev_state);
   for (const EigItem& e : d.g0_items.items)
-    if (e.n > 64) return c.err = "orbital block larger than 64 in g0", GWSYM_ESHAPE;
+    if (e.n > JAC_N) return c.err = "orbital block larger than 60 in g0", GWSYM_ESHAPE;
   Bases b = bases_of(d);
   b.p[B_F] = const_cast<void*>(F);
   b.p[B_OUT] = G;
   const int n = int(d.g0_items.items.size());
-  launch_jacobi_g0(d.g0_items.d, n, b, d.tau, c.ntau, c.prm.beta, mu, d.occ, d.erange, s);
+  launch_jacobi_g0(d.g0_items.d, n, b, d.tau, c.ntau, c.prm.beta, mu, d.occ, d.erange, d.vwork, s);
   launch_g0_reduce(d.occ, d.wts, d.erange, n, c.prm.spin / c.nk, nfree ? nfree : d.scratch + 5, d.scratch + 3, s);
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
@@ -752,14 +822,15 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
   for (size_t l = 0; l < d.p0_gemm.launches.size(); ++l) {
     const Range& rr = d.p0_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.p0_right.d) + rr.t0, rr.nt, rr.r0};
-    launch_rowblock_right(R, b, d.btab, c.nao, s);
+    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s); }, rr.bytes);
     const Range& rl = d.p0_left.launches[l];
     RowSegList L{static_cast<RowSeg*>(d.p0_left.d) + rl.t0, rl.nt, rl.r0};
-    launch_rowblock_left(L, b, d.btab, c.nao, s);
-    launch_brgemm(plan_of(d.p0_gemm, d.p0_gemm.launches[l]), b, d.partials, s);
+    timed(d, s, PC_LEFT, rl.macs, [&] { launch_rowblock_left(L, b, d.btab, c.nao, s); }, rl.bytes);
+    const Range& rg = d.p0_gemm.launches[l];
+    timed(d, s, PC_P0, rg.macs, [&] { launch_brgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1); });
   }
   const Range& m = d.p0_mirror.launches[0];
-  launch_copy(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s);
+  timed(d, s, PC_OTHER, 0, [&] { launch_copy(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s); });
   HIPCHECK(hipGetLastError());
   c.last_macs[0] = d.p0_gemm.macs;
   return GWSYM_OK;
@@ -775,11 +846,15 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
   b.p[B_P] = const_cast<void*>(P);
   b.p[B_OUT] = S;
   for (size_t l = 0; l < d.s_gemmA.launches.size(); ++l) {
-    launch_brgemm(plan_of(d.s_gemmA, d.s_gemmA.launches[l]), b, d.partials, s);
+    const Range& ra = d.s_gemmA.launches[l];
+    timed(d, s, PC_SA, ra.macs, [&] { launch_brgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2); });
     const Range& rr = d.s_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
-    launch_rowblock_right(R, b, d.btab, c.nao, s);
-    launch_brgemm(plan_of(d.s_gemmC, d.s_gemmC.launches[l]), b, d.partials, s);
+    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s); }, rr.bytes);
+    const Range& rc = d.s_gemmC.launches[l];
+    timed(d, s, PC_SC, rc.macs, [&] { launch_brgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3); });
+    const Range& rp = d.s_pack.launches[l];
+    timed(d, s, PC_OTHER, 0, [&] { launch_pack(static_cast<CopySeg*>(d.s_pack.d) + rp.t0, rp.nt, b, s); });
   }
   HIPCHECK(hipGetLastError());
   c.last_macs[1] = d.s_gemmA.macs + d.s_gemmC.macs;
@@ -796,10 +871,13 @@ int device_screened(Ctx& c, const void* P0, void* P, void* stream) {
   Bases b = bases_of(d);
   b.p[B_IN] = const_cast<void*>(P0);
   b.p[B_OUT] = P;
-  launch_brgemm(plan_of(d.scr_fwd, d.scr_fwd.launches[0]), b, d.partials, s);
-  launch_inverse(d.scr_inv.d, int(d.scr_inv.items.size()), b, INV_P, nullptr, nullptr, d.status, s);
-  launch_brgemm(plan_of(d.scr_bwd, d.scr_bwd.launches[0]), b, d.partials, s);
-  launch_herm(d.scr_herm.d, int(d.scr_herm.items.size()), b, s);
+  timed(d, s, PC_XFORM, d.scr_fwd.launches[0].macs,
+        [&] { launch_brgemm(plan_of(d.scr_fwd, d.scr_fwd.launches[0]), b, d.partials, s); });
+  timed(d, s, PC_INV, 0,
+        [&] { launch_inverse(d.scr_inv.d, int(d.scr_inv.items.size()), b, INV_P, nullptr, nullptr, d.status, s); });
+  timed(d, s, PC_XFORM, d.scr_bwd.launches[0].macs,
+        [&] { launch_brgemm(plan_of(d.scr_bwd, d.scr_bwd.launches[0]), b, d.partials, s); });
+  timed(d, s, PC_OTHER, 0, [&] { launch_herm(d.scr_herm.d, int(d.scr_herm.items.size()), b, s); });
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
 }
@@ -813,10 +891,13 @@ int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G
   b.p[B_IN] = const_cast<void*>(S);
   b.p[B_F] = const_cast<void*>(F);
   b.p[B_OUT] = G;
-  launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s);
-  launch_inverse(d.dys_inv.d, int(d.dys_inv.items.size()), b, INV_G, mu, nullptr, d.status, s);
-  launch_brgemm(plan_of(d.dys_bwd, d.dys_bwd.launches[0]), b, d.partials, s);
-  launch_herm(d.dys_herm.d, int(d.dys_herm.items.size()), b, s);
+  timed(d, s, PC_XFORM, d.dys_fwd.launches[0].macs,
+        [&] { launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s); });
+  timed(d, s, PC_INV, 0,
+        [&] { launch_inverse(d.dys_inv.d, int(d.dys_inv.items.size()), b, INV_G, mu, nullptr, d.status, s); });
+  timed(d, s, PC_XFORM, d.dys_bwd.launches[0].macs,
+        [&] { launch_brgemm(plan_of(d.dys_bwd, d.dys_bwd.launches[0]), b, d.partials, s); });
+  timed(d, s, PC_OTHER, 0, [&] { launch_herm(d.dys_herm.d, int(d.dys_herm.items.size()), b, s); });
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
 }
@@ -829,15 +910,47 @@ int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double*
   Bases b = bases_of(d);
   b.p[B_IN] = const_cast<void*>(S);
   b.p[B_F] = const_cast<void*>(F);
-  launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s);
+  timed(d, s, PC_XFORM, d.dys_fwd.launches[0].macs,
+        [&] { launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s); });
   const void* Blast = static_cast<const cplx*>(d.TR) + 2 * i64(c.nw) * c.ntau + i64(c.ntau - 1) * c.nw;
   launch_mu_init(d.scratch + 3, d.scratch, mu, s);
   const int n = int(d.mu_inv.items.size());
   for (int it = 0; it < 64; ++it) {
-    launch_inverse(d.mu_inv.d, n, b, INV_TRACE, mu, d.trace, d.status, s);
-    launch_mu_update(d.mu_items.d, n, d.trace, Blast, c.prm.spin / c.nk, ntarget, d.scratch, mu, s);
+    timed(d, s, PC_INV, 0, [&] { launch_inverse(d.mu_inv.d, n, b, INV_TRACE, mu, d.trace, d.status, s); });
+    timed(d, s, PC_OTHER, 0, [&] {
+      launch_mu_update(d.mu_items.d, n, d.trace, Blast, c.prm.spin / c.nk, ntarget, d.scratch, mu, s);
+    });
   }
   HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+int device_profile(Ctx& c, int enable) {
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  d.prof.on = enable != 0;
+  return GWSYM_OK;
+}
+
+int device_profile_read(Ctx& c, double* ms, int64_t* launches, double* macs, double* bytes) {
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  Prof& p = d.prof;
+  for (int k = 0; k < PC_N; ++k) {
+    ms[k] = 0;
+    launches[k] = 0;
+    macs[k] = p.macs[k];
+    bytes[k] = p.bytes[k];
+    p.bytes[k] = 0;
+    p.macs[k] = 0;
+  }
+  for (const auto& r : p.recs) {
+    HIPCHECK(hipEventSynchronize(p.pool[r.second + 1]));
+    float t = 0;
+    HIPCHECK(hipEventElapsedTime(&t, p.pool[r.second], p.pool[r.second + 1]));
+    ms[r.first] += t;
+    launches[r.first] += 1;
+  }
+  p.recs.clear();
+  p.used = 0;
   return GWSYM_OK;
 }
 

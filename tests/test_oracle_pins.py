@@ -357,3 +357,19 @@ def test_planted_mistakes_are_caught(func, old, new):
     # the brute-force pins above compare `good` with the printed index sums;
     # a planted mistake must move the result far outside their tolerance
     assert np.abs(got - good).max() > 1e-6 * np.abs(good).max()
+
+
+def test_single_output_units_match_full_contractions():
+    # the one-output forms used for sampled checks and CPU timing equal the full ones
+    n, s = 3, 2.0
+    V, G, P = _tiny_inputs(seed=12, nao=3, naux=4, nt=6)
+    add, sub = add_k(n), _sub_table(n)
+    P0 = oracle.polarization(G, V, add, s)
+    S = oracle.self_energy(G, V, P, sub)
+    nk = n ** 3
+    for q, j in [(0, 0), (5, 2), (13, 5)]:
+        Vq = np.stack([V[k, add[k, q]] for k in range(nk)])
+        assert np.abs(oracle.polarization_unit(G, Vq, add, q, j, s) - P0[q, j]).max() < 1e-13
+    for k, j in [(0, 1), (7, 3)]:
+        Vk = np.stack([V[k, sub[k, q]] for q in range(nk)])
+        assert np.abs(oracle.self_energy_unit(G, Vk, P[:, j], sub, k, j) - S[k, j]).max() < 1e-13
