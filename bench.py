@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--tau-chunk", type=int, default=0)
     ap.add_argument("--no-full", action="store_true", help="skip the full-matrix FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="before the timed steps, copy a buffer of this many MiB once (a plain copy kernel "
+                         "of known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the distributed path is a design "
@@ -173,6 +176,15 @@ def main():
     V_all = inp.three_index_full()
     torch.cuda.synchronize()
     log(f"[bench] inputs generated in {time.perf_counter() - t:.1f} s")
+
+    if args.copy_calib_mb > 0:
+        n = args.copy_calib_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calib_mb} MiB done")
+        del a, b
 
     # ---- block-grouped, irreducible wedge, FP64 ----
     t = time.perf_counter()

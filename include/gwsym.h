@@ -202,6 +202,16 @@ int gwsym_find_mu(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, doub
 int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, const double* mu,
                   void* G_blk, void* stream);
 
+/* One GW iteration in the order of Alg. 2: polarization(G) -> screened interaction ->
+ * self-energy(G, P) -> (find_mu when n_target > 0, else mu is read as given) -> dyson_G,
+ * which overwrites G_blk.  All buffers are device memory of the layouts above; mu is one
+ * device double.  use_graph != 0: the work is captured once into a HIP graph on `stream`
+ * (a created stream, not the null stream) and that graph is replayed by later calls with the
+ * same arguments; changing any pointer or n_target captures a new graph.  The capture
+ * contains kernels only (no memset, no allocation). */
+int gwsym_iteration(gwsym_ctx* ctx, const void* F_blk, void* G_blk, void* P0_blk, void* P_blk, void* Sigma_blk,
+                    double* mu, double n_target, int use_graph, void* stream);
+
 /* Algorithm and executed complex multiply-accumulate counts of the last
  * polarization / self_energy call, for throughput accounting (host).
  * out[0] = P0 MACs, out[1] = Sigma MACs (as executed, padding excluded). */

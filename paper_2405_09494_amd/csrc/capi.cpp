@@ -239,6 +239,15 @@ int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, cons
   return device_dyson(ctx->c, F_blk, Sigma_blk, mu, G_blk, stream);
 }
 
+int gwsym_iteration(gwsym_ctx* ctx, const void* F_blk, void* G_blk, void* P0_blk, void* P_blk, void* Sigma_blk,
+                    double* mu, double n_target, int use_graph, void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");
+  NEED(F_blk && G_blk && P0_blk && P_blk && Sigma_blk && mu, GWSYM_EINVAL, "NULL buffer");
+  NEED(!(use_graph && stream == nullptr), GWSYM_EINVAL, "graph capture needs a created stream");
+  return device_iteration(ctx->c, F_blk, G_blk, P0_blk, P_blk, Sigma_blk, mu, n_target, use_graph, stream);
+}
+
 int gwsym_profile(gwsym_ctx* ctx, int enable) {
   if (!ctx) return GWSYM_EINVAL;
   NEED(ctx->c.dev, GWSYM_ESTATE, "gwsym_device_init must come first");

@@ -63,7 +63,13 @@ struct GemmProblem {
   i64 coff, ldc, sCb;
   double alpha_re, alpha_im;
   int beta;                 // 0: overwrite, 1: accumulate
-  int pad_;
+  // Optional right multiply of A by a block-diagonal K x K matrix that depends on the
+  // outer index: opA(A_t) <- opA(A_t) * G_(t / gdiv).  Entry t / gdiv of the int64 table at
+  // bases[B_GT] + gtab holds (offset of the packed blocks in bases[gbuf], offset of their
+  // block list in the block table bases[B_BT]).  Requires K <= 32 and opA = N.
+  int gfuse;
+  int gbuf, gdiv, pad_;
+  i64 gtab;
 };
 
 // A 32 x 32 output tile (or ntn consecutive column tiles) of one problem over the outer
@@ -91,7 +97,7 @@ struct GemmPlan {
 
 // Buffer ids used in GemmProblem::abuf/bbuf/cbuf; the launch passes the base pointers.
 enum Buf : int {
-  B_VP = 0, B_VS, B_G, B_P, B_W1, B_W2, B_OUT, B_TR, B_IN, B_U, B_WT, B_F, B_SCR, NBUF
+  B_VP = 0, B_VS, B_G, B_P, B_W1, B_W2, B_OUT, B_TR, B_IN, B_U, B_WT, B_F, B_SCR, B_GT, B_BT, NBUF
 };
 
 struct Ctx {
@@ -156,6 +162,8 @@ int device_screened(Ctx& c, const void* P0, void* P, void* stream);
 int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stream);
 int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double* mu, void* stream);
 int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream);
+int device_iteration(Ctx& c, const void* F, void* G, void* P0, void* P, void* S, double* mu, double ntarget,
+                     int use_graph, void* stream);
 int device_profile(Ctx& c, int enable);
 int device_profile_read(Ctx& c, double* ms, int64_t* launches, double* macs, double* bytes);
 

@@ -59,9 +59,13 @@ struct EigItem {
 
 // tag: 0 generic, 1 polarization contraction, 2 self-energy auxiliary contraction,
 // 3 self-energy orbital contraction (separate kernel names in profiles)
-void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag = 0);
+// fp32: operands are float2 and the FP32 MFMA is used; f32mask bit b: buffer b holds float2
+void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag = 0,
+                   bool fp32 = false, unsigned f32mask = 0);
+void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s);
 void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s);
-void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s);
+void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s,
+                          bool fp32 = false);
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s);

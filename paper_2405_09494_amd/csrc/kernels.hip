@@ -12,6 +12,7 @@
 //  k_herm, k_copy packed-block helpers; k_mu_* the chemical-potential bisection.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernel_api.hpp"
@@ -38,35 +39,88 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 
 constexpr int TM = 32, TN = 32, BK = 32;
 
-__device__ __forceinline__ double2 load_op(const double2* __restrict__ p, int op, int64_t r, int64_t c,
-                                           int64_t ld) {
+// Element type of the operands: FP64 (double2, FP64 MFMA) or FP32 (float2, FP32 MFMA).
+template <typename R> struct Cx;
+template <> struct Cx<double> { using V2 = double2; using A4 = d4; };
+template <> struct Cx<float> { using V2 = float2; using A4 = f4; };
+
+template <typename V2>
+__device__ __forceinline__ V2 load_op(const V2* __restrict__ p, int op, int64_t r, int64_t c, int64_t ld) {
   // element (r, c) of op(X): N -> X[r][c], T -> X[c][r], C -> conj X[r][c], H -> conj X[c][r]
-  const double2 v = (op & 1) ? p[c * ld + r] : p[r * ld + c];
-  return (op & 2) ? cconj(v) : v;
+  V2 v = (op & 1) ? p[c * ld + r] : p[r * ld + c];
+  if (op & 2) v.y = -v.y;
+  return v;
 }
 
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row held by register j of lane l in the 16 x 16 result (column l % 16): the FP64 MFMA
+// interleaves rows (l/16 + 4 j), the FP32 one keeps them consecutive (4 (l/16) + j).
+__device__ __forceinline__ int mrow(double, int lane, int j) { return (lane >> 4) + 4 * j; }
+__device__ __forceinline__ int mrow(float, int lane, int j) { return 4 * (lane >> 4) + j; }
+
 // TAG only separates the stages in profiles (P0, Sigma aux / orbital contractions, others).
-template <int TAG>
+// f32mask: bit b set when buffer b holds float2 (then C is stored as float2).
+template <typename R, int TAG>
 __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ probs,
                                                 const GemmTile* __restrict__ tiles, Bases bases,
-                                                double2* __restrict__ partials) {
-  __shared__ double As_re[BK][TM + 1], As_im[BK][TM + 1];
-  __shared__ double Bs_re[BK][TN + 1], Bs_im[BK][TN + 1];
+                                                double2* __restrict__ partials, unsigned f32mask) {
+  using V2 = typename Cx<R>::V2;
+  using A4 = typename Cx<R>::A4;
+  __shared__ R As_re[BK][TM + 1], As_im[BK][TM + 1];
+  __shared__ R Bs_re[BK][TN + 1], Bs_im[BK][TN + 1];
+  __shared__ R Gs_re[BK][BK + 1], Gs_im[BK][BK + 1];
+  __shared__ int gcol_off[BK], gcol_sz[BK];
   const GemmTile tl = tiles[blockIdx.x];
   const GemmProblem P = probs[tl.prob];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = tl.tm * TM;
-  const double2* Ab = reinterpret_cast<const double2*>(bases.p[P.abuf]) + P.aoff + int64_t(tl.batch) * P.sAb;
-  const double2* Bb = reinterpret_cast<const double2*>(bases.p[P.bbuf]) + P.boff + int64_t(tl.batch) * P.sBb;
+  const V2* Ab = reinterpret_cast<const V2*>(bases.p[P.abuf]) + P.aoff + int64_t(tl.batch) * P.sAb;
+  const V2* Bb = reinterpret_cast<const V2*>(bases.p[P.bbuf]) + P.boff + int64_t(tl.batch) * P.sBb;
   const bool a_kfast = (P.opA & 1) == 0;  // N, C: k is the contiguous index of A
   const bool b_nfast = (P.opB & 1) == 0;  // N, C: n is the contiguous index of B
+  int gcur = -1;
   for (int tn = tl.tn; tn < tl.tn + tl.ntn; ++tn) {
     const int n0 = tn * TN;
-    d4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    A4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
     for (int t = tl.t0; t < tl.t1; ++t) {
-      const double2* A = Ab + int64_t(t) * P.sAt;
-      const double2* B = Bb + int64_t(t) * P.sBt;
+      const V2* A = Ab + int64_t(t) * P.sAt;
+      const V2* B = Bb + int64_t(t) * P.sBt;
+      if (P.gfuse) {
+        // block-diagonal right factor of A for this outer index (uniform over the group)
+        const int gi = t / P.gdiv;
+        if (gi != gcur) {
+          gcur = gi;
+          const int64_t* gt = reinterpret_cast<const int64_t*>(bases.p[B_GT]) + P.gtab + 2 * int64_t(gi);
+          const V2* G = reinterpret_cast<const V2*>(bases.p[P.gbuf]) + gt[0];
+          const int* bt = reinterpret_cast<const int*>(bases.p[B_BT]) + gt[1];
+          __syncthreads();
+          for (int e = tid; e < BK * BK; e += 256) {
+            Gs_re[e / BK][e % BK] = 0.0;
+            Gs_im[e / BK][e % BK] = 0.0;
+          }
+          __syncthreads();
+          const int nb = bt[0];
+          for (int b = 0; b < nb; ++b) {
+            const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
+            for (int e = tid; e < sz * sz; e += 256) {
+              const V2 g = G[po + e];
+              Gs_re[off + e / sz][off + e % sz] = g.x;
+              Gs_im[off + e / sz][off + e % sz] = g.y;
+            }
+            for (int cc = tid; cc < sz; cc += 256) {
+              gcol_off[off + cc] = off;
+              gcol_sz[off + cc] = sz;
+            }
+          }
+          __syncthreads();
+        }
+      }
       for (int k0 = 0; k0 < P.K; k0 += BK) {
         const int kv = min(BK, P.K - k0);
         for (int idx = tid; idx < TM * BK; idx += 256) {
@@ -74,7 +128,7 @@ __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ 
           if (a_kfast) { mm = idx / BK; kk = idx % BK; }
           else { kk = idx / TM; mm = idx % TM; }
           const int m = m0 + mm, k = k0 + kk;
-          double2 v = make_double2(0.0, 0.0);
+          V2 v = {0, 0};
           if (m < P.M && kk < kv) v = load_op(A, P.opA, m, k, P.lda);
           As_re[kk][mm] = v.x;
           As_im[kk][mm] = v.y;
@@ -84,42 +138,75 @@ __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ 
           if (b_nfast) { kk = idx / TN; nn = idx % TN; }
           else { nn = idx / BK; kk = idx % BK; }
           const int n = n0 + nn, k = k0 + kk;
-          double2 v = make_double2(0.0, 0.0);
+          V2 v = {0, 0};
           if (n < P.N && kk < kv) v = load_op(B, P.opB, k, n, P.ldb);
           Bs_re[kk][nn] = v.x;
           Bs_im[kk][nn] = v.y;
         }
         __syncthreads();
+        if (P.gfuse) {
+          // A <- A G within each block of G (K = kv <= BK, a single chunk)
+          V2 res[TM * BK / 256];
+#pragma unroll
+          for (int q = 0; q < TM * BK / 256; ++q) {
+            const int idx = tid + 256 * q, mm = idx % TM, kc = idx / TM;
+            V2 s = {0, 0};
+            if (kc < kv) {
+              const int off = gcol_off[kc], sz = gcol_sz[kc];
+              for (int kk = off; kk < off + sz; ++kk) {
+                const R ar = As_re[kk][mm], ai = As_im[kk][mm], gr = Gs_re[kk][kc], gim = Gs_im[kk][kc];
+                s.x += ar * gr - ai * gim;
+                s.y += ar * gim + ai * gr;
+              }
+            }
+            res[q] = s;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < TM * BK / 256; ++q) {
+            const int idx = tid + 256 * q, mm = idx % TM, kc = idx / TM;
+            As_re[kc][mm] = res[q].x;
+            As_im[kc][mm] = res[q].y;
+          }
+          __syncthreads();
+        }
         const int r = wm * 16 + (lane & 15), cix = wn * 16 + (lane & 15), kq = lane >> 4;
         for (int kk = 0; kk < kv; kk += 4) {
-          const double are = As_re[kk + kq][r], aim = As_im[kk + kq][r];
-          const double bre = Bs_re[kk + kq][cix], bim = Bs_im[kk + kq][cix];
-          cre = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bre, cre, 0, 0, 0);
-          cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim, bim, cre, 0, 0, 0);
-          cim = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bim, cim, 0, 0, 0);
-          cim = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bre, cim, 0, 0, 0);
+          const R are = As_re[kk + kq][r], aim = As_im[kk + kq][r];
+          const R bre = Bs_re[kk + kq][cix], bim = Bs_im[kk + kq][cix];
+          cre = mfma16(are, bre, cre);
+          cre = mfma16(-aim, bim, cre);
+          cim = mfma16(are, bim, cim);
+          cim = mfma16(aim, bre, cim);
         }
         __syncthreads();
       }
     }
-    // FP64 16x16 MFMA result layout: register j of lane l holds row l/16 + 4 j, column l%16
     const int col = wn * 16 + (lane & 15);
     if (tl.slot >= 0) {
       double2* out = partials + int64_t(tl.slot) * TM * TN;
       for (int j = 0; j < 4; ++j) {
-        const int row = wm * 16 + (lane >> 4) + 4 * j;
-        out[row * TN + col] = make_double2(cre[j], cim[j]);
+        const int row = wm * 16 + mrow(R(0), lane, j);
+        out[row * TN + col] = make_double2(double(cre[j]), double(cim[j]));
       }
       continue;
     }
-    double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]) + P.coff + int64_t(tl.batch) * P.sCb;
     const double2 al = make_double2(P.alpha_re, P.alpha_im);
+    const bool cf32 = (f32mask >> P.cbuf) & 1u;
     for (int j = 0; j < 4; ++j) {
-      const int row = m0 + wm * 16 + (lane >> 4) + 4 * j, cc = n0 + col;
+      const int row = m0 + wm * 16 + mrow(R(0), lane, j), cc = n0 + col;
       if (row < P.M && cc < P.N) {
-        double2 v = cmul(al, make_double2(cre[j], cim[j]));
-        if (P.beta) v = cadd(v, C[int64_t(row) * P.ldc + cc]);
-        C[int64_t(row) * P.ldc + cc] = v;
+        double2 v = cmul(al, make_double2(double(cre[j]), double(cim[j])));
+        const int64_t at = P.coff + int64_t(tl.batch) * P.sCb + int64_t(row) * P.ldc + cc;
+        if (cf32) {
+          float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
+          if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
+          C[at] = make_float2(float(v.x), float(v.y));
+        } else {
+          double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]);
+          if (P.beta) v = cadd(v, C[at]);
+          C[at] = v;
+        }
       }
     }
   }
@@ -127,10 +214,10 @@ __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ probs,
                                                 const GemmReduce* __restrict__ reds, Bases bases,
-                                                const double2* __restrict__ partials) {
+                                                const double2* __restrict__ partials, unsigned f32mask) {
   const GemmReduce rd = reds[blockIdx.x];
   const GemmProblem P = probs[rd.prob];
-  double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]) + P.coff + int64_t(rd.batch) * P.sCb;
+  const bool cf32 = (f32mask >> P.cbuf) & 1u;
   const double2 al = make_double2(P.alpha_re, P.alpha_im);
   for (int e = threadIdx.x; e < TM * TN; e += 256) {
     const int row = rd.tm * TM + e / TN, cc = rd.tn * TN + e % TN;
@@ -138,26 +225,54 @@ __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ 
     double2 s = make_double2(0.0, 0.0);
     for (int q = 0; q < rd.nslot; ++q) s = cadd(s, partials[int64_t(rd.slot0 + q) * TM * TN + e]);
     double2 v = cmul(al, s);
-    if (P.beta) v = cadd(v, C[int64_t(row) * P.ldc + cc]);
-    C[int64_t(row) * P.ldc + cc] = v;
+    const int64_t at = P.coff + int64_t(rd.batch) * P.sCb + int64_t(row) * P.ldc + cc;
+    if (cf32) {
+      float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
+      if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
+      C[at] = make_float2(float(v.x), float(v.y));
+    } else {
+      double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]);
+      if (P.beta) v = cadd(v, C[at]);
+      C[at] = v;
+    }
   }
 }
 
-void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag) {
+template <typename R>
+void launch_brgemm_t(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, unsigned mask) {
+  const dim3 g(p.ntiles), t(256);
+  const GemmProblem* pr = (const GemmProblem*)p.probs;
+  const GemmTile* tl = (const GemmTile*)p.tiles;
+  double2* pa = (double2*)partials;
+  switch (tag) {
+    case 1: hipLaunchKernelGGL((k_brgemm<R, 1>), g, t, 0, s, pr, tl, b, pa, mask); break;
+    case 2: hipLaunchKernelGGL((k_brgemm<R, 2>), g, t, 0, s, pr, tl, b, pa, mask); break;
+    case 3: hipLaunchKernelGGL((k_brgemm<R, 3>), g, t, 0, s, pr, tl, b, pa, mask); break;
+    default: hipLaunchKernelGGL((k_brgemm<R, 0>), g, t, 0, s, pr, tl, b, pa, mask); break;
+  }
+}
+
+void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, bool fp32,
+                   unsigned f32mask) {
   if (p.ntiles > 0) {
-    const dim3 g(p.ntiles), t(256);
-    const GemmProblem* pr = (const GemmProblem*)p.probs;
-    const GemmTile* tl = (const GemmTile*)p.tiles;
-    switch (tag) {
-      case 1: hipLaunchKernelGGL(k_brgemm<1>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
-      case 2: hipLaunchKernelGGL(k_brgemm<2>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
-      case 3: hipLaunchKernelGGL(k_brgemm<3>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
-      default: hipLaunchKernelGGL(k_brgemm<0>, g, t, 0, s, pr, tl, b, (double2*)partials); break;
-    }
+    if (fp32) launch_brgemm_t<float>(p, b, partials, s, tag, f32mask);
+    else launch_brgemm_t<double>(p, b, partials, s, tag, f32mask);
   }
   if (p.nreds > 0)
     hipLaunchKernelGGL(k_reduce, dim3(p.nreds), dim3(256), 0, s, (const GemmProblem*)p.probs,
-                       (const GemmReduce*)p.reds, b, (const double2*)partials);
+                       (const GemmReduce*)p.reds, b, (const double2*)partials, f32mask);
+}
+
+// FP64 -> FP32 copy of n complex numbers
+__global__ void k_to_f32(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+    out[e] = make_float2(float(in[e].x), float(in[e].y));
+}
+
+void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned(blocks)), dim3(256), 0, s, (const double2*)in, (float2*)out, n);
 }
 
 // ----------------------------------------------------------------------------
@@ -201,22 +316,24 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
 
 constexpr int CB_COLS = 64;
 
+template <typename V2>
 __global__ __launch_bounds__(256) void k_rowblock_left(const RowSeg* __restrict__ segs, Bases bases,
                                                        const int* __restrict__ btab, int nb_rows) {
-  extern __shared__ double2 lds[];
+  extern __shared__ double2 lds_raw[];
+  V2* tile = reinterpret_cast<V2*>(lds_raw);  // nb_rows x CB_COLS
   const RowSeg sg = segs[blockIdx.y];
   const int c0 = blockIdx.x * CB_COLS;
   const int ncols = sg.nrows;  // for left segments nrows holds the slab width
   if (c0 >= ncols) return;
   const int nc = min(CB_COLS, ncols - c0);
-  const double2* in = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
-  double2* out = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
-  const double2* G = reinterpret_cast<const double2*>(bases.p[sg.gbuf]) + sg.g_off;
+  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
+  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
+  const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
   const int* bt = btab + sg.blk;
-  double2* tile = lds;  // nb_rows x CB_COLS
   for (int e = threadIdx.x; e < nb_rows * CB_COLS; e += 256) {
     const int r = e / CB_COLS, c = e % CB_COLS;
-    tile[e] = c < nc ? in[int64_t(r) * ncols + c] : make_double2(0.0, 0.0);
+    V2 z = {0, 0};
+    tile[e] = c < nc ? in[int64_t(r) * ncols + c] : z;
   }
   __syncthreads();
   const int nblk = bt[0];
@@ -227,9 +344,13 @@ __global__ __launch_bounds__(256) void k_rowblock_left(const RowSeg* __restrict_
     while (b + 1 < nblk && rp >= bt[1 + 3 * (b + 1)]) ++b;
     const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
     const int rr = rp - off;
-    double2 s = make_double2(0.0, 0.0);
+    V2 s = {0, 0};
     // (G^H)[rr][k] = conj(G[k][rr])
-    for (int k = 0; k < sz; ++k) s = cadd(s, cmul(cconj(G[po + k * sz + rr]), tile[(off + k) * CB_COLS + c]));
+    for (int k = 0; k < sz; ++k) {
+      const V2 g = G[po + k * sz + rr], x = tile[(off + k) * CB_COLS + c];
+      s.x += g.x * x.x + g.y * x.y;
+      s.y += g.x * x.y - g.y * x.x;
+    }
     out[int64_t(rp) * ncols + c] = s;
   }
 }
@@ -241,11 +362,16 @@ void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab,
                      (const RowSeg*)l.segs, b, btab, ncol);
 }
 
-void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s) {
+void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s,
+                          bool fp32) {
   if (l.nseg == 0) return;
-  const size_t lds = size_t(nb_rows) * CB_COLS * sizeof(double2);
-  hipLaunchKernelGGL(k_rowblock_left, dim3((l.maxrows + CB_COLS - 1) / CB_COLS, l.nseg), dim3(256), lds, s,
-                     (const RowSeg*)l.segs, b, btab, nb_rows);
+  const dim3 g((l.maxrows + CB_COLS - 1) / CB_COLS, l.nseg);
+  if (fp32)
+    hipLaunchKernelGGL(k_rowblock_left<float2>, g, dim3(256), size_t(nb_rows) * CB_COLS * sizeof(float2), s,
+                       (const RowSeg*)l.segs, b, btab, nb_rows);
+  else
+    hipLaunchKernelGGL(k_rowblock_left<double2>, g, dim3(256), size_t(nb_rows) * CB_COLS * sizeof(double2), s,
+                       (const RowSeg*)l.segs, b, btab, nb_rows);
 }
 
 // ----------------------------------------------------------------------------

@@ -157,6 +157,10 @@ struct DevState {
   // V
   void* VP = nullptr;
   void* VS = nullptr;
+  void* VP32 = nullptr;     // FP32 copies for the FP32 contraction mode
+  void* VS32 = nullptr;
+  void* G32 = nullptr;
+  void* P32 = nullptr;
   void* WT = nullptr;       // per-pair rotation matrices for the polarization copy of V
   // workspaces
   void* W1 = nullptr;
@@ -176,12 +180,16 @@ struct DevState {
   GemmStage lv1, lv2, lv3;
   RowStage p0_right, p0_left, s_right;
   ListStage<CopySeg> p0_mirror, scr_herm, dys_herm, s_pack;
+  void* gtab = nullptr;     // (G offset, block-table offset) per outer group of fused GEMMs
   void* SCR = nullptr;      // full nao x nao self-energy products of one tau chunk
   ListStage<InvItem> scr_inv, dys_inv, mu_inv;
   ListStage<MuItem> mu_items;
   ListStage<EigItem> g0_items;
   std::vector<void*> allocs;
   Prof prof;
+  hipGraphExec_t graph_exec = nullptr;   // captured iteration and the arguments it was captured with
+  std::vector<const void*> graph_key;
+  double graph_ntarget = 0;
 };
 
 namespace {
@@ -356,31 +364,66 @@ int device_init(Ctx& c, void* stream) {
   for (int i = 0; i < nib; ++i)
     for (int sz : c.bao[i].size) sumsq_ao[i] += double(sz) * sz;
   const double pscale = -c.prm.spin / nk;
+  // With nao <= 32 the right multiply by G^{k+q}(tau) is done on the A tiles inside the
+  // grouped GEMM (no intermediate); otherwise by the row-block kernel into W1.
+  const bool fuse = no <= 32;
+  if (c.prm.precision == GWSYM_FP32 && !fuse) {
+    c.err = "FP32 contractions need nao <= 32";
+    return GWSYM_ESHAPE;
+  }
+  std::vector<i64> gtab;
+  auto add_gtab = [&](const std::vector<int>& ks, int j) {
+    const i64 at = i64(gtab.size());
+    for (int kk : ks) {
+      const int ik = c.rep[kk];
+      gtab.push_back(c.g_off[ik] + i64(j) * c.bao[ik].packed);
+      gtab.push_back(d.bt_ao[ik]);
+    }
+    return at;
+  };
   for (int i = 0; i < nib; ++i) {
     const int q0 = c.ibz[i];
     const Blocks& BA = c.baux[i];
+    std::vector<int> kq(nk);
+    double fused_macs = 0;
+    for (int k = 0; k < nk; ++k) {
+      kq[k] = mesh.add(k, q0);
+      fused_macs += double(no) * sumsq_ao[c.rep[kq[k]]];
+    }
     for (int j0 = 0; j0 < nthalf; j0 += J) {
       const int j1 = std::min(nthalf, j0 + J);
       for (int j = j0; j < j1; ++j) {
         const int jj = j - j0;
         for (int k = 0; k < nk; ++k) {
-          const int ik = c.rep[k], ikq = c.rep[mesh.add(k, q0)];
+          const int ik = c.rep[k], ikq = c.rep[kq[k]];
           const i64 vp = (i64(i) * nk + k) * na * no * no;
           const i64 wo = (i64(jj) * nk + k) * na * no * no;
-          RowSeg r{};
-          r.inbuf = B_VP; r.outbuf = B_W1; r.gbuf = B_G; r.blk = d.bt_ao[ikq];
-          r.in_off = vp; r.out_off = wo; r.g_off = c.g_off[ikq] + i64(j) * c.bao[ikq].packed; r.nrows = na * no;
-          d.p0_right.add(r, double(na) * no * sumsq_ao[ikq], double(na) * no * no);
+          if (!fuse) {
+            RowSeg r{};
+            r.inbuf = B_VP; r.outbuf = B_W1; r.gbuf = B_G; r.blk = d.bt_ao[ikq];
+            r.in_off = vp; r.out_off = wo; r.g_off = c.g_off[ikq] + i64(j) * c.bao[ikq].packed; r.nrows = na * no;
+            d.p0_right.add(r, double(na) * no * sumsq_ao[ikq], double(na) * no * no);
+          }
           RowSeg l{};
           l.inbuf = B_VP; l.outbuf = B_W2; l.gbuf = B_G; l.blk = d.bt_ao[ik];
           l.in_off = vp; l.out_off = wo; l.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed; l.nrows = na * no;
           d.p0_left.add(l, double(na) * no * sumsq_ao[ik], double(na) * no * no);
         }
+        const i64 gt = fuse ? add_gtab(kq, j) : 0;
         for (size_t sg = 0; sg < BA.size.size(); ++sg) {
           const int m = BA.size[sg], off = BA.off[sg];
           const i64 w0 = i64(jj) * slab + i64(off) * no;
-          d.p0_gemm.add(gp(m, m, no, nk * no, 1, B_W1, w0, no, i64(na) * no, 0, OP_N, B_W2, w0, no, i64(na) * no, 0, OP_H,
-                           B_OUT, c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale));
+          if (fuse) {
+            // A_(k,a) = Vp[i][k][a][rows s of block sg][:] G^{k+q0}(tau_j), outer index t = k nao + a
+            GemmProblem p = gp(m, m, no, nk * no, 1, B_VP, i64(i) * nk * na * no * no + i64(off) * no, no, i64(na) * no,
+                               0, OP_N, B_W2, w0, no, i64(na) * no, 0, OP_H, B_OUT,
+                               c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale);
+            p.gfuse = 1; p.gbuf = B_G; p.gdiv = no; p.gtab = gt;
+            d.p0_gemm.add(p, double(m) * m * no * nk * no + double(m) * no * fused_macs);
+          } else {
+            d.p0_gemm.add(gp(m, m, no, nk * no, 1, B_W1, w0, no, i64(na) * no, 0, OP_N, B_W2, w0, no, i64(na) * no, 0,
+                             OP_H, B_OUT, c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale));
+          }
         }
       }
       d.p0_right.close();
@@ -396,6 +439,10 @@ int device_init(Ctx& c, void* stream) {
   d.p0_mirror.close();
 
   // ---------------- self-energy (eq. sigma, Alg. 4) ----------------
+  std::vector<int> allk(nk);
+  std::iota(allk.begin(), allk.end(), 0);
+  double sfused_macs = 0;
+  for (int kp = 0; kp < nk; ++kp) sfused_macs += double(na) * no * sumsq_ao[c.rep[kp]];
   for (int i = 0; i < nib; ++i) {
     const int k0 = c.ibz[i];
     const Blocks& BO = c.bao[i];
@@ -403,6 +450,31 @@ int device_init(Ctx& c, void* stream) {
       const int j1 = std::min(nt, j0 + J);
       for (int j = j0; j < j1; ++j) {
         const int jj = j - j0;
+        for (int kp = 0; kp < nk && fuse; ++kp) {
+          const int q = mesh.sub(k0, kp), iq = c.rep[q];
+          const Blocks& BQ = c.baux[iq];
+          const i64 vs = (i64(i) * nk + kp) * na * no * no;
+          const i64 wo = (i64(jj) * nk + kp) * na * no * no;
+          for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
+            const int m = BQ.size[sg], off = BQ.off[sg];
+            d.s_gemmA.add(gp(m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j) * BQ.packed + BQ.poff[sg], m, 0, 0, OP_T, B_VS,
+                             vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1, wo + i64(off) * no * no, i64(no) * no, 0));
+          }
+        }
+        if (fuse) {
+          // Sigma = sum_(k',s') [Y(k',s') G^{k'}(tau_j)] Vs(k',s')^H with the G factor applied on the A tiles
+          GemmProblem p = gp(no, no, no, nk * na, 1, B_W1, i64(jj) * slab, no, i64(no) * no, 0, OP_N, B_VS,
+                             i64(i) * nk * na * no * no, no, i64(no) * no, 0, OP_H, B_SCR, i64(jj) * no * no, no, 0,
+                             -1.0 / nk);
+          p.gfuse = 1; p.gbuf = B_G; p.gdiv = na; p.gtab = add_gtab(allk, j);
+          d.s_gemmC.add(p, sumsq_ao[i] * no * double(nk) * na + sfused_macs);
+          for (size_t rb = 0; rb < BO.size.size(); ++rb) {
+            const int n = BO.size[rb], off = BO.off[rb];
+            d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(jj) * no * no + i64(off) * no + off,
+                                      c.g_off[i] + i64(j) * BO.packed + BO.poff[rb], no});
+          }
+          continue;
+        }
         for (int kp = 0; kp < nk; ++kp) {
           const int q = mesh.sub(k0, kp), iq = c.rep[q], ik = c.rep[kp];
           const Blocks& BQ = c.baux[iq];
@@ -542,6 +614,7 @@ int device_init(Ctx& c, void* stream) {
       if ((st = upload_stage(c, d, *g, s))) return st;
   for (RowStage* r : {&d.p0_right, &d.p0_left, &d.s_right})
     if ((st = upload(c, d, r->segs, &r->d, s))) return st;
+  if ((st = upload(c, d, gtab, &d.gtab, s))) return st;
   for (auto* l : {&d.p0_mirror, &d.scr_herm, &d.dys_herm, &d.s_pack})
     if ((st = upload(c, d, l->items, &l->d, s))) return st;
   for (auto* l : {&d.scr_inv, &d.dys_inv, &d.mu_inv})
@@ -576,6 +649,7 @@ void device_free(Ctx& c) {
   DevState* d = static_cast<DevState*>(c.dev_state);
   if (!d) return;
   for (hipEvent_t e : d->prof.pool) hipEventDestroy(e);
+  if (d->graph_exec) hipGraphExecDestroy(d->graph_exec);
   for (void* p : d->allocs) hipFree(p);
   delete d;
   c.dev_state = nullptr;
@@ -620,6 +694,8 @@ Bases bases_of(DevState& d) {
   b.p[B_U] = d.U;
   b.p[B_WT] = d.WT;
   b.p[B_SCR] = d.SCR;
+  b.p[B_GT] = d.gtab;
+  b.p[B_BT] = d.btab;
   return b;
 }
 
@@ -760,6 +836,17 @@ int device_load_V(Ctx& c, const void* Vin, void* stream) {
     launch_brgemm(plan_of(g2, g2.launches[l]), b, d.partials, s);
     launch_brgemm(plan_of(g3, g3.launches[l]), b, d.partials, s);
   }
+  if (c.prm.precision == GWSYM_FP32) {
+    const size_t n = size_t(nib) * nk * pe;
+    if (!d.VP32) {
+      if ((st = dalloc(c, d, &d.VP32, n * 8))) return st;
+      if ((st = dalloc(c, d, &d.VS32, n * 8))) return st;
+      if ((st = dalloc(c, d, &d.G32, size_t(c.g_off[nib]) * 8 + 16))) return st;
+      if ((st = dalloc(c, d, &d.P32, size_t(c.p_off[nib]) * 8 + 16))) return st;
+    }
+    launch_to_f32(d.VP, d.VP32, i64(n), s);
+    launch_to_f32(d.VS, d.VS32, i64(n), s);
+  }
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(s));
   c.vloaded = true;
@@ -819,15 +906,24 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
   Bases b = bases_of(d);
   b.p[B_G] = const_cast<void*>(G);
   b.p[B_OUT] = P0;
+  // FP32 contractions: FP32 copies of V (made once) and of G (here); W2 holds float2
+  const bool f32 = c.prm.precision == GWSYM_FP32;
+  unsigned mask = 0;
+  if (f32) {
+    launch_to_f32(G, d.G32, c.g_off[c.nibz], s);
+    b.p[B_G] = d.G32;
+    b.p[B_VP] = d.VP32;
+    mask = 1u << B_W2;
+  }
   for (size_t l = 0; l < d.p0_gemm.launches.size(); ++l) {
     const Range& rr = d.p0_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.p0_right.d) + rr.t0, rr.nt, rr.r0};
     timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s); }, rr.bytes);
     const Range& rl = d.p0_left.launches[l];
     RowSegList L{static_cast<RowSeg*>(d.p0_left.d) + rl.t0, rl.nt, rl.r0};
-    timed(d, s, PC_LEFT, rl.macs, [&] { launch_rowblock_left(L, b, d.btab, c.nao, s); }, rl.bytes);
+    timed(d, s, PC_LEFT, rl.macs, [&] { launch_rowblock_left(L, b, d.btab, c.nao, s, f32); }, rl.bytes);
     const Range& rg = d.p0_gemm.launches[l];
-    timed(d, s, PC_P0, rg.macs, [&] { launch_brgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1); });
+    timed(d, s, PC_P0, rg.macs, [&] { launch_brgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, f32, mask); });
   }
   const Range& m = d.p0_mirror.launches[0];
   timed(d, s, PC_OTHER, 0, [&] { launch_copy(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s); });
@@ -845,14 +941,24 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
   b.p[B_G] = const_cast<void*>(G);
   b.p[B_P] = const_cast<void*>(P);
   b.p[B_OUT] = S;
+  const bool f32 = c.prm.precision == GWSYM_FP32;
+  unsigned mask = 0;
+  if (f32) {
+    launch_to_f32(G, d.G32, c.g_off[c.nibz], s);
+    launch_to_f32(P, d.P32, c.p_off[c.nibz], s);
+    b.p[B_G] = d.G32;
+    b.p[B_P] = d.P32;
+    b.p[B_VS] = d.VS32;
+    mask = 1u << B_W1;
+  }
   for (size_t l = 0; l < d.s_gemmA.launches.size(); ++l) {
     const Range& ra = d.s_gemmA.launches[l];
-    timed(d, s, PC_SA, ra.macs, [&] { launch_brgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2); });
+    timed(d, s, PC_SA, ra.macs, [&] { launch_brgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, f32, mask); });
     const Range& rr = d.s_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
     timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s); }, rr.bytes);
     const Range& rc = d.s_gemmC.launches[l];
-    timed(d, s, PC_SC, rc.macs, [&] { launch_brgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3); });
+    timed(d, s, PC_SC, rc.macs, [&] { launch_brgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, f32, mask); });
     const Range& rp = d.s_pack.launches[l];
     timed(d, s, PC_OTHER, 0, [&] { launch_pack(static_cast<CopySeg*>(d.s_pack.d) + rp.t0, rp.nt, b, s); });
   }
@@ -922,6 +1028,49 @@ int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double*
     });
   }
   HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+int device_iteration(Ctx& c, const void* F, void* G, void* P0, void* P, void* S, double* mu, double ntarget,
+                     int use_graph, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  auto body = [&]() -> int {
+    int st;
+    if ((st = device_polarization(c, G, P0, stream))) return st;
+    if ((st = device_screened(c, P0, P, stream))) return st;
+    if ((st = device_self_energy(c, G, P, S, stream))) return st;
+    if (ntarget > 0 && (st = device_find_mu(c, F, S, ntarget, mu, stream))) return st;
+    return device_dyson(c, F, S, mu, G, stream);
+  };
+  if (!use_graph) return body();
+  int st;
+  if ((st = need_partials(c, d))) return st;   // no allocation may happen inside the capture
+  const std::vector<const void*> key{F, G, P0, P, S, mu, stream};
+  if (!d.graph_exec || key != d.graph_key || ntarget != d.graph_ntarget) {
+    if (d.graph_exec) {
+      hipGraphExecDestroy(d.graph_exec);
+      d.graph_exec = nullptr;
+    }
+    const bool prof = d.prof.on;
+    d.prof.on = false;  // no event records inside the graph
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = body();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    d.prof.on = prof;
+    if (st) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    HIPCHECK(e);
+    const hipError_t ei = hipGraphInstantiate(&d.graph_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHECK(ei);
+    d.graph_key = key;
+    d.graph_ntarget = ntarget;
+  }
+  HIPCHECK(hipGraphLaunch(d.graph_exec, s));
   return GWSYM_OK;
 }
 

@@ -99,3 +99,57 @@ def test_deterministic_rerun():
     run.ctx.self_energy(run.G, run.P, run.S)
     torch.cuda.synchronize()
     assert torch.equal(a, run.S)
+
+
+# FP32 contractions (FP32 operands, FP32 MFMA accumulation per tile, FP64 split sums; transforms,
+# inverses and mu in FP64): relative error bar 1e-6 on Sigma, as for the split-precision path.
+TOL32 = 1e-6
+
+
+@pytest.mark.parametrize("name", ["cfg0", "small_sc4", "small_diamond"])
+def test_fp32_contractions(name):
+    say(f"[fp32] {name}")
+    run = GpuRun(name, MODES["block"], precision=1)
+    ref = oracle_run(name)
+    r = ref["iters"][0]
+    run.g0()
+    c = run.ctx
+    c.polarization(run.G, run.P0)
+    e0 = rel(run.full(2, run.P0), r["P0"])
+    c.screened_interaction(run.P0, run.P)
+    c.self_energy(run.G, run.P, run.S)
+    es = rel(run.full(1, run.S), r["Sigma"])
+    if ref["n_target"] is not None:
+        c.find_mu(run.F, run.S, ref["n_target"], run.mu)
+    c.dyson_G(run.F, run.S, run.mu, run.G)
+    G = run.full(1, run.G)
+    eg = rel(G, r["G"])
+    occ = np.abs(np.diagonal(-G[:, -1], axis1=-2, axis2=-1) - np.diagonal(-r["G"][:, -1], axis1=-2, axis2=-1)).max()
+    say(f"  P0 {e0:.2e} Sigma {es:.2e} G {eg:.2e} occupations {occ:.2e}")
+    assert e0 < TOL32 and es < TOL32 and eg < TOL32 and occ < TOL32
+
+
+@pytest.mark.parametrize("name", ["small_rocksalt", "cfg0"])
+def test_graph_iteration(name):
+    """gwsym_iteration replayed from its captured HIP graph, three times with eager work and
+    synchronisations between the replays, against the same iterations run eagerly."""
+    say(f"[graph] {name}")
+    ref = oracle_run(name)
+    nt = ref["n_target"] or 0.0
+    eager, graph = GpuRun(name, MODES["block"]), GpuRun(name, MODES["block"])
+    eager.g0()
+    graph.g0()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for it in range(3):
+        eager.ctx.iteration(eager.F, eager.G, eager.P0, eager.P, eager.S, eager.mu, nt)
+        torch.cuda.synchronize()
+        graph.ctx.iteration(graph.F, graph.G, graph.P0, graph.P, graph.S, graph.mu, nt, use_graph=True,
+                            stream=side)
+        side.synchronize()
+        Ge, Gg = eager.full(1, eager.G), graph.full(1, graph.G)
+        say(f"  replay {it}: max |dG| {np.abs(Ge - Gg).max():.2e}, mu {graph.mu.item():.15f}")
+        assert np.array_equal(Ge, Gg)
+        assert torch.equal(eager.S, graph.S) and torch.equal(eager.mu, graph.mu)
+        if it == 0:
+            assert rel(Gg, ref["iters"][0]["G"]) < TOL
