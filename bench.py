@@ -46,8 +46,9 @@ def make_ctx(wl, mode, half_tau=True, tau_chunk=0):
 class Path:
     """Device state of one mode: F, G, P0, P, Sigma, mu, and the iteration."""
 
-    def __init__(self, ctx, F_all, V_all, torch, dev):
+    def __init__(self, ctx, F_all, V_all, torch, dev, graph=False):
         self.ctx, self.torch = ctx, torch
+        self.graph = torch.cuda.Stream() if graph else None
         ctx.device_init()
         ibz = torch.as_tensor(ctx.table("ibz"), device=dev)
         ctx.load_V(V_all[ibz].contiguous())
@@ -62,6 +63,13 @@ class Path:
 
     def step(self):
         c = self.ctx
+        if self.graph is not None:
+            # the whole iteration replayed from one captured HIP graph on a side stream
+            self.torch.cuda.current_stream().synchronize()
+            c.iteration(self.F, self.G, self.P0, self.P, self.S, self.mu, self.n_target, use_graph=True,
+                        stream=self.graph)
+            self.graph.synchronize()
+            return
         c.polarization(self.G, self.P0)
         c.screened_interaction(self.P0, self.P)
         c.self_energy(self.G, self.P, self.S)
@@ -152,6 +160,7 @@ def main():
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--tau-chunk", type=int, default=0)
     ap.add_argument("--no-full", action="store_true", help="skip the full-matrix FP64 comparison")
+    ap.add_argument("--graph", type=int, default=1, help="1 (default): replay each iteration from a captured HIP graph; 0: eager launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a plain copy kernel "
@@ -188,7 +197,8 @@ def main():
 
     # ---- block-grouped, irreducible wedge, FP64 ----
     t = time.perf_counter()
-    blk = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk), F_all, V_all, torch, dev)
+    blk = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk), F_all, V_all, torch, dev,
+               graph=bool(args.graph))
     log(f"[bench] block path set up in {time.perf_counter() - t:.1f} s; N_target={blk.n_target:.6f}")
     s_blk = time_steps(blk, args.steps, args.warmup, torch)
     log(f"[bench] block: {s_blk:.4f} s/iteration")

@@ -72,15 +72,16 @@ struct GemmProblem {
   i64 gtab;
 };
 
-// A 32 x 32 output tile (or ntn consecutive column tiles) of one problem over the outer
-// range [t0, t1).  slot < 0: the tile writes C directly; otherwise (ntn = 1) it writes its
-// raw sum to partial slot `slot` and a reduction item combines the slots in order.
+// An output tile of one problem over the outer range [t0, t1), in units of 16: rows
+// [16 tm, 16 (tm + mh)) with mh = 1 or 2, columns [16 tn, 16 (tn + nn)) walked in chunks of
+// 32.  slot < 0: the tile writes C directly; otherwise (nn <= 2) it writes its raw sum to
+// the 32 x 32 partial slot `slot` and a reduction item combines the slots in order.
 struct GemmTile {
-  int prob, batch, tm, tn, t0, t1, slot, ntn;   // ntn: consecutive column tiles handled
+  int prob, batch, tm, tn, t0, t1, slot, mh, nn, pad_;
 };
 
 struct GemmReduce {
-  int prob, batch, tm, tn, slot0, nslot, pad0_, pad1_;
+  int prob, batch, tm, tn, slot0, nslot, mh, nh;   // tm, tn, mh, nh in units of 16
 };
 
 struct GemmPlan {

@@ -34,10 +34,16 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 }
 
 // ----------------------------------------------------------------------------
-// grouped batch-reduce complex GEMM, 32 x 32 output tile per workgroup of four waves;
-// each wave owns a 16 x 16 quarter and issues four FP64 MFMAs per complex K-step of 4.
+// grouped batch-reduce complex GEMM on FP64 (or FP32) MFMA.  A workgroup of four waves owns
+// an output tile of 16 or 32 rows and walks its columns in chunks of 16 or 32; each 16 x 16
+// quarter of a chunk belongs to one wave, and when a chunk has fewer than four quarters the
+// waves of a quarter share out its K steps and add their sums through LDS at the end.  A
+// complex K step of 4 is four real MFMAs.  The next step's A and B elements are fetched into
+// registers while the current step computes.
 
 constexpr int TM = 32, TN = 32, BK = 32;
+constexpr int LD = TM + 1;     // LDS row length (padding against bank conflicts)
+constexpr int PF = TM * BK / 256;  // elements of A (and of B) fetched per thread per step
 
 // Element type of the operands: FP64 (double2, FP64 MFMA) or FP32 (float2, FP32 MFMA).
 template <typename R> struct Cx;
@@ -63,34 +69,75 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
 __device__ __forceinline__ int mrow(double, int lane, int j) { return (lane >> 4) + 4 * j; }
 __device__ __forceinline__ int mrow(float, int lane, int j) { return 4 * (lane >> 4) + j; }
 
+// Position (row or column index within the tile, k index within the chunk) of fetch slot
+// idx of an operand whose tile dimension is `dim`: the contiguous index of the source runs
+// fastest across threads.
+__device__ __forceinline__ void slot_pos(int idx, bool kfast, int dim, int& x, int& k) {
+  if (kfast) { x = idx / BK; k = idx % BK; }
+  else { k = idx / dim; x = idx % dim; }
+}
+
 // TAG only separates the stages in profiles (P0, Sigma aux / orbital contractions, others).
 // f32mask: bit b set when buffer b holds float2 (then C is stored as float2).
 template <typename R, int TAG>
-__global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ probs,
+__global__ __launch_bounds__(256, 3) void k_brgemm(const GemmProblem* __restrict__ probs,
                                                 const GemmTile* __restrict__ tiles, Bases bases,
                                                 double2* __restrict__ partials, unsigned f32mask) {
   using V2 = typename Cx<R>::V2;
   using A4 = typename Cx<R>::A4;
-  __shared__ R As_re[BK][TM + 1], As_im[BK][TM + 1];
-  __shared__ R Bs_re[BK][TN + 1], Bs_im[BK][TN + 1];
+  __shared__ R lds_ab[4][BK][LD];   // A re, A im, B re, B im; also the cross-wave sums
   __shared__ R Gs_re[BK][BK + 1], Gs_im[BK][BK + 1];
   __shared__ int gcol_off[BK], gcol_sz[BK];
+  R(*As_re)[LD] = lds_ab[0];
+  R(*As_im)[LD] = lds_ab[1];
+  R(*Bs_re)[LD] = lds_ab[2];
+  R(*Bs_im)[LD] = lds_ab[3];
   const GemmTile tl = tiles[blockIdx.x];
   const GemmProblem P = probs[tl.prob];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = tl.tm * TM;
+  const int m0 = tl.tm * 16, tmv = tl.mh * 16;
   const V2* Ab = reinterpret_cast<const V2*>(bases.p[P.abuf]) + P.aoff + int64_t(tl.batch) * P.sAb;
   const V2* Bb = reinterpret_cast<const V2*>(bases.p[P.bbuf]) + P.boff + int64_t(tl.batch) * P.sBb;
   const bool a_kfast = (P.opA & 1) == 0;  // N, C: k is the contiguous index of A
   const bool b_nfast = (P.opB & 1) == 0;  // N, C: n is the contiguous index of B
+  const int nkc = (P.K + BK - 1) / BK;
+  const int nsteps = (tl.t1 - tl.t0) * nkc;
   int gcur = -1;
-  for (int tn = tl.tn; tn < tl.tn + tl.ntn; ++tn) {
-    const int n0 = tn * TN;
+  for (int cu = tl.tn; cu < tl.tn + tl.nn; cu += 2) {
+    const int nc = min(2, tl.tn + tl.nn - cu);
+    const int n0 = cu * 16, tnv = nc * 16;
+    // quarters of this chunk and the waves that share one
+    const int nq = tl.mh * nc, wpq = 4 / nq;
+    const int quarter = wave / wpq, phase = wave % wpq;
+    const int qm = (tl.mh == 2) ? (nc == 2 ? quarter >> 1 : quarter) : 0;
+    const int qn = (tl.mh == 2) ? (nc == 2 ? (quarter & 1) : 0) : quarter;
     A4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-    for (int t = tl.t0; t < tl.t1; ++t) {
+    V2 ra[PF], rb[PF];
+    auto fetch = [&](int st) {
+      const int t = tl.t0 + st / nkc, k0 = (st % nkc) * BK, kv = min(BK, P.K - k0);
       const V2* A = Ab + int64_t(t) * P.sAt;
       const V2* B = Bb + int64_t(t) * P.sBt;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int idx = tid + 256 * q;
+        int x, kk;
+        V2 v = {0, 0};
+        if (idx < tmv * BK) {
+          slot_pos(idx, a_kfast, tmv, x, kk);
+          if (m0 + x < P.M && kk < kv) v = load_op(A, P.opA, m0 + x, k0 + kk, P.lda);
+        }
+        ra[q] = v;
+        V2 w = {0, 0};
+        if (idx < tnv * BK) {
+          slot_pos(idx, !b_nfast, tnv, x, kk);
+          if (n0 + x < P.N && kk < kv) w = load_op(B, P.opB, k0 + kk, n0 + x, P.ldb);
+        }
+        rb[q] = w;
+      }
+    };
+    if (nsteps > 0) fetch(0);
+    for (int st = 0; st < nsteps; ++st) {
+      const int t = tl.t0 + st / nkc, k0 = (st % nkc) * BK, kv = min(BK, P.K - k0);
       if (P.gfuse) {
         // block-diagonal right factor of A for this outer index (uniform over the group)
         const int gi = t / P.gdiv;
@@ -118,75 +165,93 @@ __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ 
               gcol_sz[off + cc] = sz;
             }
           }
-          __syncthreads();
         }
       }
-      for (int k0 = 0; k0 < P.K; k0 += BK) {
-        const int kv = min(BK, P.K - k0);
-        for (int idx = tid; idx < TM * BK; idx += 256) {
-          int mm, kk;
-          if (a_kfast) { mm = idx / BK; kk = idx % BK; }
-          else { kk = idx / TM; mm = idx % TM; }
-          const int m = m0 + mm, k = k0 + kk;
-          V2 v = {0, 0};
-          if (m < P.M && kk < kv) v = load_op(A, P.opA, m, k, P.lda);
-          As_re[kk][mm] = v.x;
-          As_im[kk][mm] = v.y;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int idx = tid + 256 * q;
+        int x, kk;
+        if (idx < tmv * BK) {
+          slot_pos(idx, a_kfast, tmv, x, kk);
+          As_re[kk][x] = ra[q].x;
+          As_im[kk][x] = ra[q].y;
         }
-        for (int idx = tid; idx < TN * BK; idx += 256) {
-          int nn, kk;
-          if (b_nfast) { kk = idx / TN; nn = idx % TN; }
-          else { nn = idx / BK; kk = idx % BK; }
-          const int n = n0 + nn, k = k0 + kk;
-          V2 v = {0, 0};
-          if (n < P.N && kk < kv) v = load_op(B, P.opB, k, n, P.ldb);
-          Bs_re[kk][nn] = v.x;
-          Bs_im[kk][nn] = v.y;
+        if (idx < tnv * BK) {
+          slot_pos(idx, !b_nfast, tnv, x, kk);
+          Bs_re[kk][x] = rb[q].x;
+          Bs_im[kk][x] = rb[q].y;
+        }
+      }
+      __syncthreads();
+      if (st + 1 < nsteps) fetch(st + 1);
+      if (P.gfuse) {
+        // A <- A G within each block of G (K = kv <= BK, a single chunk)
+        V2 res[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+          const int idx = tid + 256 * q, mm = idx % tmv, kc = idx / tmv;
+          V2 s = {0, 0};
+          if (idx < tmv * BK && kc < kv) {
+            const int off = gcol_off[kc], sz = gcol_sz[kc];
+            for (int kk = off; kk < off + sz; ++kk) {
+              const R ar = As_re[kk][mm], ai = As_im[kk][mm], gr = Gs_re[kk][kc], gim = Gs_im[kk][kc];
+              s.x += ar * gr - ai * gim;
+              s.y += ar * gim + ai * gr;
+            }
+          }
+          res[q] = s;
         }
         __syncthreads();
-        if (P.gfuse) {
-          // A <- A G within each block of G (K = kv <= BK, a single chunk)
-          V2 res[TM * BK / 256];
 #pragma unroll
-          for (int q = 0; q < TM * BK / 256; ++q) {
-            const int idx = tid + 256 * q, mm = idx % TM, kc = idx / TM;
-            V2 s = {0, 0};
-            if (kc < kv) {
-              const int off = gcol_off[kc], sz = gcol_sz[kc];
-              for (int kk = off; kk < off + sz; ++kk) {
-                const R ar = As_re[kk][mm], ai = As_im[kk][mm], gr = Gs_re[kk][kc], gim = Gs_im[kk][kc];
-                s.x += ar * gr - ai * gim;
-                s.y += ar * gim + ai * gr;
-              }
-            }
-            res[q] = s;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int q = 0; q < TM * BK / 256; ++q) {
-            const int idx = tid + 256 * q, mm = idx % TM, kc = idx / TM;
+        for (int q = 0; q < PF; ++q) {
+          const int idx = tid + 256 * q, mm = idx % tmv, kc = idx / tmv;
+          if (idx < tmv * BK) {
             As_re[kc][mm] = res[q].x;
             As_im[kc][mm] = res[q].y;
           }
-          __syncthreads();
-        }
-        const int r = wm * 16 + (lane & 15), cix = wn * 16 + (lane & 15), kq = lane >> 4;
-        for (int kk = 0; kk < kv; kk += 4) {
-          const R are = As_re[kk + kq][r], aim = As_im[kk + kq][r];
-          const R bre = Bs_re[kk + kq][cix], bim = Bs_im[kk + kq][cix];
-          cre = mfma16(are, bre, cre);
-          cre = mfma16(-aim, bim, cre);
-          cim = mfma16(are, bim, cim);
-          cim = mfma16(aim, bre, cim);
         }
         __syncthreads();
       }
+      const int r = qm * 16 + (lane & 15), cix = qn * 16 + (lane & 15), kq = lane >> 4;
+      for (int kk = 4 * phase; kk < kv; kk += 4 * wpq) {
+        const R are = As_re[kk + kq][r], aim = As_im[kk + kq][r];
+        const R bre = Bs_re[kk + kq][cix], bim = Bs_im[kk + kq][cix];
+        cre = mfma16(are, bre, cre);
+        cre = mfma16(-aim, bim, cre);
+        cim = mfma16(are, bim, cim);
+        cim = mfma16(aim, bre, cim);
+      }
+      __syncthreads();
     }
-    const int col = wn * 16 + (lane & 15);
+    if (wpq > 1) {
+      // waves that shared a quarter's K steps add their sums in LDS (the tile buffers are free)
+      R* red = &lds_ab[0][0][0];
+      if (phase > 0) {
+        R* dst = red + ((quarter * 3 + phase - 1) * 64 + lane) * 8;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          dst[j] = cre[j];
+          dst[4 + j] = cim[j];
+        }
+      }
+      __syncthreads();
+      if (phase == 0)
+        for (int p2 = 1; p2 < wpq; ++p2) {
+          const R* src = red + ((quarter * 3 + p2 - 1) * 64 + lane) * 8;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cre[j] += src[j];
+            cim[j] += src[4 + j];
+          }
+        }
+      __syncthreads();
+      if (phase > 0) continue;
+    }
+    const int col = qn * 16 + (lane & 15);
     if (tl.slot >= 0) {
       double2* out = partials + int64_t(tl.slot) * TM * TN;
       for (int j = 0; j < 4; ++j) {
-        const int row = wm * 16 + mrow(R(0), lane, j);
+        const int row = qm * 16 + mrow(R(0), lane, j);
         out[row * TN + col] = make_double2(double(cre[j]), double(cim[j]));
       }
       continue;
@@ -194,7 +259,7 @@ __global__ __launch_bounds__(256) void k_brgemm(const GemmProblem* __restrict__ 
     const double2 al = make_double2(P.alpha_re, P.alpha_im);
     const bool cf32 = (f32mask >> P.cbuf) & 1u;
     for (int j = 0; j < 4; ++j) {
-      const int row = m0 + wm * 16 + mrow(R(0), lane, j), cc = n0 + col;
+      const int row = m0 + qm * 16 + mrow(R(0), lane, j), cc = n0 + col;
       if (row < P.M && cc < P.N) {
         double2 v = cmul(al, make_double2(double(cre[j]), double(cim[j])));
         const int64_t at = P.coff + int64_t(tl.batch) * P.sCb + int64_t(row) * P.ldc + cc;
@@ -220,8 +285,9 @@ __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ 
   const bool cf32 = (f32mask >> P.cbuf) & 1u;
   const double2 al = make_double2(P.alpha_re, P.alpha_im);
   for (int e = threadIdx.x; e < TM * TN; e += 256) {
-    const int row = rd.tm * TM + e / TN, cc = rd.tn * TN + e % TN;
-    if (row >= P.M || cc >= P.N) continue;
+    const int er = e / TN, ec = e % TN;
+    const int row = rd.tm * 16 + er, cc = rd.tn * 16 + ec;
+    if (er >= rd.mh * 16 || ec >= rd.nh * 16 || row >= P.M || cc >= P.N) continue;
     double2 s = make_double2(0.0, 0.0);
     for (int q = 0; q < rd.nslot; ++q) s = cadd(s, partials[int64_t(rd.slot0 + q) * TM * TN + e]);
     double2 v = cmul(al, s);

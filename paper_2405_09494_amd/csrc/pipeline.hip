@@ -48,35 +48,39 @@ struct GemmStage {
     Range r;
     r.t0 = int(tiles.size());
     r.r0 = int(reds.size());
+    // tiles of 32 rows (columns), the last one 16 when the remainder allows
+    auto units = [](int n) { return (n + 15) / 16; };
     long base = 0;
     for (int id : pending) {
       const GemmProblem& p = probs[id];
-      base += long(p.batch) * ((p.M + 31) / 32) * ((p.N + 31) / 32);
+      base += long(p.batch) * ((units(p.M) + 1) / 2) * ((units(p.N) + 1) / 2);
     }
     r.macs = pending_macs;
     pending_macs = 0;
     int slots = 0;
     for (int id : pending) {
       const GemmProblem& p = probs[id];
-      const int tm = (p.M + 31) / 32, tn = (p.N + 31) / 32;
+      const int mu = units(p.M), nu = units(p.N);
       int split = 1;
       if (base < target && p.T >= 8) split = int(std::min<long>(p.T / 4, (target + base - 1) / std::max(1L, base)));
       split = std::max(1, split);
       for (int b = 0; b < p.batch; ++b)
-        for (int i = 0; i < tm; ++i) {
+        for (int i = 0; i < mu; i += 2) {
+          const int mh = std::min(2, mu - i);
           if (split == 1) {
-            const int group = 8;
-            for (int j = 0; j < tn; j += group)
-              tiles.push_back({id, b, i, j, 0, p.T, -1, std::min(group, tn - j)});
+            const int group = 16;   // up to eight 32-column chunks per workgroup
+            for (int j = 0; j < nu; j += group)
+              tiles.push_back({id, b, i, j, 0, p.T, -1, mh, std::min(group, nu - j), 0});
             continue;
           }
-          for (int j = 0; j < tn; ++j) {
+          for (int j = 0; j < nu; j += 2) {
+            const int nh = std::min(2, nu - j);
             const int s0 = slots;
             for (int s = 0; s < split; ++s) {
               const int t0 = int(long(s) * p.T / split), t1 = int(long(s + 1) * p.T / split);
-              tiles.push_back({id, b, i, j, t0, t1, s0 + s, 1});
+              tiles.push_back({id, b, i, j, t0, t1, s0 + s, mh, nh, 0});
             }
-            reds.push_back({id, b, i, j, s0, split, 0, 0});
+            reds.push_back({id, b, i, j, s0, split, mh, nh});
             slots += split;
           }
         }
@@ -419,7 +423,7 @@ int device_init(Ctx& c, void* stream) {
                                0, OP_N, B_W2, w0, no, i64(na) * no, 0, OP_H, B_OUT,
                                c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale);
             p.gfuse = 1; p.gbuf = B_G; p.gdiv = no; p.gtab = gt;
-            d.p0_gemm.add(p, double(m) * m * no * nk * no + double(m) * no * fused_macs);
+            d.p0_gemm.add(p, double(m) * m * no * nk * no + double(m) * fused_macs);
           } else {
             d.p0_gemm.add(gp(m, m, no, nk * no, 1, B_W1, w0, no, i64(na) * no, 0, OP_N, B_W2, w0, no, i64(na) * no, 0,
                              OP_H, B_OUT, c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale));
