@@ -26,6 +26,44 @@ sys.path.insert(0, ROOT)
 METRIC = "s/GW iteration + contraction TFLOP/s, block-grouped vs full FP64, at ≤1e-6 rel Σ err"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop per byte where the two bounds meet
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cfg1.md")
+
+
+def source_digest():
+    """sha256 over the kernel and launch-plan sources: measured counters apply only to the
+    code they were taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "pipeline.hip"):
+        with open(os.path.join(ROOT, "paper_2405_09494_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when that summary was taken from other kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    digest = None
+    for line in text.splitlines():
+        if line.startswith("source-sha256:"):
+            digest = line.split(":", 1)[1].strip()
+    if digest != source_digest():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == cls:
+            try:
+                return float(cells[-1])
+            except ValueError:
+                return None
+    return None
 
 
 def log(*a):
@@ -61,9 +99,9 @@ class Path:
         torch.cuda.synchronize()
         self.n_target = float(self.nfree.item())
 
-    def step(self):
+    def step(self, eager=False):
         c = self.ctx
-        if self.graph is not None:
+        if self.graph is not None and not eager:
             # the whole iteration replayed from one captured HIP graph on a side stream
             self.torch.cuda.current_stream().synchronize()
             c.iteration(self.F, self.G, self.P0, self.P, self.S, self.mu, self.n_target, use_graph=True,
@@ -97,7 +135,7 @@ def time_steps(path, steps, warmup, torch):
 
 def profile_step(path, torch):
     path.ctx.profile(True)
-    path.step()
+    path.step(eager=True)   # per-launch events need the launches themselves, not a graph replay
     torch.cuda.synchronize()
     prof = path.ctx.profile_read()
     path.ctx.profile(False)
@@ -206,26 +244,31 @@ def main():
     p0_macs, s_macs = blk.ctx.flop_counts()
     flops_iter = 8.0 * (p0_macs + s_macs)
     contr_ms = sum(prof[k][0] for k in ("p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction",
-                                         "row_block_multiply", "col_block_multiply"))
+                                         "row_block_multiply", "two_sided_block_multiply"))
     log("[bench] profile: " + ", ".join(f"{k} {v[0]:.1f} ms/{v[1]}" for k, v in prof.items()))
 
-    # dominant kernel class by time
+    # dominant kernel class by time; its bound follows from the algorithmic intensity
     def roofline(name):
         ms, nl, macs, nbytes = prof[name]
-        if nbytes > 0:   # block-diagonal multiplies: HBM-bound
-            achieved = nbytes / nl / (ms / nl * 1e-3) / 1e9
-            return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": name,
-                    "per_launch_bytes": nbytes / nl, "avg_launch_ms": ms / nl}
-        achieved = 8.0 * macs / nl / (ms / nl * 1e-3) / 1e12
-        return {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": name,
-                "per_launch_flops": 8.0 * macs / nl, "avg_launch_ms": ms / nl}
+        flops = 8.0 * macs
+        avg_s = ms / nl * 1e-3
+        entry = {"kernel": name, "avg_launch_ms": ms / nl, "launches": nl,
+                 "per_launch_flops": flops / nl, "per_launch_bytes": nbytes / nl,
+                 "intensity_flop_per_byte": flops / nbytes if nbytes > 0 else None}
+        if nbytes > 0 and flops / nbytes < RIDGE:
+            achieved = nbytes / nl / avg_s / 1e9
+            entry.update({"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"})
+        else:
+            achieved = flops / nl / avg_s / 1e12
+            entry.update({"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"})
+        entry["frac"] = entry["achieved"] / entry["peak"]
+        entry["traffic"] = measured_traffic(name)
+        return entry
 
     dom = max(prof, key=lambda k: prof[k][0])
     roof = roofline(dom)
     kernels = {k: roofline(k) for k in ("p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction",
-                                        "row_block_multiply", "col_block_multiply") if prof[k][1] > 0}
+                                        "row_block_multiply", "two_sided_block_multiply") if prof[k][1] > 0}
 
     out = {"metric": METRIC, "value": s_blk, "unit": "s/iteration", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * s_blk, "higher_is_better": False, "scaling": "weak",

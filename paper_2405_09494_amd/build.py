@@ -24,9 +24,15 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-I", os.path.join(ROOT, "include")]
 
 
+# device code: MFMA results in ordinary VGPRs, so loop-carried accumulators are not copied
+# between the accumulation and the arithmetic register files on every iteration
+DEVICE_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = DEVICE_FLAGS if src.endswith(".hip") else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")

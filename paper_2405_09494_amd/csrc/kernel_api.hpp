@@ -20,14 +20,24 @@ struct GemmPlanDev {
   void* tiles = nullptr;
   void* reds = nullptr;
   int ntiles = 0, nreds = 0, nslots = 0;
+  int shape[4] = {0, 0, 0, 0};   // wave-tile lists: tiles per shape (16x16, 16x32, 32x16, 32x32), in order
 };
 
 // rows [0, nrows) of a row-major slab (right multiply), or the slab width (left multiply)
+// One slab for a block-diagonal multiply.  Right multiply: nrows rows of ncol columns, each
+// row times the block-diagonal matrix at g_off.  Left multiply: nb_rows rows of nrows
+// columns, G^H (at g_off) applied from the left.  Both-sided multiply: nb_rows rows of
+// nrows columns made of nrows / nb_rows square nb_rows x nb_rows matrices side by side, each
+// X -> Gl^H X Gr^H with Gl at (g_off, blk) and Gr at (g_off2, blk2).
 struct RowSeg {
   int inbuf, outbuf, gbuf, blk;  // blk: offset of the block table entry in btab
   int64_t in_off, out_off, g_off;
-  int nrows, pad_;
+  int nrows, blk2;
+  int64_t g_off2;
 };
+
+// Tile elements per workgroup of the both-sided block multiply; one n x n matrix must fit.
+constexpr int RBB_ELEMS = 2048;
 
 struct RowSegList {
   void* segs = nullptr;
@@ -63,7 +73,12 @@ struct EigItem {
 void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag = 0,
                    bool fp32 = false, unsigned f32mask = 0);
 void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s);
-void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s);
+void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s,
+                           bool fp32 = false);
+void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s, bool fp32);
+// Wave-tile complex GEMM over the same problem and tile lists (tiles of at most 32 x 32).
+void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, bool fp32,
+                  unsigned f32mask);
 void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s,
                           bool fp32 = false);
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);

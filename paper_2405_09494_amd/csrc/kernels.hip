@@ -70,19 +70,21 @@ __device__ __forceinline__ int mrow(double, int lane, int j) { return (lane >> 4
 __device__ __forceinline__ int mrow(float, int lane, int j) { return 4 * (lane >> 4) + j; }
 
 // Position (row or column index within the tile, k index within the chunk) of fetch slot
-// idx of an operand whose tile dimension is `dim`: the contiguous index of the source runs
-// fastest across threads.
-__device__ __forceinline__ void slot_pos(int idx, bool kfast, int dim, int& x, int& k) {
-  if (kfast) { x = idx / BK; k = idx % BK; }
-  else { k = idx / dim; x = idx % dim; }
+// idx of an operand whose tile dimension is 16 << lg16: the contiguous index of the source
+// runs fastest across threads.
+__device__ __forceinline__ void slot_pos(int idx, bool kfast, int lg16, int& x, int& k) {
+  if (kfast) { x = idx >> 5; k = idx & (BK - 1); }
+  else { k = idx >> (4 + lg16); x = idx & ((16 << lg16) - 1); }
 }
 
 // TAG only separates the stages in profiles (P0, Sigma aux / orbital contractions, others).
 // f32mask: bit b set when buffer b holds float2 (then C is stored as float2).
+// The steps of all column chunks of a tile form one sequence, so the fetch of the next
+// step (possibly the first of the next chunk) overlaps the current step's arithmetic.
 template <typename R, int TAG>
 __global__ __launch_bounds__(256, 3) void k_brgemm(const GemmProblem* __restrict__ probs,
-                                                const GemmTile* __restrict__ tiles, Bases bases,
-                                                double2* __restrict__ partials, unsigned f32mask) {
+                                                   const GemmTile* __restrict__ tiles, Bases bases,
+                                                   double2* __restrict__ partials, unsigned f32mask) {
   using V2 = typename Cx<R>::V2;
   using A4 = typename Cx<R>::A4;
   __shared__ R lds_ab[4][BK][LD];   // A re, A im, B re, B im; also the cross-wave sums
@@ -93,136 +95,153 @@ __global__ __launch_bounds__(256, 3) void k_brgemm(const GemmProblem* __restrict
   R(*Bs_re)[LD] = lds_ab[2];
   R(*Bs_im)[LD] = lds_ab[3];
   const GemmTile tl = tiles[blockIdx.x];
+  if (tl.prob < 0) return;   // padding entry of the XCD-ordered tile list
   const GemmProblem P = probs[tl.prob];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = tl.tm * 16, tmv = tl.mh * 16;
+  const int m0 = tl.tm * 16, lgm = tl.mh - 1, tmv = tl.mh * 16;
   const V2* Ab = reinterpret_cast<const V2*>(bases.p[P.abuf]) + P.aoff + int64_t(tl.batch) * P.sAb;
   const V2* Bb = reinterpret_cast<const V2*>(bases.p[P.bbuf]) + P.boff + int64_t(tl.batch) * P.sBb;
   const bool a_kfast = (P.opA & 1) == 0;  // N, C: k is the contiguous index of A
   const bool b_nfast = (P.opB & 1) == 0;  // N, C: n is the contiguous index of B
   const int nkc = (P.K + BK - 1) / BK;
-  const int nsteps = (tl.t1 - tl.t0) * nkc;
+  const int spc = (tl.t1 - tl.t0) * nkc;   // steps per column chunk
+  const int nchunk = (tl.nn + 1) >> 1;
+  const int total = spc * nchunk;
+  V2 ra[PF], rb[PF];
+  auto fetch = [&](int st) {
+    const int ch = st / spc, sc = st - ch * spc;
+    const int cu = tl.tn + 2 * ch, nc = min(2, tl.tn + tl.nn - cu), n0 = cu * 16, lgn = nc - 1;
+    const int tt = sc / nkc, t = tl.t0 + tt, k0 = (sc - tt * nkc) * BK, kv = min(BK, P.K - k0);
+    const V2* A = Ab + int64_t(t) * P.sAt;
+    const V2* B = Bb + int64_t(t) * P.sBt;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int idx = tid + 256 * q;
+      int x, kk;
+      V2 v = {0, 0};
+      if (idx < (tmv << 5)) {
+        slot_pos(idx, a_kfast, lgm, x, kk);
+        if (m0 + x < P.M && kk < kv) v = load_op(A, P.opA, m0 + x, k0 + kk, P.lda);
+      }
+      ra[q] = v;
+      V2 w = {0, 0};
+      if (idx < (nc << 9)) {
+        slot_pos(idx, !b_nfast, lgn, x, kk);
+        if (n0 + x < P.N && kk < kv) w = load_op(B, P.opB, k0 + kk, n0 + x, P.ldb);
+      }
+      rb[q] = w;
+    }
+  };
   int gcur = -1;
-  for (int cu = tl.tn; cu < tl.tn + tl.nn; cu += 2) {
-    const int nc = min(2, tl.tn + tl.nn - cu);
-    const int n0 = cu * 16, tnv = nc * 16;
-    // quarters of this chunk and the waves that share one
-    const int nq = tl.mh * nc, wpq = 4 / nq;
-    const int quarter = wave / wpq, phase = wave % wpq;
-    const int qm = (tl.mh == 2) ? (nc == 2 ? quarter >> 1 : quarter) : 0;
-    const int qn = (tl.mh == 2) ? (nc == 2 ? (quarter & 1) : 0) : quarter;
-    A4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-    V2 ra[PF], rb[PF];
-    auto fetch = [&](int st) {
-      const int t = tl.t0 + st / nkc, k0 = (st % nkc) * BK, kv = min(BK, P.K - k0);
-      const V2* A = Ab + int64_t(t) * P.sAt;
-      const V2* B = Bb + int64_t(t) * P.sBt;
-#pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        const int idx = tid + 256 * q;
-        int x, kk;
-        V2 v = {0, 0};
-        if (idx < tmv * BK) {
-          slot_pos(idx, a_kfast, tmv, x, kk);
-          if (m0 + x < P.M && kk < kv) v = load_op(A, P.opA, m0 + x, k0 + kk, P.lda);
+  int nc = 0, n0 = 0, wpq = 1, quarter = 0, phase = 0, qm = 0, qn = 0;
+  A4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+  if (total > 0) fetch(0);
+  for (int st = 0; st < total; ++st) {
+    const int ch = st / spc, sc = st - ch * spc;
+    if (sc == 0) {
+      // a new column chunk: its quarters and the waves that share one
+      const int cu = tl.tn + 2 * ch;
+      nc = min(2, tl.tn + tl.nn - cu);
+      n0 = cu * 16;
+      const int nq = tl.mh * nc;
+      wpq = 4 / nq;
+      quarter = wave / wpq;
+      phase = wave % wpq;
+      qm = (tl.mh == 2) ? (nc == 2 ? quarter >> 1 : quarter) : 0;
+      qn = (tl.mh == 2) ? (nc == 2 ? (quarter & 1) : 0) : quarter;
+      cre = A4{0, 0, 0, 0};
+      cim = A4{0, 0, 0, 0};
+    }
+    const int tnv = nc * 16, lgn = nc - 1;
+    const int tt = sc / nkc, t = tl.t0 + tt, kv = min(BK, P.K - (sc - tt * nkc) * BK);
+    if (P.gfuse) {
+      // block-diagonal right factor of A for this outer index (uniform over the group)
+      const int gi = t / P.gdiv;
+      if (gi != gcur) {
+        gcur = gi;
+        const int64_t* gt = reinterpret_cast<const int64_t*>(bases.p[B_GT]) + P.gtab + 2 * int64_t(gi);
+        const V2* G = reinterpret_cast<const V2*>(bases.p[P.gbuf]) + gt[0];
+        const int* bt = reinterpret_cast<const int*>(bases.p[B_BT]) + gt[1];
+        __syncthreads();
+        for (int e = tid; e < BK * BK; e += 256) {
+          Gs_re[e / BK][e % BK] = 0.0;
+          Gs_im[e / BK][e % BK] = 0.0;
         }
-        ra[q] = v;
-        V2 w = {0, 0};
-        if (idx < tnv * BK) {
-          slot_pos(idx, !b_nfast, tnv, x, kk);
-          if (n0 + x < P.N && kk < kv) w = load_op(B, P.opB, k0 + kk, n0 + x, P.ldb);
-        }
-        rb[q] = w;
-      }
-    };
-    if (nsteps > 0) fetch(0);
-    for (int st = 0; st < nsteps; ++st) {
-      const int t = tl.t0 + st / nkc, k0 = (st % nkc) * BK, kv = min(BK, P.K - k0);
-      if (P.gfuse) {
-        // block-diagonal right factor of A for this outer index (uniform over the group)
-        const int gi = t / P.gdiv;
-        if (gi != gcur) {
-          gcur = gi;
-          const int64_t* gt = reinterpret_cast<const int64_t*>(bases.p[B_GT]) + P.gtab + 2 * int64_t(gi);
-          const V2* G = reinterpret_cast<const V2*>(bases.p[P.gbuf]) + gt[0];
-          const int* bt = reinterpret_cast<const int*>(bases.p[B_BT]) + gt[1];
-          __syncthreads();
-          for (int e = tid; e < BK * BK; e += 256) {
-            Gs_re[e / BK][e % BK] = 0.0;
-            Gs_im[e / BK][e % BK] = 0.0;
+        __syncthreads();
+        const int nb = bt[0];
+        for (int b = 0; b < nb; ++b) {
+          const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
+          for (int e = tid; e < sz * sz; e += 256) {
+            const V2 g = G[po + e];
+            Gs_re[off + e / sz][off + e % sz] = g.x;
+            Gs_im[off + e / sz][off + e % sz] = g.y;
           }
-          __syncthreads();
-          const int nb = bt[0];
-          for (int b = 0; b < nb; ++b) {
-            const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
-            for (int e = tid; e < sz * sz; e += 256) {
-              const V2 g = G[po + e];
-              Gs_re[off + e / sz][off + e % sz] = g.x;
-              Gs_im[off + e / sz][off + e % sz] = g.y;
-            }
-            for (int cc = tid; cc < sz; cc += 256) {
-              gcol_off[off + cc] = off;
-              gcol_sz[off + cc] = sz;
-            }
+          for (int cc = tid; cc < sz; cc += 256) {
+            gcol_off[off + cc] = off;
+            gcol_sz[off + cc] = sz;
           }
         }
       }
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int idx = tid + 256 * q;
+      int x, kk;
+      if (idx < (tmv << 5)) {
+        slot_pos(idx, a_kfast, lgm, x, kk);
+        As_re[kk][x] = ra[q].x;
+        As_im[kk][x] = ra[q].y;
+      }
+      if (idx < (tnv << 5)) {
+        slot_pos(idx, !b_nfast, lgn, x, kk);
+        Bs_re[kk][x] = rb[q].x;
+        Bs_im[kk][x] = rb[q].y;
+      }
+    }
+    __syncthreads();
+    if (st + 1 < total) fetch(st + 1);
+    if (P.gfuse) {
+      // A <- A G within each block of G (K = kv <= BK, a single chunk)
+      V2 res[PF];
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
-        const int idx = tid + 256 * q;
-        int x, kk;
-        if (idx < tmv * BK) {
-          slot_pos(idx, a_kfast, tmv, x, kk);
-          As_re[kk][x] = ra[q].x;
-          As_im[kk][x] = ra[q].y;
+        const int idx = tid + 256 * q, mm = idx & (tmv - 1), kc = idx >> (4 + lgm);
+        V2 s = {0, 0};
+        if (idx < (tmv << 5) && kc < kv) {
+          const int off = gcol_off[kc], sz = gcol_sz[kc];
+          for (int kk = off; kk < off + sz; ++kk) {
+            const R ar = As_re[kk][mm], ai = As_im[kk][mm], gr = Gs_re[kk][kc], gim = Gs_im[kk][kc];
+            s.x += ar * gr - ai * gim;
+            s.y += ar * gim + ai * gr;
+          }
         }
-        if (idx < tnv * BK) {
-          slot_pos(idx, !b_nfast, tnv, x, kk);
-          Bs_re[kk][x] = rb[q].x;
-          Bs_im[kk][x] = rb[q].y;
+        res[q] = s;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        const int idx = tid + 256 * q, mm = idx & (tmv - 1), kc = idx >> (4 + lgm);
+        if (idx < (tmv << 5)) {
+          As_re[kc][mm] = res[q].x;
+          As_im[kc][mm] = res[q].y;
         }
       }
       __syncthreads();
-      if (st + 1 < nsteps) fetch(st + 1);
-      if (P.gfuse) {
-        // A <- A G within each block of G (K = kv <= BK, a single chunk)
-        V2 res[PF];
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-          const int idx = tid + 256 * q, mm = idx % tmv, kc = idx / tmv;
-          V2 s = {0, 0};
-          if (idx < tmv * BK && kc < kv) {
-            const int off = gcol_off[kc], sz = gcol_sz[kc];
-            for (int kk = off; kk < off + sz; ++kk) {
-              const R ar = As_re[kk][mm], ai = As_im[kk][mm], gr = Gs_re[kk][kc], gim = Gs_im[kk][kc];
-              s.x += ar * gr - ai * gim;
-              s.y += ar * gim + ai * gr;
-            }
-          }
-          res[q] = s;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PF; ++q) {
-          const int idx = tid + 256 * q, mm = idx % tmv, kc = idx / tmv;
-          if (idx < tmv * BK) {
-            As_re[kc][mm] = res[q].x;
-            As_im[kc][mm] = res[q].y;
-          }
-        }
-        __syncthreads();
-      }
+    }
+    {
       const int r = qm * 16 + (lane & 15), cix = qn * 16 + (lane & 15), kq = lane >> 4;
       for (int kk = 4 * phase; kk < kv; kk += 4 * wpq) {
         const R are = As_re[kk + kq][r], aim = As_im[kk + kq][r];
         const R bre = Bs_re[kk + kq][cix], bim = Bs_im[kk + kq][cix];
         cre = mfma16(are, bre, cre);
-        cre = mfma16(-aim, bim, cre);
         cim = mfma16(are, bim, cim);
+        cre = mfma16(-aim, bim, cre);
         cim = mfma16(aim, bre, cim);
       }
-      __syncthreads();
     }
+    __syncthreads();
+    if (sc != spc - 1) continue;
+    // ---- end of a column chunk ----
     if (wpq > 1) {
       // waves that shared a quarter's K steps add their sums in LDS (the tile buffers are free)
       R* red = &lds_ab[0][0][0];
@@ -304,6 +323,191 @@ __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ 
   }
 }
 
+// ----------------------------------------------------------------------------
+// Wave-tile grouped complex GEMM for the contractions: one wave per workgroup owns an output
+// tile of 16 or 32 rows by 16 or 32 columns (M2, N2) over its outer range.  The MFMA operands
+// come straight from global memory: in a step over four k values lane l holds row (column)
+// l % 16 of each 16-row quarter at k = 4 s + l / 16, so four lanes read 64 contiguous bytes of
+// a row.  The k steps of all outer indices of the tile form one sequence, taken two at a time
+// with the next pair in flight; the loop body has no branches (the last step of an odd count
+// and k values beyond K are zeroed through the B operand).  Rows and columns beyond the
+// problem read clamped, in-range addresses and are never stored.  No LDS, no barriers.
+
+template <typename R, int TAG, bool M2, bool N2>
+__global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ probs,
+                                              const GemmTile* __restrict__ tiles, Bases bases,
+                                              double2* __restrict__ partials, unsigned f32mask) {
+  using V2 = typename Cx<R>::V2;
+  using A4 = typename Cx<R>::A4;
+  const GemmTile tl = tiles[blockIdx.x];
+  if (tl.prob < 0) return;   // padding entry of the XCD-ordered tile list
+  const GemmProblem P = probs[tl.prob];
+  const int lane = threadIdx.x, li = lane & 15, kq = lane >> 4;
+  const int m0 = tl.tm * 16, n0 = tl.tn * 16;
+  const V2* Ab = reinterpret_cast<const V2*>(bases.p[P.abuf]) + P.aoff + int64_t(tl.batch) * P.sAb;
+  const V2* Bb = reinterpret_cast<const V2*>(bases.p[P.bbuf]) + P.boff + int64_t(tl.batch) * P.sBb;
+  const int K = P.K, nk4 = (K + 3) >> 2;
+  const bool aT = P.opA & 1, bT = P.opB & 1;
+  const R sA = (P.opA & 2) ? R(-1) : R(1), sB = (P.opB & 2) ? R(-1) : R(1);
+  // element offset of (row or column x, k): x * ldx + k (k contiguous) or k * ldx + x
+  const int ra0 = min(m0 + li, P.M - 1), ra1 = min(m0 + 16 + li, P.M - 1);
+  const int cb0 = min(n0 + li, P.N - 1), cb1 = min(n0 + 16 + li, P.N - 1);
+  const int64_t ax0 = aT ? ra0 : int64_t(ra0) * P.lda, ax1 = aT ? ra1 : int64_t(ra1) * P.lda;
+  const int64_t ak = aT ? P.lda : 1;
+  const int64_t bx0 = bT ? int64_t(cb0) * P.ldb : cb0, bx1 = bT ? int64_t(cb1) * P.ldb : cb1;
+  const int64_t bk = bT ? 1 : P.ldb;
+  const int nsub = (tl.t1 - tl.t0) * nk4, npair = (nsub + 1) >> 1;
+  A4 c00r = {0, 0, 0, 0}, c00i = c00r, c01r = c00r, c01i = c00r, c10r = c00r, c10i = c00r, c11r = c00r, c11i = c00r;
+  // fetch position: outer index t and k step j of the next sub-step; the mask zeroes k >= K
+  // and sub-steps past the end
+  int ft = tl.t0, fj = 0, fs = 0;
+  V2 fa[2][2], fb[2][2];
+  R fm[2];
+  auto fetch1 = [&](int h) {
+    const bool live = fs < nsub;
+    const int t = live ? ft : tl.t1 - 1;
+    const int k = 4 * fj + kq;
+    const int64_t kc = min(k, K - 1);
+    const V2* A = Ab + int64_t(t) * P.sAt;
+    const V2* B = Bb + int64_t(t) * P.sBt;
+    fa[h][0] = A[ax0 + kc * ak];
+    if (M2) fa[h][1] = A[ax1 + kc * ak];
+    fb[h][0] = B[bx0 + kc * bk];
+    if (N2) fb[h][1] = B[bx1 + kc * bk];
+    fm[h] = (live && k < K) ? R(1) : R(0);
+    ++fs;
+    if (++fj == nk4) {
+      fj = 0;
+      ++ft;
+    }
+  };
+  if (npair > 0) {
+    fetch1(0);
+    fetch1(1);
+  }
+  for (int pr = 0; pr < npair; ++pr) {
+    V2 a[2][2], b[2][2];
+    R m[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h][0] = fa[h][0];
+      a[h][1] = M2 ? fa[h][1] : fa[h][0];
+      b[h][0] = fb[h][0];
+      b[h][1] = N2 ? fb[h][1] : fb[h][0];
+      m[h] = fm[h];
+    }
+    if (pr + 1 < npair) {
+      fetch1(0);
+      fetch1(1);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const R a0r = R(a[h][0].x), a0i = R(a[h][0].y) * sA, a1r = R(a[h][1].x), a1i = R(a[h][1].y) * sA;
+      const R b0r = R(b[h][0].x) * m[h], b0i = R(b[h][0].y) * (sB * m[h]);
+      const R b1r = R(b[h][1].x) * m[h], b1i = R(b[h][1].y) * (sB * m[h]);
+      c00r = mfma16(a0r, b0r, c00r);
+      c00i = mfma16(a0r, b0i, c00i);
+      if (N2) {
+        c01r = mfma16(a0r, b1r, c01r);
+        c01i = mfma16(a0r, b1i, c01i);
+      }
+      if (M2) {
+        c10r = mfma16(a1r, b0r, c10r);
+        c10i = mfma16(a1r, b0i, c10i);
+      }
+      if (M2 && N2) {
+        c11r = mfma16(a1r, b1r, c11r);
+        c11i = mfma16(a1r, b1i, c11i);
+      }
+      c00r = mfma16(-a0i, b0i, c00r);
+      c00i = mfma16(a0i, b0r, c00i);
+      if (N2) {
+        c01r = mfma16(-a0i, b1i, c01r);
+        c01i = mfma16(a0i, b1r, c01i);
+      }
+      if (M2) {
+        c10r = mfma16(-a1i, b0i, c10r);
+        c10i = mfma16(a1i, b0r, c10i);
+      }
+      if (M2 && N2) {
+        c11r = mfma16(-a1i, b1i, c11r);
+        c11i = mfma16(a1i, b1r, c11i);
+      }
+    }
+  }
+  const double2 al = make_double2(P.alpha_re, P.alpha_im);
+  const bool cf32 = (f32mask >> P.cbuf) & 1u;
+  auto store = [&](int qm, int qn, const A4& cr, const A4& ci) {
+    for (int j = 0; j < 4; ++j) {
+      const int row = qm * 16 + mrow(R(0), lane, j), col = qn * 16 + li;
+      if (tl.slot >= 0) {
+        partials[int64_t(tl.slot) * TM * TN + row * TN + col] = make_double2(double(cr[j]), double(ci[j]));
+        continue;
+      }
+      const int gr = m0 + row, gc = n0 + col;
+      if (gr >= P.M || gc >= P.N) continue;
+      double2 v = cmul(al, make_double2(double(cr[j]), double(ci[j])));
+      const int64_t at = P.coff + int64_t(tl.batch) * P.sCb + int64_t(gr) * P.ldc + gc;
+      if (cf32) {
+        float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
+        if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
+        C[at] = make_float2(float(v.x), float(v.y));
+      } else {
+        double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]);
+        if (P.beta) v = cadd(v, C[at]);
+        C[at] = v;
+      }
+    }
+  };
+  store(0, 0, c00r, c00i);
+  if (N2) store(0, 1, c01r, c01i);
+  if (M2) store(1, 0, c10r, c10i);
+  if (M2 && N2) store(1, 1, c11r, c11i);
+}
+
+template <typename R, int TAG>
+void launch_wgemm_tag(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, unsigned mask) {
+  const GemmProblem* pr = (const GemmProblem*)p.probs;
+  const GemmTile* tl = (const GemmTile*)p.tiles;
+  double2* pa = (double2*)partials;
+  // the tile list is sorted by shape: 16x16, 16x32, 32x16, 32x32, counts in p.shape
+  int at = 0;
+  for (int sh = 0; sh < 4; ++sh) {
+    const int n = p.shape[sh];
+    if (n == 0) continue;
+    const dim3 g(n), t(64);
+    const GemmTile* ts = tl + at;
+    switch (sh) {
+      case 0: hipLaunchKernelGGL((k_wgemm<R, TAG, false, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 1: hipLaunchKernelGGL((k_wgemm<R, TAG, false, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 2: hipLaunchKernelGGL((k_wgemm<R, TAG, true, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      default: hipLaunchKernelGGL((k_wgemm<R, TAG, true, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
+    }
+    at += n;
+  }
+}
+
+template <typename R>
+void launch_wgemm_t(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, unsigned mask) {
+  switch (tag) {
+    case 1: launch_wgemm_tag<R, 1>(p, b, partials, s, mask); break;
+    case 2: launch_wgemm_tag<R, 2>(p, b, partials, s, mask); break;
+    case 3: launch_wgemm_tag<R, 3>(p, b, partials, s, mask); break;
+    default: launch_wgemm_tag<R, 0>(p, b, partials, s, mask); break;
+  }
+}
+
+void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, bool fp32,
+                  unsigned f32mask) {
+  if (p.ntiles > 0) {
+    if (fp32) launch_wgemm_t<float>(p, b, partials, s, tag, f32mask);
+    else launch_wgemm_t<double>(p, b, partials, s, tag, f32mask);
+  }
+  if (p.nreds > 0)
+    hipLaunchKernelGGL(k_reduce, dim3(p.nreds), dim3(256), 0, s, (const GemmProblem*)p.probs,
+                       (const GemmReduce*)p.reds, b, (const double2*)partials, f32mask);
+}
+
 template <typename R>
 void launch_brgemm_t(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, unsigned mask) {
   const dim3 g(p.ntiles), t(256);
@@ -350,21 +554,25 @@ void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s) {
 
 constexpr int RB_ROWS = 64;
 
+template <typename V2>
 __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict__ segs, Bases bases,
                                                         const int* __restrict__ btab, int ncol) {
-  extern __shared__ double2 lds[];
+  extern __shared__ double2 lds_rr[];
   const RowSeg sg = segs[blockIdx.y];
   const int r0 = blockIdx.x * RB_ROWS;
   if (r0 >= sg.nrows) return;
   const int nrows = min(RB_ROWS, sg.nrows - r0);
-  const double2* in = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off + int64_t(r0) * ncol;
-  double2* out = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off + int64_t(r0) * ncol;
-  const double2* G = reinterpret_cast<const double2*>(bases.p[sg.gbuf]) + sg.g_off;
+  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + int64_t(r0) * ncol;
+  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + int64_t(r0) * ncol;
+  const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
   const int* bt = btab + sg.blk;  // bt[0] = count, then (off, size, poff) per block
-  double2* tile = lds;            // nrows x ncol
-  int* colblk = reinterpret_cast<int*>(lds + RB_ROWS * ncol);  // per column: block index
-  for (int e = threadIdx.x; e < nrows * ncol; e += 256) tile[e] = in[e];
+  V2* tile = reinterpret_cast<V2*>(lds_rr);               // nrows x ncol
+  V2* gs = tile + RB_ROWS * ncol;                          // packed blocks, ncol^2 at most
+  int* colblk = reinterpret_cast<int*>(gs + ncol * ncol);  // per column: block index
   const int nb = bt[0];
+  const int gsz = bt[3 * nb] + bt[3 * nb - 1] * bt[3 * nb - 1];   // poff + size^2 of the last block
+  for (int e = threadIdx.x; e < gsz; e += 256) gs[e] = G[e];
+  for (int e = threadIdx.x; e < nrows * ncol; e += 256) tile[e] = in[e];
   for (int c = threadIdx.x; c < ncol; c += 256)
     for (int b = 0; b < nb; ++b)
       if (c >= bt[1 + 3 * b] && c < bt[1 + 3 * b] + bt[2 + 3 * b]) colblk[c] = b;
@@ -374,9 +582,94 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
     const int b = colblk[c];
     const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
     const int cc = c - off;
-    double2 s = make_double2(0.0, 0.0);
-    for (int k = 0; k < sz; ++k) s = cadd(s, cmul(tile[row * ncol + off + k], G[po + k * sz + cc]));
+    V2 s = {0, 0};
+    for (int k = 0; k < sz; ++k) {
+      const V2 x = tile[row * ncol + off + k], g = gs[po + k * sz + cc];
+      s.x += x.x * g.x - x.y * g.y;
+      s.y += x.x * g.y + x.y * g.x;
+    }
     out[e] = s;
+  }
+}
+
+// X -> Gl^H X Gr^H for nq square n x n matrices side by side per workgroup (the polarization's
+// second factor with both Green's function blocks applied in one pass over the slab).
+
+template <typename V2>
+__global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict__ segs, Bases bases,
+                                                       const int* __restrict__ btab, int n) {
+  extern __shared__ double2 lds_rb[];
+  const RowSeg sg = segs[blockIdx.y];
+  const int nq = max(1, RBB_ELEMS / (n * n)), w = nq * n;
+  const int c0 = blockIdx.x * w;
+  const int ncols = sg.nrows;   // slab width: whole matrices side by side
+  if (c0 >= ncols) return;
+  const int wv = min(w, ncols - c0);
+  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
+  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
+  const V2* Gl = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
+  const V2* Gr = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off2;
+  const int* btl = btab + sg.blk;
+  const int* btr = btab + sg.blk2;
+  V2* tile = reinterpret_cast<V2*>(lds_rb);   // n x w
+  V2* gl = tile + n * w;                      // packed blocks of Gl, then of Gr
+  const int nbl = btl[0], nbr = btr[0];
+  const int szl = btl[3 * nbl] + btl[3 * nbl - 1] * btl[3 * nbl - 1];
+  const int szr = btr[3 * nbr] + btr[3 * nbr - 1] * btr[3 * nbr - 1];
+  V2* gr = gl + szl;
+  int* idx = reinterpret_cast<int*>(gr + szr);  // per index: block of the left, block of the right
+  for (int e = threadIdx.x; e < szl; e += 256) gl[e] = Gl[e];
+  for (int e = threadIdx.x; e < szr; e += 256) gr[e] = Gr[e];
+  for (int c = threadIdx.x; c < n; c += 256) {
+    int bl = 0, br = 0;
+    while (bl + 1 < nbl && c >= btl[1 + 3 * (bl + 1)]) ++bl;
+    while (br + 1 < nbr && c >= btr[1 + 3 * (br + 1)]) ++br;
+    idx[c] = bl;
+    idx[n + c] = br;
+  }
+  for (int e = threadIdx.x; e < n * w; e += 256) {
+    const int r = e / w, c = e % w;
+    V2 z = {0, 0};
+    tile[e] = c < wv ? in[int64_t(r) * ncols + c] : z;
+  }
+  __syncthreads();
+  // left: row a' of Gl^H X = sum over a in the block of a' of conj(Gl[a][a']) X[a][:]
+  V2 acc[RBB_ELEMS / 256];
+#pragma unroll
+  for (int q = 0; q < RBB_ELEMS / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    V2 s = {0, 0};
+    if (e < n * w) {
+      const int ap = e / w, c = e % w, b = idx[ap];
+      const int off = btl[1 + 3 * b], sz = btl[2 + 3 * b], po = btl[3 + 3 * b], rr = ap - off;
+      for (int k = 0; k < sz; ++k) {
+        const V2 g = gl[po + k * sz + rr], x = tile[(off + k) * w + c];
+        s.x += g.x * x.x + g.y * x.y;
+        s.y += g.x * x.y - g.y * x.x;
+      }
+    }
+    acc[q] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < RBB_ELEMS / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < n * w) tile[e] = acc[q];
+  }
+  __syncthreads();
+  // right: column b' of Y Gr^H = sum over b in the block of b' of Y[:][b] conj(Gr[b'][b])
+  for (int e = threadIdx.x; e < n * w; e += 256) {
+    const int r = e / w, c = e % w;
+    if (c >= wv) continue;
+    const int mq = c / n, bp = c % n, b = idx[n + bp];
+    const int off = btr[1 + 3 * b], sz = btr[2 + 3 * b], po = btr[3 + 3 * b], cc = bp - off;
+    V2 s = {0, 0};
+    for (int k = 0; k < sz; ++k) {
+      const V2 y = tile[r * w + mq * n + off + k], g = gr[po + cc * sz + k];
+      s.x += y.x * g.x + y.y * g.y;
+      s.y += y.y * g.x - y.x * g.y;
+    }
+    out[int64_t(r) * ncols + c] = s;
   }
 }
 
@@ -421,11 +714,32 @@ __global__ __launch_bounds__(256) void k_rowblock_left(const RowSeg* __restrict_
   }
 }
 
-void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s) {
+void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s,
+                           bool fp32) {
   if (l.nseg == 0) return;
-  const size_t lds = size_t(RB_ROWS) * ncol * sizeof(double2) + ncol * sizeof(int) + 16;
-  hipLaunchKernelGGL(k_rowblock_right, dim3((l.maxrows + RB_ROWS - 1) / RB_ROWS, l.nseg), dim3(256), lds, s,
-                     (const RowSeg*)l.segs, b, btab, ncol);
+  const dim3 g((l.maxrows + RB_ROWS - 1) / RB_ROWS, l.nseg);
+  const size_t el = size_t(RB_ROWS) * ncol + size_t(ncol) * ncol;
+  const size_t ex = ncol * sizeof(int) + 16;
+  if (fp32)
+    hipLaunchKernelGGL(k_rowblock_right<float2>, g, dim3(256), el * sizeof(float2) + ex, s, (const RowSeg*)l.segs, b,
+                       btab, ncol);
+  else
+    hipLaunchKernelGGL(k_rowblock_right<double2>, g, dim3(256), el * sizeof(double2) + ex, s, (const RowSeg*)l.segs,
+                       b, btab, ncol);
+}
+
+void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s, bool fp32) {
+  if (l.nseg == 0) return;
+  const int w = std::max(1, RBB_ELEMS / (n * n)) * n;
+  const dim3 g((l.maxrows + w - 1) / w, l.nseg);
+  const size_t el = size_t(n) * w + 2 * size_t(n) * n;
+  const size_t ex = 2 * n * sizeof(int) + 16;
+  if (fp32)
+    hipLaunchKernelGGL(k_rowblock_both<float2>, g, dim3(256), el * sizeof(float2) + ex, s, (const RowSeg*)l.segs, b,
+                       btab, n);
+  else
+    hipLaunchKernelGGL(k_rowblock_both<double2>, g, dim3(256), el * sizeof(double2) + ex, s, (const RowSeg*)l.segs,
+                       b, btab, n);
 }
 
 void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -18,7 +20,63 @@ struct Range {
   int t0 = 0, nt = 0, r0 = 0, nr = 0;
   double macs = 0;   // complex multiply-accumulates requested by the launch
   double bytes = 0;  // algorithmic bytes moved (memory-bound launches)
+  int shape[4] = {0, 0, 0, 0};   // wave-tile launches: tiles per shape class, in list order
 };
+
+// Workgroup p of a launch runs on XCD p % 8, and each XCD has its own L2.  Tiles that read
+// the same operand rows (the same A rows over the same outer range, or the same B columns)
+// are gathered into one group, each group is given to the least loaded XCD, and the list is
+// interleaved so that a group's tiles run on that XCD one after another.  Short queues are
+// padded with empty tiles (prob = -1).
+inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vector<GemmProblem>& probs) {
+  constexpr int NX = 8;
+  const int n = int(tiles.size()) - t0;
+  if (n <= NX) return;
+  using Key = std::array<i64, 5>;
+  auto keyA = [&](const GemmTile& t) {
+    const GemmProblem& p = probs[t.prob];
+    return Key{p.abuf, p.aoff + i64(t.batch) * p.sAb, t.tm, t.t0, 0};
+  };
+  auto keyB = [&](const GemmTile& t) {
+    const GemmProblem& p = probs[t.prob];
+    return Key{p.bbuf, p.boff + i64(t.batch) * p.sBb, t.tn, t.t0, 1};
+  };
+  std::map<Key, int> ca, cb;
+  for (int i = t0; i < int(tiles.size()); ++i) {
+    ca[keyA(tiles[i])]++;
+    cb[keyB(tiles[i])]++;
+  }
+  std::map<Key, int> gid;
+  std::vector<std::vector<int>> groups;
+  for (int i = t0; i < int(tiles.size()); ++i) {
+    const Key ka = keyA(tiles[i]), kb = keyB(tiles[i]);
+    const Key k = ca[ka] >= cb[kb] ? ka : kb;
+    auto it = gid.find(k);
+    if (it == gid.end()) {
+      it = gid.emplace(k, int(groups.size())).first;
+      groups.emplace_back();
+    }
+    groups[it->second].push_back(i);
+  }
+  std::vector<std::vector<int>> q(NX);
+  for (const auto& g : groups) {
+    int x = 0;
+    for (int y = 1; y < NX; ++y)
+      if (q[y].size() < q[x].size()) x = y;
+    q[x].insert(q[x].end(), g.begin(), g.end());
+  }
+  size_t len = 0;
+  for (const auto& v : q) len = std::max(len, v.size());
+  std::vector<GemmTile> out;
+  out.reserve(len * NX);
+  for (size_t i = 0; i < len; ++i)
+    for (int x = 0; x < NX; ++x) {
+      if (i < q[x].size()) out.push_back(tiles[q[x][i]]);
+      else out.push_back(GemmTile{-1, 0, 0, 0, 0, 0, -1, 1, 1, 0});
+    }
+  tiles.resize(t0);
+  tiles.insert(tiles.end(), out.begin(), out.end());
+}
 
 struct GemmStage {
   std::vector<GemmProblem> probs;
@@ -33,18 +91,24 @@ struct GemmStage {
   double macs = 0;
 
   // algo_macs: the multiply-accumulates the algorithm needs when the problem computes more
-  // (e.g. zero off-diagonal blocks); by default the problem's own M N K T batch.
+  // (e.g. zero off-diagonal blocks); by default the problem's own M N K T batch.  The
+  // algorithmic bytes of a problem are one read of each operand and one write of C, in
+  // complex128 (the fused block-diagonal factor is small and cached).
   void add(const GemmProblem& p, double algo_macs = -1.0) {
     pending.push_back(int(probs.size()));
     probs.push_back(p);
     const double m = algo_macs >= 0 ? algo_macs : double(p.M) * p.N * p.K * double(p.T) * p.batch;
     macs += m;
     pending_macs += m;
+    pending_bytes += 16.0 * p.batch * (double(p.K) * p.T * (double(p.M) + p.N) + double(p.M) * p.N);
   }
-  double pending_macs = 0;
+  double pending_macs = 0, pending_bytes = 0;
+  void xcd_order(int t0) { xcd_order_tiles(tiles, t0, probs); }
   // Closes a launch: turns its problems into tiles; problems with a long outer loop are
   // split so that the launch has about `target` workgroups.
+  bool wave = false;   // tiles for the wave-tile kernel: one 32-column chunk each, more of them
   void close(int target = 2048) {
+    if (wave) target = 8192;
     Range r;
     r.t0 = int(tiles.size());
     r.r0 = int(reds.size());
@@ -56,7 +120,9 @@ struct GemmStage {
       base += long(p.batch) * ((units(p.M) + 1) / 2) * ((units(p.N) + 1) / 2);
     }
     r.macs = pending_macs;
+    r.bytes = pending_bytes;
     pending_macs = 0;
+    pending_bytes = 0;
     int slots = 0;
     for (int id : pending) {
       const GemmProblem& p = probs[id];
@@ -68,7 +134,7 @@ struct GemmStage {
         for (int i = 0; i < mu; i += 2) {
           const int mh = std::min(2, mu - i);
           if (split == 1) {
-            const int group = 16;   // up to eight 32-column chunks per workgroup
+            const int group = wave ? 2 : 16;   // 32-column chunks per workgroup
             for (int j = 0; j < nu; j += group)
               tiles.push_back({id, b, i, j, 0, p.T, -1, mh, std::min(group, nu - j), 0});
             continue;
@@ -84,6 +150,20 @@ struct GemmStage {
             slots += split;
           }
         }
+    }
+    if (wave) {
+      // sort by shape class (rows 32? columns 32?), each class in XCD order of its own
+      std::vector<GemmTile> all(tiles.begin() + r.t0, tiles.end());
+      tiles.resize(r.t0);
+      for (int sh = 0; sh < 4; ++sh) {
+        const int c0 = int(tiles.size());
+        for (const GemmTile& t : all)
+          if ((t.mh == 2) * 2 + (t.nn == 2) == sh) tiles.push_back(t);
+        xcd_order(c0);
+        r.shape[sh] = int(tiles.size()) - c0;
+      }
+    } else {
+      xcd_order(r.t0);
     }
     r.nt = int(tiles.size()) - r.t0;
     r.nr = int(reds.size()) - r.r0;
@@ -182,9 +262,8 @@ struct DevState {
   // stages
   GemmStage p0_gemm, s_gemmA, s_gemmC, scr_fwd, scr_bwd, dys_fwd, dys_bwd, tb_1[3], tb_2[3], fb_1[3], fb_2[3];
   GemmStage lv1, lv2, lv3;
-  RowStage p0_right, p0_left, s_right;
+  RowStage p0_both, s_right;
   ListStage<CopySeg> p0_mirror, scr_herm, dys_herm, s_pack;
-  void* gtab = nullptr;     // (G offset, block-table offset) per outer group of fused GEMMs
   void* SCR = nullptr;      // full nao x nao self-energy products of one tau chunk
   ListStage<InvItem> scr_inv, dys_inv, mu_inv;
   ListStage<MuItem> mu_items;
@@ -243,6 +322,7 @@ GemmPlanDev plan_of(const GemmStage& g, const Range& r) {
   p.reds = static_cast<GemmReduce*>(g.d_reds) + r.r0;
   p.ntiles = r.nt;
   p.nreds = r.nr;
+  for (int i = 0; i < 4; ++i) p.shape[i] = r.shape[i];
   return p;
 }
 
@@ -282,6 +362,7 @@ int device_init(Ctx& c, void* stream) {
   c.dev_state = dp;
   DevState& d = *dp;
   const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nw = c.nw, nib = c.nibz;
+  d.p0_gemm.wave = d.s_gemmA.wave = d.s_gemmC.wave = true;
   int st;
   // U tables
   {
@@ -368,32 +449,18 @@ int device_init(Ctx& c, void* stream) {
   for (int i = 0; i < nib; ++i)
     for (int sz : c.bao[i].size) sumsq_ao[i] += double(sz) * sz;
   const double pscale = -c.prm.spin / nk;
-  // With nao <= 32 the right multiply by G^{k+q}(tau) is done on the A tiles inside the
-  // grouped GEMM (no intermediate); otherwise by the row-block kernel into W1.
-  const bool fuse = no <= 32;
-  if (c.prm.precision == GWSYM_FP32 && !fuse) {
-    c.err = "FP32 contractions need nao <= 32";
+  if (no * no > RBB_ELEMS) {
+    c.err = "orbital basis larger than 45 functions";
     return GWSYM_ESHAPE;
   }
-  std::vector<i64> gtab;
-  auto add_gtab = [&](const std::vector<int>& ks, int j) {
-    const i64 at = i64(gtab.size());
-    for (int kk : ks) {
-      const int ik = c.rep[kk];
-      gtab.push_back(c.g_off[ik] + i64(j) * c.bao[ik].packed);
-      gtab.push_back(d.bt_ao[ik]);
-    }
-    return at;
-  };
+  // P0^q(tau_j)[Q, Q'] = -(s/Nk) sum_k sum_(a,b) Vp(Q)_ab conj(W(Q')_ab) with
+  // W(Q') = G^k(beta - tau_j)^H Vp(Q') G^(k+q)(tau_j)^H, which equals the trace of eq. P0;
+  // W comes from one pass of the both-sided block multiply, then a plain grouped GEMM.
   for (int i = 0; i < nib; ++i) {
     const int q0 = c.ibz[i];
     const Blocks& BA = c.baux[i];
     std::vector<int> kq(nk);
-    double fused_macs = 0;
-    for (int k = 0; k < nk; ++k) {
-      kq[k] = mesh.add(k, q0);
-      fused_macs += double(no) * sumsq_ao[c.rep[kq[k]]];
-    }
+    for (int k = 0; k < nk; ++k) kq[k] = mesh.add(k, q0);
     for (int j0 = 0; j0 < nthalf; j0 += J) {
       const int j1 = std::min(nthalf, j0 + J);
       for (int j = j0; j < j1; ++j) {
@@ -402,36 +469,22 @@ int device_init(Ctx& c, void* stream) {
           const int ik = c.rep[k], ikq = c.rep[kq[k]];
           const i64 vp = (i64(i) * nk + k) * na * no * no;
           const i64 wo = (i64(jj) * nk + k) * na * no * no;
-          if (!fuse) {
-            RowSeg r{};
-            r.inbuf = B_VP; r.outbuf = B_W1; r.gbuf = B_G; r.blk = d.bt_ao[ikq];
-            r.in_off = vp; r.out_off = wo; r.g_off = c.g_off[ikq] + i64(j) * c.bao[ikq].packed; r.nrows = na * no;
-            d.p0_right.add(r, double(na) * no * sumsq_ao[ikq], double(na) * no * no);
-          }
-          RowSeg l{};
-          l.inbuf = B_VP; l.outbuf = B_W2; l.gbuf = B_G; l.blk = d.bt_ao[ik];
-          l.in_off = vp; l.out_off = wo; l.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed; l.nrows = na * no;
-          d.p0_left.add(l, double(na) * no * sumsq_ao[ik], double(na) * no * no);
+          RowSeg r{};
+          r.inbuf = B_VP; r.outbuf = B_W2; r.gbuf = B_G;
+          r.blk = d.bt_ao[ik]; r.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed;
+          r.blk2 = d.bt_ao[ikq]; r.g_off2 = c.g_off[ikq] + i64(j) * c.bao[ikq].packed;
+          r.in_off = vp; r.out_off = wo; r.nrows = na * no;
+          d.p0_both.add(r, double(na) * no * (sumsq_ao[ik] + sumsq_ao[ikq]), double(na) * no * no);
         }
-        const i64 gt = fuse ? add_gtab(kq, j) : 0;
         for (size_t sg = 0; sg < BA.size.size(); ++sg) {
           const int m = BA.size[sg], off = BA.off[sg];
-          const i64 w0 = i64(jj) * slab + i64(off) * no;
-          if (fuse) {
-            // A_(k,a) = Vp[i][k][a][rows s of block sg][:] G^{k+q0}(tau_j), outer index t = k nao + a
-            GemmProblem p = gp(m, m, no, nk * no, 1, B_VP, i64(i) * nk * na * no * no + i64(off) * no, no, i64(na) * no,
-                               0, OP_N, B_W2, w0, no, i64(na) * no, 0, OP_H, B_OUT,
-                               c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale);
-            p.gfuse = 1; p.gbuf = B_G; p.gdiv = no; p.gtab = gt;
-            d.p0_gemm.add(p, double(m) * m * no * nk * no + double(m) * fused_macs);
-          } else {
-            d.p0_gemm.add(gp(m, m, no, nk * no, 1, B_W1, w0, no, i64(na) * no, 0, OP_N, B_W2, w0, no, i64(na) * no, 0,
-                             OP_H, B_OUT, c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale));
-          }
+          // A_(k,a) = Vp[i][k][a][rows of block sg][:], B_(k,a) = W[k][a][rows of block sg][:]
+          d.p0_gemm.add(gp(m, m, no, nk * no, 1, B_VP, i64(i) * nk * na * no * no + i64(off) * no, no, i64(na) * no, 0,
+                           OP_N, B_W2, i64(jj) * slab + i64(off) * no, no, i64(na) * no, 0, OP_H, B_OUT,
+                           c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale));
         }
       }
-      d.p0_right.close();
-      d.p0_left.close();
+      d.p0_both.close();
       d.p0_gemm.close();
     }
     if (c.prm.half_tau)
@@ -443,10 +496,9 @@ int device_init(Ctx& c, void* stream) {
   d.p0_mirror.close();
 
   // ---------------- self-energy (eq. sigma, Alg. 4) ----------------
-  std::vector<int> allk(nk);
-  std::iota(allk.begin(), allk.end(), 0);
-  double sfused_macs = 0;
-  for (int kp = 0; kp < nk; ++kp) sfused_macs += double(na) * no * sumsq_ao[c.rep[kp]];
+  // Y(k', s') = P_blk^T Vs (per auxiliary block), Z = Y G^{k'}(tau_j) (block multiply),
+  // Sigma = -(1/Nk) sum_(k', s') Z Vs^H over all orbital blocks of k0 at once, then the
+  // diagonal blocks are gathered into Sigma_blk; only the block work is counted.
   for (int i = 0; i < nib; ++i) {
     const int k0 = c.ibz[i];
     const Blocks& BO = c.bao[i];
@@ -454,31 +506,6 @@ int device_init(Ctx& c, void* stream) {
       const int j1 = std::min(nt, j0 + J);
       for (int j = j0; j < j1; ++j) {
         const int jj = j - j0;
-        for (int kp = 0; kp < nk && fuse; ++kp) {
-          const int q = mesh.sub(k0, kp), iq = c.rep[q];
-          const Blocks& BQ = c.baux[iq];
-          const i64 vs = (i64(i) * nk + kp) * na * no * no;
-          const i64 wo = (i64(jj) * nk + kp) * na * no * no;
-          for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
-            const int m = BQ.size[sg], off = BQ.off[sg];
-            d.s_gemmA.add(gp(m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j) * BQ.packed + BQ.poff[sg], m, 0, 0, OP_T, B_VS,
-                             vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1, wo + i64(off) * no * no, i64(no) * no, 0));
-          }
-        }
-        if (fuse) {
-          // Sigma = sum_(k',s') [Y(k',s') G^{k'}(tau_j)] Vs(k',s')^H with the G factor applied on the A tiles
-          GemmProblem p = gp(no, no, no, nk * na, 1, B_W1, i64(jj) * slab, no, i64(no) * no, 0, OP_N, B_VS,
-                             i64(i) * nk * na * no * no, no, i64(no) * no, 0, OP_H, B_SCR, i64(jj) * no * no, no, 0,
-                             -1.0 / nk);
-          p.gfuse = 1; p.gbuf = B_G; p.gdiv = na; p.gtab = add_gtab(allk, j);
-          d.s_gemmC.add(p, sumsq_ao[i] * no * double(nk) * na + sfused_macs);
-          for (size_t rb = 0; rb < BO.size.size(); ++rb) {
-            const int n = BO.size[rb], off = BO.off[rb];
-            d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(jj) * no * no + i64(off) * no + off,
-                                      c.g_off[i] + i64(j) * BO.packed + BO.poff[rb], no});
-          }
-          continue;
-        }
         for (int kp = 0; kp < nk; ++kp) {
           const int q = mesh.sub(k0, kp), iq = c.rep[q], ik = c.rep[kp];
           const Blocks& BQ = c.baux[iq];
@@ -486,7 +513,6 @@ int device_init(Ctx& c, void* stream) {
           const i64 wo = (i64(jj) * nk + kp) * na * no * no;
           for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
             const int m = BQ.size[sg], off = BQ.off[sg];
-            // Y = P_blk^T Vs  (rows s' of block sg)
             d.s_gemmA.add(gp(m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j) * BQ.packed + BQ.poff[sg], m, 0, 0, OP_T, B_VS,
                              vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1, wo + i64(off) * no * no, i64(no) * no, 0));
           }
@@ -495,8 +521,6 @@ int device_init(Ctx& c, void* stream) {
           r.in_off = wo; r.out_off = wo; r.g_off = c.g_off[ik] + i64(j) * c.bao[ik].packed; r.nrows = na * no;
           d.s_right.add(r, double(na) * no * sumsq_ao[ik], double(na) * no * no);
         }
-        // All orbital blocks of k0 in one product (one tile per 32 x 32 of nao x nao), then the
-        // diagonal blocks are gathered into Sigma_blk; only the block work is counted.
         d.s_gemmC.add(gp(no, no, no, nk * na, 1, B_W2, i64(jj) * slab, no, i64(no) * no, 0, OP_N, B_VS,
                          i64(i) * nk * na * no * no, no, i64(no) * no, 0, OP_H, B_SCR, i64(jj) * no * no, no, 0,
                          -1.0 / nk),
@@ -616,9 +640,8 @@ int device_init(Ctx& c, void* stream) {
   for (int kind = 0; kind < 3; ++kind)
     for (GemmStage* g : {&d.tb_1[kind], &d.tb_2[kind], &d.fb_1[kind], &d.fb_2[kind]})
       if ((st = upload_stage(c, d, *g, s))) return st;
-  for (RowStage* r : {&d.p0_right, &d.p0_left, &d.s_right})
+  for (RowStage* r : {&d.p0_both, &d.s_right})
     if ((st = upload(c, d, r->segs, &r->d, s))) return st;
-  if ((st = upload(c, d, gtab, &d.gtab, s))) return st;
   for (auto* l : {&d.p0_mirror, &d.scr_herm, &d.dys_herm, &d.s_pack})
     if ((st = upload(c, d, l->items, &l->d, s))) return st;
   for (auto* l : {&d.scr_inv, &d.dys_inv, &d.mu_inv})
@@ -698,7 +721,6 @@ Bases bases_of(DevState& d) {
   b.p[B_U] = d.U;
   b.p[B_WT] = d.WT;
   b.p[B_SCR] = d.SCR;
-  b.p[B_GT] = d.gtab;
   b.p[B_BT] = d.btab;
   return b;
 }
@@ -920,14 +942,11 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
     mask = 1u << B_W2;
   }
   for (size_t l = 0; l < d.p0_gemm.launches.size(); ++l) {
-    const Range& rr = d.p0_right.launches[l];
-    RowSegList R{static_cast<RowSeg*>(d.p0_right.d) + rr.t0, rr.nt, rr.r0};
-    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s); }, rr.bytes);
-    const Range& rl = d.p0_left.launches[l];
-    RowSegList L{static_cast<RowSeg*>(d.p0_left.d) + rl.t0, rl.nt, rl.r0};
-    timed(d, s, PC_LEFT, rl.macs, [&] { launch_rowblock_left(L, b, d.btab, c.nao, s, f32); }, rl.bytes);
+    const Range& rb = d.p0_both.launches[l];
+    RowSegList L{static_cast<RowSeg*>(d.p0_both.d) + rb.t0, rb.nt, rb.r0};
+    timed(d, s, PC_LEFT, rb.macs, [&] { launch_rowblock_both(L, b, d.btab, c.nao, s, f32); }, rb.bytes);
     const Range& rg = d.p0_gemm.launches[l];
-    timed(d, s, PC_P0, rg.macs, [&] { launch_brgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, f32, mask); });
+    timed(d, s, PC_P0, rg.macs, [&] { launch_wgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, f32, mask); }, rg.bytes);
   }
   const Range& m = d.p0_mirror.launches[0];
   timed(d, s, PC_OTHER, 0, [&] { launch_copy(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s); });
@@ -953,16 +972,16 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
     b.p[B_G] = d.G32;
     b.p[B_P] = d.P32;
     b.p[B_VS] = d.VS32;
-    mask = 1u << B_W1;
+    mask = (1u << B_W1) | (1u << B_W2);
   }
   for (size_t l = 0; l < d.s_gemmA.launches.size(); ++l) {
     const Range& ra = d.s_gemmA.launches[l];
-    timed(d, s, PC_SA, ra.macs, [&] { launch_brgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, f32, mask); });
+    timed(d, s, PC_SA, ra.macs, [&] { launch_wgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, f32, mask); }, ra.bytes);
     const Range& rr = d.s_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
-    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s); }, rr.bytes);
+    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s, f32); }, rr.bytes);
     const Range& rc = d.s_gemmC.launches[l];
-    timed(d, s, PC_SC, rc.macs, [&] { launch_brgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, f32, mask); });
+    timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, f32, mask); }, rc.bytes);
     const Range& rp = d.s_pack.launches[l];
     timed(d, s, PC_OTHER, 0, [&] { launch_pack(static_cast<CopySeg*>(d.s_pack.d) + rp.t0, rp.nt, b, s); });
   }

@@ -72,7 +72,7 @@ EXPORTED = ["gwsym_create", "gwsym_destroy", "gwsym_last_error", "gwsym_build_sy
             "gwsym_profile", "gwsym_profile_read"]
 
 PROFILE_CLASSES = ["p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction", "row_block_multiply",
-                   "col_block_multiply", "transforms", "inverses", "other"]
+                   "two_sided_block_multiply", "transforms", "inverses", "other"]
 
 
 class GwsymError(RuntimeError):
