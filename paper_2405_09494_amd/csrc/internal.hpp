@@ -70,6 +70,11 @@ struct GemmProblem {
   int gfuse;
   int gbuf, gdiv, pad_;
   i64 gtab;
+  // Row and column batches (wave-tile kernel): row r of A and C is row r % rdiv of batch
+  // r / rdiv, whose A and C start sArb and sCrb elements further on; column n of B and C is
+  // column n % cdiv of batch n / cdiv, offset by sBcb and sCcb.  rdiv = M, cdiv = N: none.
+  int rdiv, cdiv;
+  i64 sArb, sCrb, sBcb, sCcb;
 };
 
 // An output tile of one problem over the outer range [t0, t1), in units of 16: rows

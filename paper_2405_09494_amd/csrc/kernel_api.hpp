@@ -36,8 +36,11 @@ struct RowSeg {
   int64_t g_off2;
 };
 
-// Tile elements per workgroup of the both-sided block multiply; one n x n matrix must fit.
-constexpr int RBB_ELEMS = 2048;
+// n x n matrices per workgroup of the both-sided block multiply (at most 64 columns, n <= 32)
+__host__ __device__ inline int rbb_nq(int n) {
+  const int q = 64 / n;
+  return q > 1 ? q : 1;
+}
 
 struct RowSegList {
   void* segs = nullptr;
@@ -75,12 +78,12 @@ void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStre
 void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s);
 void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s,
                            bool fp32 = false);
-void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s, bool fp32);
+// gmax: largest packed block-diagonal matrix (sum of squared block sizes) among the factors
+void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, int gmax, hipStream_t s,
+                          bool fp32);
 // Wave-tile complex GEMM over the same problem and tile lists (tiles of at most 32 x 32).
 void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, bool fp32,
                   unsigned f32mask);
-void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s,
-                          bool fp32 = false);
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s);

@@ -1,12 +1,14 @@
 // HIP kernels of libgwsym for gfx950 (MI355X).
 //
-//  k_brgemm       grouped batch-reduce complex GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64):
-//                 every contraction stage, transform and basis change is a list of
-//                 problems C_b = alpha sum_t opA(A_{b,t}) opB(B_{b,t}) + beta C_b with uneven
-//                 sizes, run as one launch over a precomputed tile list.
+//  k_wgemm        grouped batch-reduce complex GEMM for the P0 and Sigma contractions: one
+//                 wave per tile of up to 32 x 32, MFMA operands loaded straight from HBM.
+//  k_brgemm       the same problem lists with 32 x 32 workgroup tiles staged through LDS
+//                 (transforms, block changes of basis): C_b = alpha sum_t opA(A_{b,t})
+//                 opB(B_{b,t}) + beta C_b with uneven sizes, one launch per tile list.
 //  k_reduce       ordered sum of split-K partial tiles (deterministic, no atomics).
-//  k_rowblock_*   multiply many rows (columns) by a small block-diagonal matrix: the
-//                 G-sandwich stages of P0 and Sigma, which have K = block size.
+//  k_rowblock_*   multiply many rows by a small block-diagonal matrix from the right, or
+//                 n x n matrices by two of them from both sides: the Green's function
+//                 factors of the Sigma and P0 contractions.
 //  k_inverse      batched Gauss-Jordan inverses for the two Dyson equations.
 //  k_jacobi_g0    batched Hermitian Jacobi eigen-decomposition and the free G0(tau).
 //  k_herm, k_copy packed-block helpers; k_mu_* the chemical-potential bisection.
@@ -75,6 +77,12 @@ __device__ __forceinline__ int mrow(float, int lane, int j) { return 4 * (lane >
 __device__ __forceinline__ void slot_pos(int idx, bool kfast, int lg16, int& x, int& k) {
   if (kfast) { x = idx >> 5; k = idx & (BK - 1); }
   else { k = idx >> (4 + lg16); x = idx & ((16 << lg16) - 1); }
+}
+
+// offset of element (row, col) of C within one batch, row and column batches included
+__device__ __forceinline__ int64_t c_offset(const GemmProblem& P, int row, int col) {
+  const int rb = row / P.rdiv, cb = col / P.cdiv;
+  return rb * P.sCrb + int64_t(row - rb * P.rdiv) * P.ldc + cb * P.sCcb + (col - cb * P.cdiv);
 }
 
 // TAG only separates the stages in profiles (P0, Sigma aux / orbital contractions, others).
@@ -310,7 +318,7 @@ __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ 
     double2 s = make_double2(0.0, 0.0);
     for (int q = 0; q < rd.nslot; ++q) s = cadd(s, partials[int64_t(rd.slot0 + q) * TM * TN + e]);
     double2 v = cmul(al, s);
-    const int64_t at = P.coff + int64_t(rd.batch) * P.sCb + int64_t(row) * P.ldc + cc;
+    const int64_t at = P.coff + int64_t(rd.batch) * P.sCb + c_offset(P, row, cc);
     if (cf32) {
       float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
       if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
@@ -349,12 +357,19 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   const int K = P.K, nk4 = (K + 3) >> 2;
   const bool aT = P.opA & 1, bT = P.opB & 1;
   const R sA = (P.opA & 2) ? R(-1) : R(1), sB = (P.opB & 2) ? R(-1) : R(1);
-  // element offset of (row or column x, k): x * ldx + k (k contiguous) or k * ldx + x
-  const int ra0 = min(m0 + li, P.M - 1), ra1 = min(m0 + 16 + li, P.M - 1);
-  const int cb0 = min(n0 + li, P.N - 1), cb1 = min(n0 + 16 + li, P.N - 1);
-  const int64_t ax0 = aT ? ra0 : int64_t(ra0) * P.lda, ax1 = aT ? ra1 : int64_t(ra1) * P.lda;
+  // element offset of (row or column x, k): x * ldx + k (k contiguous) or k * ldx + x, plus
+  // the offset of the row (column) batch that x falls in
+  auto arow = [&](int r) -> int64_t {
+    const int rb = r / P.rdiv, rl = r - rb * P.rdiv;
+    return rb * P.sArb + (aT ? int64_t(rl) : int64_t(rl) * P.lda);
+  };
+  auto bcol = [&](int c) -> int64_t {
+    const int cb = c / P.cdiv, cl = c - cb * P.cdiv;
+    return cb * P.sBcb + (bT ? int64_t(cl) * P.ldb : int64_t(cl));
+  };
+  const int64_t ax0 = arow(min(m0 + li, P.M - 1)), ax1 = arow(min(m0 + 16 + li, P.M - 1));
   const int64_t ak = aT ? P.lda : 1;
-  const int64_t bx0 = bT ? int64_t(cb0) * P.ldb : cb0, bx1 = bT ? int64_t(cb1) * P.ldb : cb1;
+  const int64_t bx0 = bcol(min(n0 + li, P.N - 1)), bx1 = bcol(min(n0 + 16 + li, P.N - 1));
   const int64_t bk = bT ? 1 : P.ldb;
   const int nsub = (tl.t1 - tl.t0) * nk4, npair = (nsub + 1) >> 1;
   A4 c00r = {0, 0, 0, 0}, c00i = c00r, c01r = c00r, c01i = c00r, c10r = c00r, c10i = c00r, c11r = c00r, c11i = c00r;
@@ -447,7 +462,7 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       const int gr = m0 + row, gc = n0 + col;
       if (gr >= P.M || gc >= P.N) continue;
       double2 v = cmul(al, make_double2(double(cr[j]), double(ci[j])));
-      const int64_t at = P.coff + int64_t(tl.batch) * P.sCb + int64_t(gr) * P.ldc + gc;
+      const int64_t at = P.coff + int64_t(tl.batch) * P.sCb + c_offset(P, gr, gc);
       if (cf32) {
         float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
         if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
@@ -554,6 +569,9 @@ void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s) {
 
 constexpr int RB_ROWS = 64;
 
+// Right multiply of RB_ROWS rows of ncol (<= 32) columns by a block-diagonal matrix: thread
+// (column c, row group g) forms out[r][c] = sum over k in the block of c of X[r][k] G[k][c] for
+// the rows r = g, g + 8, ...; each G element is read once and used for all those rows.
 template <typename V2>
 __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict__ segs, Bases bases,
                                                         const int* __restrict__ btab, int ncol) {
@@ -568,39 +586,46 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
   const int* bt = btab + sg.blk;  // bt[0] = count, then (off, size, poff) per block
   V2* tile = reinterpret_cast<V2*>(lds_rr);               // nrows x ncol
   V2* gs = tile + RB_ROWS * ncol;                          // packed blocks, ncol^2 at most
-  int* colblk = reinterpret_cast<int*>(gs + ncol * ncol);  // per column: block index
   const int nb = bt[0];
   const int gsz = bt[3 * nb] + bt[3 * nb - 1] * bt[3 * nb - 1];   // poff + size^2 of the last block
   for (int e = threadIdx.x; e < gsz; e += 256) gs[e] = G[e];
   for (int e = threadIdx.x; e < nrows * ncol; e += 256) tile[e] = in[e];
-  for (int c = threadIdx.x; c < ncol; c += 256)
-    for (int b = 0; b < nb; ++b)
-      if (c >= bt[1 + 3 * b] && c < bt[1 + 3 * b] + bt[2 + 3 * b]) colblk[c] = b;
   __syncthreads();
-  for (int e = threadIdx.x; e < nrows * ncol; e += 256) {
-    const int row = e / ncol, c = e % ncol;
-    const int b = colblk[c];
-    const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
-    const int cc = c - off;
-    V2 s = {0, 0};
-    for (int k = 0; k < sz; ++k) {
-      const V2 x = tile[row * ncol + off + k], g = gs[po + k * sz + cc];
-      s.x += x.x * g.x - x.y * g.y;
-      s.y += x.x * g.y + x.y * g.x;
+  const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+  if (c >= ncol) return;
+  int b = 0;
+  while (b + 1 < nb && c >= bt[1 + 3 * (b + 1)]) ++b;
+  const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b], cc = c - off;
+  V2 acc[RB_ROWS / 8];
+#pragma unroll
+  for (int i = 0; i < RB_ROWS / 8; ++i) acc[i] = V2{0, 0};
+  for (int k = 0; k < sz; ++k) {
+    const V2 gv = gs[po + k * sz + cc];
+#pragma unroll
+    for (int i = 0; i < RB_ROWS / 8; ++i) {
+      const V2 x = tile[(g + 8 * i) * ncol + off + k];
+      acc[i].x += x.x * gv.x - x.y * gv.y;
+      acc[i].y += x.x * gv.y + x.y * gv.x;
     }
-    out[e] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < RB_ROWS / 8; ++i) {
+    const int r = g + 8 * i;
+    if (r < nrows) out[r * ncol + c] = acc[i];
   }
 }
 
 // X -> Gl^H X Gr^H for nq square n x n matrices side by side per workgroup (the polarization's
-// second factor with both Green's function blocks applied in one pass over the slab).
-
+// second factor with both Green's function blocks applied in one pass over the slab).  The
+// tile is at most 64 columns wide: lane = column, wave w = rows w, w + 4, ...; each Green's
+// function element is read once per lane and used for all of its rows, and the intermediate
+// stays in LDS.
 template <typename V2>
 __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict__ segs, Bases bases,
                                                        const int* __restrict__ btab, int n) {
   extern __shared__ double2 lds_rb[];
   const RowSeg sg = segs[blockIdx.y];
-  const int nq = max(1, RBB_ELEMS / (n * n)), w = nq * n;
+  const int nq = rbb_nq(n), w = nq * n;
   const int c0 = blockIdx.x * w;
   const int ncols = sg.nrows;   // slab width: whole matrices side by side
   if (c0 >= ncols) return;
@@ -617,100 +642,71 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
   const int szl = btl[3 * nbl] + btl[3 * nbl - 1] * btl[3 * nbl - 1];
   const int szr = btr[3 * nbr] + btr[3 * nbr - 1] * btr[3 * nbr - 1];
   V2* gr = gl + szl;
-  int* idx = reinterpret_cast<int*>(gr + szr);  // per index: block of the left, block of the right
+  int* info = reinterpret_cast<int*>(gr + szr);   // per index: (off, size, poff) of its block, left then right
   for (int e = threadIdx.x; e < szl; e += 256) gl[e] = Gl[e];
   for (int e = threadIdx.x; e < szr; e += 256) gr[e] = Gr[e];
   for (int c = threadIdx.x; c < n; c += 256) {
     int bl = 0, br = 0;
     while (bl + 1 < nbl && c >= btl[1 + 3 * (bl + 1)]) ++bl;
     while (br + 1 < nbr && c >= btr[1 + 3 * (br + 1)]) ++br;
-    idx[c] = bl;
-    idx[n + c] = br;
+    info[3 * c] = btl[1 + 3 * bl];
+    info[3 * c + 1] = btl[2 + 3 * bl];
+    info[3 * c + 2] = btl[3 + 3 * bl];
+    info[3 * (n + c)] = btr[1 + 3 * br];
+    info[3 * (n + c) + 1] = btr[2 + 3 * br];
+    info[3 * (n + c) + 2] = btr[3 + 3 * br];
   }
-  for (int e = threadIdx.x; e < n * w; e += 256) {
-    const int r = e / w, c = e % w;
-    V2 z = {0, 0};
-    tile[e] = c < wv ? in[int64_t(r) * ncols + c] : z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < n; r += 4) {
+    V2 v = {0, 0};
+    if (lane < wv) v = in[int64_t(r) * ncols + lane];
+    if (lane < w) tile[r * w + lane] = v;
   }
   __syncthreads();
-  // left: row a' of Gl^H X = sum over a in the block of a' of conj(Gl[a][a']) X[a][:]
-  V2 acc[RBB_ELEMS / 256];
+  constexpr int RPW = 8;   // rows per wave: n <= 32
+  V2 acc[RPW];
+  // left: Y[a'][col] = sum over a in the block of a' of conj(Gl[a][a']) X[a][col]
 #pragma unroll
-  for (int q = 0; q < RBB_ELEMS / 256; ++q) {
-    const int e = threadIdx.x + 256 * q;
+  for (int i = 0; i < RPW; ++i) {
+    const int ap = wave + 4 * i;
     V2 s = {0, 0};
-    if (e < n * w) {
-      const int ap = e / w, c = e % w, b = idx[ap];
-      const int off = btl[1 + 3 * b], sz = btl[2 + 3 * b], po = btl[3 + 3 * b], rr = ap - off;
+    if (ap < n) {
+      const int off = info[3 * ap], sz = info[3 * ap + 1], po = info[3 * ap + 2], rr = ap - off;
       for (int k = 0; k < sz; ++k) {
-        const V2 g = gl[po + k * sz + rr], x = tile[(off + k) * w + c];
+        const V2 g = gl[po + k * sz + rr], x = tile[(off + k) * w + lane];
         s.x += g.x * x.x + g.y * x.y;
         s.y += g.x * x.y - g.y * x.x;
       }
     }
-    acc[q] = s;
+    acc[i] = s;
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < RBB_ELEMS / 256; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    if (e < n * w) tile[e] = acc[q];
+  for (int i = 0; i < RPW; ++i) {
+    const int ap = wave + 4 * i;
+    if (ap < n && lane < w) tile[ap * w + lane] = acc[i];
   }
   __syncthreads();
-  // right: column b' of Y Gr^H = sum over b in the block of b' of Y[:][b] conj(Gr[b'][b])
-  for (int e = threadIdx.x; e < n * w; e += 256) {
-    const int r = e / w, c = e % w;
-    if (c >= wv) continue;
-    const int mq = c / n, bp = c % n, b = idx[n + bp];
-    const int off = btr[1 + 3 * b], sz = btr[2 + 3 * b], po = btr[3 + 3 * b], cc = bp - off;
-    V2 s = {0, 0};
-    for (int k = 0; k < sz; ++k) {
-      const V2 y = tile[r * w + mq * n + off + k], g = gr[po + cc * sz + k];
-      s.x += y.x * g.x + y.y * g.y;
-      s.y += y.y * g.x - y.x * g.y;
+  if (lane >= wv) return;
+  // right: W[a][q n + b'] = sum over b in the block of b' of Y[a][q n + b] conj(Gr[b'][b])
+  const int mq = lane / n, bp = lane - mq * n;
+  const int off = info[3 * (n + bp)], sz = info[3 * (n + bp) + 1], po = info[3 * (n + bp) + 2], cc = bp - off;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) acc[i] = V2{0, 0};
+  for (int k = 0; k < sz; ++k) {
+    const V2 g = gr[po + cc * sz + k];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int a = wave + 4 * i;
+      const V2 y = tile[min(a, n - 1) * w + mq * n + off + k];
+      acc[i].x += y.x * g.x + y.y * g.y;
+      acc[i].y += y.y * g.x - y.x * g.y;
     }
-    out[int64_t(r) * ncols + c] = s;
   }
-}
-
-constexpr int CB_COLS = 64;
-
-template <typename V2>
-__global__ __launch_bounds__(256) void k_rowblock_left(const RowSeg* __restrict__ segs, Bases bases,
-                                                       const int* __restrict__ btab, int nb_rows) {
-  extern __shared__ double2 lds_raw[];
-  V2* tile = reinterpret_cast<V2*>(lds_raw);  // nb_rows x CB_COLS
-  const RowSeg sg = segs[blockIdx.y];
-  const int c0 = blockIdx.x * CB_COLS;
-  const int ncols = sg.nrows;  // for left segments nrows holds the slab width
-  if (c0 >= ncols) return;
-  const int nc = min(CB_COLS, ncols - c0);
-  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
-  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
-  const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
-  const int* bt = btab + sg.blk;
-  for (int e = threadIdx.x; e < nb_rows * CB_COLS; e += 256) {
-    const int r = e / CB_COLS, c = e % CB_COLS;
-    V2 z = {0, 0};
-    tile[e] = c < nc ? in[int64_t(r) * ncols + c] : z;
-  }
-  __syncthreads();
-  const int nblk = bt[0];
-  for (int e = threadIdx.x; e < nb_rows * CB_COLS; e += 256) {
-    const int rp = e / CB_COLS, c = e % CB_COLS;
-    if (c >= nc) continue;
-    int b = 0;
-    while (b + 1 < nblk && rp >= bt[1 + 3 * (b + 1)]) ++b;
-    const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b];
-    const int rr = rp - off;
-    V2 s = {0, 0};
-    // (G^H)[rr][k] = conj(G[k][rr])
-    for (int k = 0; k < sz; ++k) {
-      const V2 g = G[po + k * sz + rr], x = tile[(off + k) * CB_COLS + c];
-      s.x += g.x * x.x + g.y * x.y;
-      s.y += g.x * x.y - g.y * x.x;
-    }
-    out[int64_t(rp) * ncols + c] = s;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int a = wave + 4 * i;
+    if (a < n) out[int64_t(a) * ncols + lane] = acc[i];
   }
 }
 
@@ -728,12 +724,13 @@ void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab,
                        b, btab, ncol);
 }
 
-void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s, bool fp32) {
+void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, int gmax, hipStream_t s,
+                          bool fp32) {
   if (l.nseg == 0) return;
-  const int w = std::max(1, RBB_ELEMS / (n * n)) * n;
+  const int w = rbb_nq(n) * n;
   const dim3 g((l.maxrows + w - 1) / w, l.nseg);
-  const size_t el = size_t(n) * w + 2 * size_t(n) * n;
-  const size_t ex = 2 * n * sizeof(int) + 16;
+  const size_t el = size_t(n) * w + 2 * size_t(gmax);
+  const size_t ex = 6 * n * sizeof(int) + 16;
   if (fp32)
     hipLaunchKernelGGL(k_rowblock_both<float2>, g, dim3(256), el * sizeof(float2) + ex, s, (const RowSeg*)l.segs, b,
                        btab, n);
@@ -742,17 +739,6 @@ void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, 
                        b, btab, n);
 }
 
-void launch_rowblock_left(const RowSegList& l, const Bases& b, const int* btab, int nb_rows, hipStream_t s,
-                          bool fp32) {
-  if (l.nseg == 0) return;
-  const dim3 g((l.maxrows + CB_COLS - 1) / CB_COLS, l.nseg);
-  if (fp32)
-    hipLaunchKernelGGL(k_rowblock_left<float2>, g, dim3(256), size_t(nb_rows) * CB_COLS * sizeof(float2), s,
-                       (const RowSeg*)l.segs, b, btab, nb_rows);
-  else
-    hipLaunchKernelGGL(k_rowblock_left<double2>, g, dim3(256), size_t(nb_rows) * CB_COLS * sizeof(double2), s,
-                       (const RowSeg*)l.segs, b, btab, nb_rows);
-}
 
 // ----------------------------------------------------------------------------
 // Packed-block helpers.

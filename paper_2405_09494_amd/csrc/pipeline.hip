@@ -128,7 +128,8 @@ struct GemmStage {
       const GemmProblem& p = probs[id];
       const int mu = units(p.M), nu = units(p.N);
       int split = 1;
-      if (base < target && p.T >= 8) split = int(std::min<long>(p.T / 4, (target + base - 1) / std::max(1L, base)));
+      if (base < target && p.T >= 8)
+        split = int(std::min<long>(std::min<long>(p.T / 4, 256), (target + base - 1) / std::max(1L, base)));
       split = std::max(1, split);
       for (int b = 0; b < p.batch; ++b)
         for (int i = 0; i < mu; i += 2) {
@@ -270,6 +271,7 @@ struct DevState {
   ListStage<EigItem> g0_items;
   std::vector<void*> allocs;
   Prof prof;
+  int gmax = 0;                          // largest packed orbital block-diagonal matrix
   hipGraphExec_t graph_exec = nullptr;   // captured iteration and the arguments it was captured with
   std::vector<const void*> graph_key;
   double graph_ntarget = 0;
@@ -335,6 +337,7 @@ GemmProblem gp(int M, int N, int K, int T, int batch, int abuf, i64 aoff, i64 ld
   p.bbuf = bbuf; p.boff = boff; p.ldb = ldb; p.sBt = sBt; p.sBb = sBb; p.opB = opB;
   p.cbuf = cbuf; p.coff = coff; p.ldc = ldc; p.sCb = sCb;
   p.alpha_re = are; p.alpha_im = aim; p.beta = beta;
+  p.rdiv = M; p.cdiv = N;
   return p;
 }
 
@@ -363,6 +366,7 @@ int device_init(Ctx& c, void* stream) {
   DevState& d = *dp;
   const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nw = c.nw, nib = c.nibz;
   d.p0_gemm.wave = d.s_gemmA.wave = d.s_gemmC.wave = true;
+  for (int i = 0; i < nib; ++i) d.gmax = std::max<int>(d.gmax, int(c.bao[i].packed));
   int st;
   // U tables
   {
@@ -449,8 +453,8 @@ int device_init(Ctx& c, void* stream) {
   for (int i = 0; i < nib; ++i)
     for (int sz : c.bao[i].size) sumsq_ao[i] += double(sz) * sz;
   const double pscale = -c.prm.spin / nk;
-  if (no * no > RBB_ELEMS) {
-    c.err = "orbital basis larger than 45 functions";
+  if (no > 32) {   // the block multiplies give each orbital column one lane
+    c.err = "orbital basis larger than 32 functions";
     return GWSYM_ESHAPE;
   }
   // P0^q(tau_j)[Q, Q'] = -(s/Nk) sum_k sum_(a,b) Vp(Q)_ab conj(W(Q')_ab) with
@@ -476,13 +480,20 @@ int device_init(Ctx& c, void* stream) {
           r.in_off = vp; r.out_off = wo; r.nrows = na * no;
           d.p0_both.add(r, double(na) * no * (sumsq_ao[ik] + sumsq_ao[ikq]), double(na) * no * no);
         }
-        for (size_t sg = 0; sg < BA.size.size(); ++sg) {
-          const int m = BA.size[sg], off = BA.off[sg];
-          // A_(k,a) = Vp[i][k][a][rows of block sg][:], B_(k,a) = W[k][a][rows of block sg][:]
-          d.p0_gemm.add(gp(m, m, no, nk * no, 1, B_VP, i64(i) * nk * na * no * no + i64(off) * no, no, i64(na) * no, 0,
-                           OP_N, B_W2, i64(jj) * slab + i64(off) * no, no, i64(na) * no, 0, OP_H, B_OUT,
-                           c.p_off[i] + i64(j) * BA.packed + BA.poff[sg], m, 0, pscale));
-        }
+      }
+      // one problem per auxiliary block for all tau of the chunk: the columns are (tau, Q'), so
+      // the Vp rows of the block are read once for every tau and small blocks fill the tiles
+      const int jc = j1 - j0;
+      for (size_t sg = 0; sg < BA.size.size(); ++sg) {
+        const int m = BA.size[sg], off = BA.off[sg];
+        // A_(k,a) = Vp[i][k][a][rows of block sg][:], B_(k,a) = W[tau][k][a][rows of block sg][:]
+        GemmProblem p = gp(m, jc * m, no, nk * no, 1, B_VP, i64(i) * nk * na * no * no + i64(off) * no, no,
+                           i64(na) * no, 0, OP_N, B_W2, i64(off) * no, no, i64(na) * no, 0, OP_H, B_OUT,
+                           c.p_off[i] + i64(j0) * BA.packed + BA.poff[sg], m, 0, pscale);
+        p.cdiv = m;
+        p.sBcb = slab;
+        p.sCcb = BA.packed;
+        d.p0_gemm.add(p, double(jc) * m * m * no * nk * no);
       }
       d.p0_both.close();
       d.p0_gemm.close();
@@ -511,15 +522,30 @@ int device_init(Ctx& c, void* stream) {
           const Blocks& BQ = c.baux[iq];
           const i64 vs = (i64(i) * nk + kp) * na * no * no;
           const i64 wo = (i64(jj) * nk + kp) * na * no * no;
-          for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
-            const int m = BQ.size[sg], off = BQ.off[sg];
-            d.s_gemmA.add(gp(m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j) * BQ.packed + BQ.poff[sg], m, 0, 0, OP_T, B_VS,
-                             vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1, wo + i64(off) * no * no, i64(no) * no, 0));
-          }
           RowSeg r{};
           r.inbuf = B_W1; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
           r.in_off = wo; r.out_off = wo; r.g_off = c.g_off[ik] + i64(j) * c.bao[ik].packed; r.nrows = na * no;
           d.s_right.add(r, double(na) * no * sumsq_ao[ik], double(na) * no * no);
+        }
+        if (j == j0) {
+          // Y = P_blk^T Vs with the rows (tau, s') of all tau of the chunk in one problem per
+          // (k', auxiliary block): the Vs rows are read once for every tau
+          const int jc = j1 - j0;
+          for (int kp = 0; kp < nk; ++kp) {
+            const int q = mesh.sub(k0, kp), iq = c.rep[q];
+            const Blocks& BQ = c.baux[iq];
+            const i64 vs = (i64(i) * nk + kp) * na * no * no;
+            for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
+              const int m = BQ.size[sg], off = BQ.off[sg];
+              GemmProblem p = gp(jc * m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j0) * BQ.packed + BQ.poff[sg], m, 0, 0,
+                                 OP_T, B_VS, vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1,
+                                 i64(kp) * na * no * no + i64(off) * no * no, i64(no) * no, 0);
+              p.rdiv = m;
+              p.sArb = BQ.packed;
+              p.sCrb = slab;
+              d.s_gemmA.add(p);
+            }
+          }
         }
         d.s_gemmC.add(gp(no, no, no, nk * na, 1, B_W2, i64(jj) * slab, no, i64(no) * no, 0, OP_N, B_VS,
                          i64(i) * nk * na * no * no, no, i64(no) * no, 0, OP_H, B_SCR, i64(jj) * no * no, no, 0,
@@ -944,7 +970,7 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
   for (size_t l = 0; l < d.p0_gemm.launches.size(); ++l) {
     const Range& rb = d.p0_both.launches[l];
     RowSegList L{static_cast<RowSeg*>(d.p0_both.d) + rb.t0, rb.nt, rb.r0};
-    timed(d, s, PC_LEFT, rb.macs, [&] { launch_rowblock_both(L, b, d.btab, c.nao, s, f32); }, rb.bytes);
+    timed(d, s, PC_LEFT, rb.macs, [&] { launch_rowblock_both(L, b, d.btab, c.nao, d.gmax, s, f32); }, rb.bytes);
     const Range& rg = d.p0_gemm.launches[l];
     timed(d, s, PC_P0, rg.macs, [&] { launch_wgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, f32, mask); }, rg.bytes);
   }
