@@ -143,10 +143,11 @@ def profile_step(path, torch):
 
 
 def cpu_baseline(wl, F_all, V_all, ibz_rep_q, torch):
-    """The FP64 oracle on the host: one P0 output (one q, one tau, every k) and one Sigma
-    output (one k, one tau, every q), the screened interaction and one Dyson solve at the
-    workload's shapes; extrapolated to a full iteration (every q, k and tau; 65 Dyson
-    solves for the bisection)."""
+    """The FP64 oracle (full matrices, no symmetry) on the host, timed on a bounded sample of
+    one iteration at the workload's shapes: 32 P0 outputs (one q, 32 tau, every k), 32 Sigma
+    outputs (one k, 32 tau, every q), the screened interaction for 4 of the Nk transfer
+    momenta and one Dyson solve over every k; scaled to a full iteration (Nk x ntau outputs of
+    each contraction, Nk momenta, 65 Dyson solves for the bisection)."""
     import oracle
     from gwinputs import add_k, minus_k
     try:
@@ -155,6 +156,7 @@ def cpu_baseline(wl, F_all, V_all, ibz_rep_q, torch):
     except Exception:
         cores = os.cpu_count() or 1
     nk, nt = wl.nk, wl.ntau
+    ns = min(32, nt)
     add = add_k(wl.n)
     mk = minus_k(wl.n)
     sub = np.array([[add[k, mk[q]] for q in range(nk)] for k in range(nk)])
@@ -167,25 +169,30 @@ def cpu_baseline(wl, F_all, V_all, ibz_rep_q, torch):
     Vk = V_all[k, torch.as_tensor(sub[k])].cpu().numpy()
     rng = np.random.default_rng(0)
     Ph = rng.standard_normal((nk, wl.naux, wl.naux)) * 1e-3
+    Ph = Ph + Ph.transpose(0, 2, 1)
     t = time.perf_counter()
-    oracle.polarization_unit(G, Vq, add, q, 0, wl.spin)
-    t_p0 = time.perf_counter() - t
+    for j in range(ns):
+        oracle.polarization_unit(G, Vq, add, q, j, wl.spin)
+    t_p0 = (time.perf_counter() - t) / ns
     t = time.perf_counter()
-    oracle.self_energy_unit(G, Vk, Ph + Ph.transpose(0, 2, 1), sub, k, 0)
-    t_s = time.perf_counter() - t
-    X = rng.standard_normal((nk, nt, wl.naux, wl.naux)) * 1e-3
+    for j in range(ns):
+        oracle.self_energy_unit(G, Vk, Ph, sub, k, j)
+    t_s = (time.perf_counter() - t) / ns
+    nq = min(4, nk)
+    X = rng.standard_normal((nq, nt, wl.naux, wl.naux)) * 1e-3
     X = X + X.transpose(0, 1, 3, 2)
     t = time.perf_counter()
     oracle.screened(X.astype(complex), wl.beta, wl.nw)
-    t_scr = time.perf_counter() - t
+    t_scr = (time.perf_counter() - t) / nq
     S0 = np.zeros((nk, nt, wl.nao, wl.nao), complex)
     t = time.perf_counter()
     oracle.dyson(F, S0, 0.0, wl.beta, wl.nw)
     t_dys = time.perf_counter() - t
-    total = (t_p0 + t_s) * nk * nt + t_scr + 65 * t_dys
-    sample = (f"measured: one P0 output (q={q}, tau_0, all {nk} k) {t_p0:.3f} s, one Sigma output (k={k}, tau_0, "
-              f"all {nk} q) {t_s:.3f} s, screened interaction {t_scr:.2f} s, one Dyson solve {t_dys:.3f} s; "
-              f"extrapolated x{nk * nt} outputs each and 65 Dyson solves")
+    total = (t_p0 + t_s) * nk * nt + t_scr * nk + 65 * t_dys
+    sample = (f"measured: {ns} P0 outputs (q={q}, all {nk} k) at {t_p0:.3f} s each, {ns} Sigma outputs (k={k}, "
+              f"all {nk} q) at {t_s:.3f} s each, screened interaction for {nq} momenta at {t_scr:.2f} s each, one "
+              f"Dyson solve over all k {t_dys:.3f} s; scaled to {nk * nt} outputs of each contraction, {nk} "
+              f"momenta and 65 Dyson solves")
     return {"value": total, "unit": "s/iteration", "cores": int(cores), "kind": "oracle", "sample": sample,
             "extrapolated": True}
 

@@ -30,6 +30,21 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// s += x g and s += x conj(g), four fused multiply-adds each
+template <typename V2>
+__device__ __forceinline__ void cfma(V2& s, const V2 x, const V2 g) {
+  s.x = fma(x.x, g.x, s.x);
+  s.x = fma(-x.y, g.y, s.x);
+  s.y = fma(x.x, g.y, s.y);
+  s.y = fma(x.y, g.x, s.y);
+}
+template <typename V2>
+__device__ __forceinline__ void cfma_conj(V2& s, const V2 x, const V2 g) {
+  s.x = fma(x.x, g.x, s.x);
+  s.x = fma(x.y, g.y, s.x);
+  s.y = fma(x.y, g.x, s.y);
+  s.y = fma(-x.x, g.y, s.y);
+}
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   const double d = b.x * b.x + b.y * b.y;
   return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
@@ -304,6 +319,10 @@ __global__ __launch_bounds__(256, 3) void k_brgemm(const GemmProblem* __restrict
   }
 }
 
+// Ordered sum of the split-K partial slots of one output tile; a workgroup takes a quarter
+// of the tile (one element per thread) and keeps eight running sums over the slots, combined
+// in a fixed order at the end (deterministic).
+template <int TAG>
 __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ probs,
                                                 const GemmReduce* __restrict__ reds, Bases bases,
                                                 const double2* __restrict__ partials, unsigned f32mask) {
@@ -311,23 +330,47 @@ __global__ __launch_bounds__(256) void k_reduce(const GemmProblem* __restrict__ 
   const GemmProblem P = probs[rd.prob];
   const bool cf32 = (f32mask >> P.cbuf) & 1u;
   const double2 al = make_double2(P.alpha_re, P.alpha_im);
-  for (int e = threadIdx.x; e < TM * TN; e += 256) {
-    const int er = e / TN, ec = e % TN;
-    const int row = rd.tm * 16 + er, cc = rd.tn * 16 + ec;
-    if (er >= rd.mh * 16 || ec >= rd.nh * 16 || row >= P.M || cc >= P.N) continue;
-    double2 s = make_double2(0.0, 0.0);
-    for (int q = 0; q < rd.nslot; ++q) s = cadd(s, partials[int64_t(rd.slot0 + q) * TM * TN + e]);
-    double2 v = cmul(al, s);
-    const int64_t at = P.coff + int64_t(rd.batch) * P.sCb + c_offset(P, row, cc);
-    if (cf32) {
-      float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
-      if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
-      C[at] = make_float2(float(v.x), float(v.y));
-    } else {
-      double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]);
-      if (P.beta) v = cadd(v, C[at]);
-      C[at] = v;
-    }
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  const int er = e / TN, ec = e % TN;
+  const int row = rd.tm * 16 + er, cc = rd.tn * 16 + ec;
+  if (er >= rd.mh * 16 || ec >= rd.nh * 16 || row >= P.M || cc >= P.N) return;
+  const double2* src = partials + int64_t(rd.slot0) * TM * TN + e;
+  double2 acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = make_double2(0.0, 0.0);
+  int q = 0;
+  for (; q + 8 <= rd.nslot; q += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = cadd(acc[u], src[int64_t(q + u) * TM * TN]);
+  }
+  for (int u = 0; q + u < rd.nslot; ++u) acc[u] = cadd(acc[u], src[int64_t(q + u) * TM * TN]);
+  const double2 s = cadd(cadd(cadd(acc[0], acc[1]), cadd(acc[2], acc[3])), cadd(cadd(acc[4], acc[5]), cadd(acc[6], acc[7])));
+  double2 v = cmul(al, s);
+  const int64_t at = P.coff + int64_t(rd.batch) * P.sCb + c_offset(P, row, cc);
+  if (cf32) {
+    float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
+    if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
+    C[at] = make_float2(float(v.x), float(v.y));
+  } else {
+    double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]);
+    if (P.beta) v = cadd(v, C[at]);
+    C[at] = v;
+  }
+}
+
+template <int TAG>
+void launch_reduce(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, unsigned mask) {
+  if (p.nreds > 0)
+    hipLaunchKernelGGL(k_reduce<TAG>, dim3(p.nreds, TM * TN / 256), dim3(256), 0, s, (const GemmProblem*)p.probs,
+                       (const GemmReduce*)p.reds, b, (const double2*)partials, mask);
+}
+
+void launch_reduce_tag(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, unsigned mask) {
+  switch (tag) {
+    case 1: launch_reduce<1>(p, b, partials, s, mask); break;
+    case 2: launch_reduce<2>(p, b, partials, s, mask); break;
+    case 3: launch_reduce<3>(p, b, partials, s, mask); break;
+    default: launch_reduce<0>(p, b, partials, s, mask); break;
   }
 }
 
@@ -452,6 +495,22 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   }
   const double2 al = make_double2(P.alpha_re, P.alpha_im);
   const bool cf32 = (f32mask >> P.cbuf) & 1u;
+  // column offsets of this lane's two columns (row offsets are formed per row below)
+  int64_t coffs[2];
+#pragma unroll
+  for (int qn = 0; qn < 2; ++qn) {
+    const int gc = n0 + qn * 16 + li, cb = gc / P.cdiv;
+    coffs[qn] = cb * P.sCcb + (gc - cb * P.cdiv);
+  }
+  const int64_t cbase = P.coff + int64_t(tl.batch) * P.sCb;
+  int64_t roffs[2][4];
+#pragma unroll
+  for (int qm = 0; qm < 2; ++qm)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gr = m0 + qm * 16 + mrow(R(0), lane, j), rb = gr / P.rdiv;
+      roffs[qm][j] = cbase + rb * P.sCrb + int64_t(gr - rb * P.rdiv) * P.ldc;
+    }
   auto store = [&](int qm, int qn, const A4& cr, const A4& ci) {
     for (int j = 0; j < 4; ++j) {
       const int row = qm * 16 + mrow(R(0), lane, j), col = qn * 16 + li;
@@ -462,7 +521,7 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       const int gr = m0 + row, gc = n0 + col;
       if (gr >= P.M || gc >= P.N) continue;
       double2 v = cmul(al, make_double2(double(cr[j]), double(ci[j])));
-      const int64_t at = P.coff + int64_t(tl.batch) * P.sCb + c_offset(P, gr, gc);
+      const int64_t at = roffs[qm][j] + coffs[qn];
       if (cf32) {
         float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
         if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
@@ -518,9 +577,7 @@ void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStrea
     if (fp32) launch_wgemm_t<float>(p, b, partials, s, tag, f32mask);
     else launch_wgemm_t<double>(p, b, partials, s, tag, f32mask);
   }
-  if (p.nreds > 0)
-    hipLaunchKernelGGL(k_reduce, dim3(p.nreds), dim3(256), 0, s, (const GemmProblem*)p.probs,
-                       (const GemmReduce*)p.reds, b, (const double2*)partials, f32mask);
+  launch_reduce_tag(p, b, partials, s, tag, f32mask);
 }
 
 template <typename R>
@@ -543,9 +600,7 @@ void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStre
     if (fp32) launch_brgemm_t<float>(p, b, partials, s, tag, f32mask);
     else launch_brgemm_t<double>(p, b, partials, s, tag, f32mask);
   }
-  if (p.nreds > 0)
-    hipLaunchKernelGGL(k_reduce, dim3(p.nreds), dim3(256), 0, s, (const GemmProblem*)p.probs,
-                       (const GemmReduce*)p.reds, b, (const double2*)partials, f32mask);
+  launch_reduce_tag(p, b, partials, s, tag, f32mask);
 }
 
 // FP64 -> FP32 copy of n complex numbers
@@ -602,11 +657,7 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
   for (int k = 0; k < sz; ++k) {
     const V2 gv = gs[po + k * sz + cc];
 #pragma unroll
-    for (int i = 0; i < RB_ROWS / 8; ++i) {
-      const V2 x = tile[(g + 8 * i) * ncol + off + k];
-      acc[i].x += x.x * gv.x - x.y * gv.y;
-      acc[i].y += x.x * gv.y + x.y * gv.x;
-    }
+    for (int i = 0; i < RB_ROWS / 8; ++i) cfma(acc[i], tile[(g + 8 * i) * ncol + off + k], gv);
   }
 #pragma unroll
   for (int i = 0; i < RB_ROWS / 8; ++i) {
@@ -656,7 +707,7 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
     info[3 * (n + c) + 1] = btr[2 + 3 * br];
     info[3 * (n + c) + 2] = btr[3 + 3 * br];
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int r = wave; r < n; r += 4) {
     V2 v = {0, 0};
     if (lane < wv) v = in[int64_t(r) * ncols + lane];
@@ -671,12 +722,11 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
     const int ap = wave + 4 * i;
     V2 s = {0, 0};
     if (ap < n) {
-      const int off = info[3 * ap], sz = info[3 * ap + 1], po = info[3 * ap + 2], rr = ap - off;
-      for (int k = 0; k < sz; ++k) {
-        const V2 g = gl[po + k * sz + rr], x = tile[(off + k) * w + lane];
-        s.x += g.x * x.x + g.y * x.y;
-        s.y += g.x * x.y - g.y * x.x;
-      }
+      // the row and its block are the same for the whole wave (scalar registers)
+      const int off = __builtin_amdgcn_readfirstlane(info[3 * ap]);
+      const int sz = __builtin_amdgcn_readfirstlane(info[3 * ap + 1]);
+      const int po = __builtin_amdgcn_readfirstlane(info[3 * ap + 2]), rr = ap - off;
+      for (int k = 0; k < sz; ++k) cfma_conj(s, tile[(off + k) * w + lane], gl[po + k * sz + rr]);
     }
     acc[i] = s;
   }
@@ -698,9 +748,7 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int a = wave + 4 * i;
-      const V2 y = tile[min(a, n - 1) * w + mq * n + off + k];
-      acc[i].x += y.x * g.x + y.y * g.y;
-      acc[i].y += y.y * g.x - y.x * g.y;
+      cfma_conj(acc[i], tile[min(a, n - 1) * w + mq * n + off + k], g);
     }
   }
 #pragma unroll

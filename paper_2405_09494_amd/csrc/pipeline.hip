@@ -48,9 +48,14 @@ inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vec
   }
   std::map<Key, int> gid;
   std::vector<std::vector<int>> groups;
+  // a problem whose operands fit in an L2 comfortably keeps all its tiles on one XCD
+  auto small = [&](const GemmTile& t) {
+    const GemmProblem& p = probs[t.prob];
+    return 16.0 * double(p.K) * p.T * (double(p.M) + p.N) <= 1.0e6;
+  };
   for (int i = t0; i < int(tiles.size()); ++i) {
     const Key ka = keyA(tiles[i]), kb = keyB(tiles[i]);
-    const Key k = ca[ka] >= cb[kb] ? ka : kb;
+    const Key k = small(tiles[i]) ? Key{tiles[i].prob, tiles[i].batch, 0, 0, 2} : (ca[ka] >= cb[kb] ? ka : kb);
     auto it = gid.find(k);
     if (it == gid.end()) {
       it = gid.emplace(k, int(groups.size())).first;
