@@ -70,13 +70,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_ctx(wl, mode, half_tau=True, tau_chunk=0):
+def make_ctx(wl, mode, half_tau=True, tau_chunk=0, precision=0):
     from gwinputs import crystal
     from paper_2405_09494_amd import gwsym
     cr = crystal(wl.crystal)
     rot = np.array([W for W, _ in cr.ops])
     trans = np.array([w for _, w in cr.ops])
-    ctx = gwsym.Context(wl.beta, wl.ntau, wl.nw, wl.spin, mode, gwsym.FP64, half_tau, tau_chunk)
+    ctx = gwsym.Context(wl.beta, wl.ntau, wl.nw, wl.spin, mode, precision, half_tau, tau_chunk)
     ctx.build_symmetry_basis(cr.lattice, cr.positions, rot, trans, wl.n, wl.ao, wl.aux)
     return ctx
 
@@ -207,6 +207,7 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip the full-matrix FP64 comparison")
     ap.add_argument("--graph", type=int, default=1, help="1 (default): replay each iteration from a captured HIP graph; 0: eager launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-contraction run of the block path")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a plain copy kernel "
                          "of known traffic, to scale hardware byte counters)")
@@ -292,7 +293,6 @@ def main():
 
     # ---- full-matrix FP64 (no symmetry) on the same GPU ----
     if not args.no_full:
-        S_blk_full = blk.full(1, blk.S)
         full = Path(make_ctx(wl, gwsym.MODE_FULL, tau_chunk=args.tau_chunk), F_all, V_all, torch, dev)
         # compare one iteration from the same G0 against the block path
         blk2 = blk
@@ -310,6 +310,26 @@ def main():
         out["sigma_rel_err_block_vs_full"] = err
         log(f"[bench] full: {s_full:.3f} s/iteration, Sigma block vs full {err:.2e}")
         del full
+
+    # ---- the same block path with FP32 contractions (FP64 transforms, inverses and mu) ----
+    if not args.no_fp32:
+        f32 = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=gwsym.FP32), F_all, V_all,
+                   torch, dev, graph=bool(args.graph))
+        s_f32 = time_steps(f32, args.steps, args.warmup, torch)
+        for pth in (blk, f32):   # one iteration from the same G0 in both precisions
+            pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)
+            pth.step()
+        torch.cuda.synchronize()
+        a, b = f32.full(1, f32.S), blk.full(1, blk.S)
+        err32 = float((a - b).abs().max() / b.abs().max())
+        ga, gb = f32.full(1, f32.G), blk.full(1, blk.G)
+        nk_, nt_, no_ = blk.ctx.nk, blk.ctx.ntau, blk.ctx.nao
+        occ = lambda g: -torch.diagonal(g.view(nk_, nt_, no_, no_)[:, -1], dim1=-2, dim2=-1).real
+        occ_err = float((occ(ga) - occ(gb)).abs().max())
+        out["fp32_contractions"] = {"s_per_iteration": s_f32, "speedup_vs_fp64_block": s_blk / s_f32,
+                                    "sigma_rel_err_vs_fp64": err32, "occupation_max_abs_err_vs_fp64": occ_err}
+        log(f"[bench] fp32 contractions: {s_f32:.4f} s/iteration, Sigma vs fp64 {err32:.2e}, occupations {occ_err:.2e}")
+        del f32
 
     if not args.no_cpu:
         ibz = blk.ctx.table("ibz")

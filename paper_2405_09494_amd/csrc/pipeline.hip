@@ -512,6 +512,21 @@ int device_init(Ctx& c, void* stream) {
   d.p0_mirror.close();
 
   // ---------------- self-energy (eq. sigma, Alg. 4) ----------------
+  // bins of consecutive orbital blocks, at most 16 rows each (a larger block is a bin alone)
+  std::vector<std::vector<std::pair<int, int>>> bins_ao(nib);
+  for (int i = 0; i < nib; ++i) {
+    const Blocks& B = c.bao[i];
+    int r0 = 0, nb = 0;
+    for (size_t r = 0; r < B.size.size(); ++r) {
+      if (nb > 0 && nb + B.size[r] > 16) {
+        bins_ao[i].push_back({r0, nb});
+        r0 += nb;
+        nb = 0;
+      }
+      nb += B.size[r];
+    }
+    if (nb > 0) bins_ao[i].push_back({r0, nb});
+  }
   // Y(k', s') = P_blk^T Vs (per auxiliary block), Z = Y G^{k'}(tau_j) (block multiply),
   // Sigma = -(1/Nk) sum_(k', s') Z Vs^H over all orbital blocks of k0 at once, then the
   // diagonal blocks are gathered into Sigma_blk; only the block work is counted.
@@ -552,10 +567,25 @@ int device_init(Ctx& c, void* stream) {
             }
           }
         }
-        d.s_gemmC.add(gp(no, no, no, nk * na, 1, B_W2, i64(jj) * slab, no, i64(no) * no, 0, OP_N, B_VS,
-                         i64(i) * nk * na * no * no, no, i64(no) * no, 0, OP_H, B_SCR, i64(jj) * no * no, no, 0,
-                         -1.0 / nk),
-                      sumsq_ao[i] * no * double(nk) * na);
+        // only the diagonal blocks of Sigma are kept: consecutive orbital blocks are grouped into
+        // bins of at most 16 rows and each bin's diagonal square is one problem, with the rows
+        // (tau, a) of all tau of the chunk stacked
+        if (j == j0) {
+          const int jc = j1 - j0;
+          for (const auto& bn : bins_ao[i]) {
+            const int r0 = bn.first, nb = bn.second;
+            GemmProblem p = gp(jc * nb, nb, no, nk * na, 1, B_W2, i64(r0) * no, no, i64(no) * no, 0, OP_N, B_VS,
+                               i64(i) * nk * na * no * no + i64(r0) * no, no, i64(no) * no, 0, OP_H, B_SCR,
+                               i64(r0) * no + r0, no, 0, -1.0 / nk);
+            p.rdiv = nb;
+            p.sArb = slab;
+            p.sCrb = i64(no) * no;
+            double algo = 0;
+            for (size_t rb = 0; rb < BO.size.size(); ++rb)
+              if (BO.off[rb] >= r0 && BO.off[rb] < r0 + nb) algo += double(BO.size[rb]) * BO.size[rb];
+            d.s_gemmC.add(p, double(jc) * algo * no * double(nk) * na);
+          }
+        }
         for (size_t rb = 0; rb < BO.size.size(); ++rb) {
           const int n = BO.size[rb], off = BO.off[rb];
           d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(jj) * no * no + i64(off) * no + off,
