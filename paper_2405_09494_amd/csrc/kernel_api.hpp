@@ -87,8 +87,9 @@ void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStrea
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s);
-void launch_inverse(const void* items, int nitems, const Bases& b, int mode, const double* mu, double* trace,
-                    int* status, hipStream_t s);
+// nmax: largest matrix among the items
+void launch_inverse(const void* items, int nitems, int nmax, const Bases& b, int mode, const double* mu,
+                    double* trace, int* status, hipStream_t s);
 void launch_mu_init(const double* eps_range, double* state, double* mu, hipStream_t s);
 void launch_mu_update(const void* items, int nitems, const double* trace, const void* Blast, double scale,
                       double ntarget, double* state, double* mu, hipStream_t s);

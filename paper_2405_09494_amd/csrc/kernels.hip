@@ -412,13 +412,16 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   };
   const int64_t ax0 = arow(min(m0 + li, P.M - 1)), ax1 = arow(min(m0 + 16 + li, P.M - 1));
   const int64_t ak = aT ? P.lda : 1;
-  const int64_t bx0 = bcol(min(n0 + li, P.N - 1)), bx1 = bcol(min(n0 + 16 + li, P.N - 1));
   const int64_t bk = bT ? 1 : P.ldb;
-  const int nsub = (tl.t1 - tl.t0) * nk4, npair = (nsub + 1) >> 1;
+  // a tile of an N2 class covers nn / 2 consecutive 32-column chunks, walked in one sequence of
+  // K-step pairs so that the first loads of a chunk overlap the last MFMAs of the one before
+  const int nchunk = N2 ? (tl.nn >> 1) : 1;
+  const int nsub = (tl.t1 - tl.t0) * nk4, npair = (nsub + 1) >> 1, total = npair * nchunk;
   A4 c00r = {0, 0, 0, 0}, c00i = c00r, c01r = c00r, c01i = c00r, c10r = c00r, c10i = c00r, c11r = c00r, c11i = c00r;
-  // fetch position: outer index t and k step j of the next sub-step; the mask zeroes k >= K
-  // and sub-steps past the end
-  int ft = tl.t0, fj = 0, fs = 0;
+  // fetch position: chunk, outer index t and k step j of the next sub-step; the mask zeroes
+  // k >= K and the sub-step past the end of a chunk's odd count
+  int fc = 0, ft = tl.t0, fj = 0, fs = 0;
+  int64_t fbx0 = bcol(min(n0 + li, P.N - 1)), fbx1 = bcol(min(n0 + 16 + li, P.N - 1));
   V2 fa[2][2], fb[2][2];
   R fm[2];
   auto fetch1 = [&](int h) {
@@ -430,20 +433,64 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
     const V2* B = Bb + int64_t(t) * P.sBt;
     fa[h][0] = A[ax0 + kc * ak];
     if (M2) fa[h][1] = A[ax1 + kc * ak];
-    fb[h][0] = B[bx0 + kc * bk];
-    if (N2) fb[h][1] = B[bx1 + kc * bk];
+    fb[h][0] = B[fbx0 + kc * bk];
+    if (N2) fb[h][1] = B[fbx1 + kc * bk];
     fm[h] = (live && k < K) ? R(1) : R(0);
     ++fs;
     if (++fj == nk4) {
       fj = 0;
       ++ft;
     }
+    if (fs == 2 * npair && fc + 1 < nchunk) {   // on to the next chunk
+      ++fc;
+      fs = 0;
+      fj = 0;
+      ft = tl.t0;
+      const int nc = n0 + 32 * fc;
+      fbx0 = bcol(min(nc + li, P.N - 1));
+      fbx1 = bcol(min(nc + 16 + li, P.N - 1));
+    }
   };
-  if (npair > 0) {
+  const double2 al = make_double2(P.alpha_re, P.alpha_im);
+  const bool cf32 = (f32mask >> P.cbuf) & 1u;
+  const int64_t cbase = P.coff + int64_t(tl.batch) * P.sCb;
+  int64_t roffs[2][4];
+#pragma unroll
+  for (int qm = 0; qm < 2; ++qm)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gr = m0 + qm * 16 + mrow(R(0), lane, j), rb = gr / P.rdiv;
+      roffs[qm][j] = cbase + rb * P.sCrb + int64_t(gr - rb * P.rdiv) * P.ldc;
+    }
+  auto store = [&](int cn0, int qm, int qn, const A4& cr, const A4& ci) {
+    const int gc = cn0 + qn * 16 + li, cb = gc / P.cdiv;
+    const int64_t coff = cb * P.sCcb + (gc - cb * P.cdiv);
+    for (int j = 0; j < 4; ++j) {
+      const int row = qm * 16 + mrow(R(0), lane, j), col = qn * 16 + li;
+      if (tl.slot >= 0) {
+        partials[int64_t(tl.slot) * TM * TN + row * TN + col] = make_double2(double(cr[j]), double(ci[j]));
+        continue;
+      }
+      if (m0 + row >= P.M || gc >= P.N) continue;
+      double2 v = cmul(al, make_double2(double(cr[j]), double(ci[j])));
+      const int64_t at = roffs[qm][j] + coff;
+      if (cf32) {
+        float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
+        if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
+        C[at] = make_float2(float(v.x), float(v.y));
+      } else {
+        double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]);
+        if (P.beta) v = cadd(v, C[at]);
+        C[at] = v;
+      }
+    }
+  };
+  if (total > 0) {
     fetch1(0);
     fetch1(1);
   }
-  for (int pr = 0; pr < npair; ++pr) {
+  int cc = 0, cp = 0;   // chunk and pair being computed
+  for (int st = 0; st < total; ++st) {
     V2 a[2][2], b[2][2];
     R m[2];
 #pragma unroll
@@ -454,7 +501,7 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       b[h][1] = N2 ? fb[h][1] : fb[h][0];
       m[h] = fm[h];
     }
-    if (pr + 1 < npair) {
+    if (st + 1 < total) {
       fetch1(0);
       fetch1(1);
     }
@@ -492,51 +539,25 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
         c11i = mfma16(a1i, b1r, c11i);
       }
     }
-  }
-  const double2 al = make_double2(P.alpha_re, P.alpha_im);
-  const bool cf32 = (f32mask >> P.cbuf) & 1u;
-  // column offsets of this lane's two columns (row offsets are formed per row below)
-  int64_t coffs[2];
-#pragma unroll
-  for (int qn = 0; qn < 2; ++qn) {
-    const int gc = n0 + qn * 16 + li, cb = gc / P.cdiv;
-    coffs[qn] = cb * P.sCcb + (gc - cb * P.cdiv);
-  }
-  const int64_t cbase = P.coff + int64_t(tl.batch) * P.sCb;
-  int64_t roffs[2][4];
-#pragma unroll
-  for (int qm = 0; qm < 2; ++qm)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gr = m0 + qm * 16 + mrow(R(0), lane, j), rb = gr / P.rdiv;
-      roffs[qm][j] = cbase + rb * P.sCrb + int64_t(gr - rb * P.rdiv) * P.ldc;
+    if (++cp == npair) {
+      // end of a chunk: store it and start the next from zero
+      const int cn0 = n0 + 32 * cc;
+      store(cn0, 0, 0, c00r, c00i);
+      if (N2) store(cn0, 0, 1, c01r, c01i);
+      if (M2) store(cn0, 1, 0, c10r, c10i);
+      if (M2 && N2) store(cn0, 1, 1, c11r, c11i);
+      c00r = A4{0, 0, 0, 0};
+      c00i = c00r;
+      c01r = c00r;
+      c01i = c00r;
+      c10r = c00r;
+      c10i = c00r;
+      c11r = c00r;
+      c11i = c00r;
+      cp = 0;
+      ++cc;
     }
-  auto store = [&](int qm, int qn, const A4& cr, const A4& ci) {
-    for (int j = 0; j < 4; ++j) {
-      const int row = qm * 16 + mrow(R(0), lane, j), col = qn * 16 + li;
-      if (tl.slot >= 0) {
-        partials[int64_t(tl.slot) * TM * TN + row * TN + col] = make_double2(double(cr[j]), double(ci[j]));
-        continue;
-      }
-      const int gr = m0 + row, gc = n0 + col;
-      if (gr >= P.M || gc >= P.N) continue;
-      double2 v = cmul(al, make_double2(double(cr[j]), double(ci[j])));
-      const int64_t at = roffs[qm][j] + coffs[qn];
-      if (cf32) {
-        float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
-        if (P.beta) v = cadd(v, make_double2(C[at].x, C[at].y));
-        C[at] = make_float2(float(v.x), float(v.y));
-      } else {
-        double2* C = reinterpret_cast<double2*>(bases.p[P.cbuf]);
-        if (P.beta) v = cadd(v, C[at]);
-        C[at] = v;
-      }
-    }
-  };
-  store(0, 0, c00r, c00i);
-  if (N2) store(0, 1, c01r, c01i);
-  if (M2) store(1, 0, c10r, c10i);
-  if (M2 && N2) store(1, 1, c11r, c11i);
+  }
 }
 
 template <typename R, int TAG>
@@ -839,6 +860,7 @@ void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s) {
 // Matrices with n <= INV_LDS_N are factorised in LDS, larger ones in place in `out`.
 
 constexpr int INV_LDS_N = 48;
+constexpr int INV_WAVE_N = 16;   // matrices up to this size take the one-wave kernel
 
 __device__ void gauss_jordan(double2* A, int n, int* piv, double2* fcol, double* red, int* redi, int* sing) {
   const int tid = threadIdx.x;
@@ -909,6 +931,7 @@ __global__ __launch_bounds__(256) void k_inverse(const InvItem* __restrict__ ite
   __shared__ int sing;
   const InvItem it = items[blockIdx.x];
   const int n = it.n, tid = threadIdx.x;
+  if (n <= INV_WAVE_N) return;   // done by k_inverse_w
   if (tid == 0) sing = 0;
   const double2* X = reinterpret_cast<const double2*>(bases.p[it.xbuf]) + it.x_off;
   const double2* F = it.f_off >= 0 ? reinterpret_cast<const double2*>(bases.p[it.fbuf]) + it.f_off : nullptr;
@@ -963,9 +986,137 @@ __global__ __launch_bounds__(256) void k_inverse(const InvItem* __restrict__ ite
   }
 }
 
-void launch_inverse(const void* items, int nitems, const Bases& b, int mode, const double* mu, double* trace,
-                    int* status, hipStream_t s) {
-  if (nitems)
+// The same inverses for matrices of at most INV_WAVE_N rows: one wave per matrix, four per
+// workgroup, each in its own LDS region; no workgroup barriers (a wave's LDS accesses are
+// performed in order), the pivot search is a cross-lane reduction.
+__global__ __launch_bounds__(256) void k_inverse_w(const InvItem* __restrict__ items, int nitems, Bases bases,
+                                                   int mode, const double* __restrict__ mu,
+                                                   double* __restrict__ trace, int* __restrict__ status) {
+  __shared__ double2 lds[4][INV_WAVE_N * INV_WAVE_N];
+  __shared__ int pivs[4][INV_WAVE_N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 4 + wave;
+  if (idx >= nitems) return;
+  const InvItem it = items[idx];
+  const int n = it.n;
+  if (n > INV_WAVE_N) return;
+  double2* A = lds[wave];
+  int* piv = pivs[wave];
+  const double2* X = reinterpret_cast<const double2*>(bases.p[it.xbuf]) + it.x_off;
+  const double2* F = it.f_off >= 0 ? reinterpret_cast<const double2*>(bases.p[it.fbuf]) + it.f_off : nullptr;
+  double2* out = reinterpret_cast<double2*>(bases.p[it.outbuf]) + it.out_off;
+  const double shift = (mode == INV_P) ? 0.0 : *mu;
+  constexpr int EPL = INV_WAVE_N * INV_WAVE_N / 64;   // elements per lane
+  int er[EPL], ej[EPL];
+#pragma unroll
+  for (int q = 0; q < EPL; ++q) {
+    const int e = lane + 64 * q;
+    er[q] = e / n;
+    ej[q] = e - er[q] * n;
+  }
+#pragma unroll
+  for (int q = 0; q < EPL; ++q) {
+    const int e = lane + 64 * q;
+    if (e >= n * n) continue;
+    const double2 x = X[e];
+    double2 a;
+    if (mode == INV_P) {
+      a = make_double2(-x.x, -x.y);
+      if (er[q] == ej[q]) a.x += 1.0;
+    } else {
+      const double2 f = F[e];
+      a = make_double2(-f.x - x.x, -f.y - x.y);
+      if (er[q] == ej[q]) { a.x += shift; a.y += it.w; }
+    }
+    A[e] = a;
+  }
+  __builtin_amdgcn_wave_barrier();
+  bool sing = false;
+  for (int c = 0; c < n; ++c) {
+    // pivot: largest |Re| + |Im| in column c at rows >= c, lowest row on ties
+    double best = -1.0;
+    int bi = c;
+    if (lane >= c && lane < n) {
+      const double2 v = A[lane * n + c];
+      best = fabs(v.x) + fabs(v.y);
+      bi = lane;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int p = bi;
+    sing = sing || best <= 0.0;
+    if (lane == 0) piv[c] = p;
+    if (p != c && lane < n) {
+      const double2 t = A[c * n + lane];
+      A[c * n + lane] = A[p * n + lane];
+      A[p * n + lane] = t;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const double2 d = cdiv(make_double2(1.0, 0.0), A[c * n + c]);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) A[c * n + lane] = (lane == c) ? d : cmul(A[c * n + lane], d);
+    __builtin_amdgcn_wave_barrier();
+    double2 fv[EPL], rv[EPL];
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      const int e = lane + 64 * q;
+      if (e < n * n) {
+        fv[q] = A[er[q] * n + c];
+        rv[q] = A[c * n + ej[q]];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      const int e = lane + 64 * q;
+      if (e >= n * n || er[q] == c) continue;
+      if (ej[q] == c) A[e] = cmul(make_double2(-fv[q].x, -fv[q].y), d);
+      else A[e] = csub(A[e], cmul(fv[q], rv[q]));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    const int p = piv[c];
+    if (p != c && lane < n) {
+      const double2 t = A[lane * n + c];
+      A[lane * n + c] = A[lane * n + p];
+      A[lane * n + p] = t;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (sing && lane == 0) atomicOr(status, 1);
+  if (mode == INV_TRACE) {
+    double2 t = make_double2(0.0, 0.0);
+    if (lane < n) t = A[lane * n + lane];
+    for (int off = 32; off > 0; off >>= 1) {
+      t.x += __shfl_xor(t.x, off);
+      t.y += __shfl_xor(t.y, off);
+    }
+    if (lane == 0) {
+      trace[2 * idx] = t.x;
+      trace[2 * idx + 1] = t.y;
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < EPL; ++q) {
+    const int e = lane + 64 * q;
+    if (e >= n * n) continue;
+    double2 v = A[e];
+    if (mode == INV_P && er[q] == ej[q]) v.x -= 1.0;
+    out[e] = v;
+  }
+}
+
+void launch_inverse(const void* items, int nitems, int nmax, const Bases& b, int mode, const double* mu,
+                    double* trace, int* status, hipStream_t s) {
+  if (nitems == 0) return;
+  hipLaunchKernelGGL(k_inverse_w, dim3((nitems + 3) / 4), dim3(256), 0, s, (const InvItem*)items, nitems, b, mode, mu,
+                     trace, status);
+  if (nmax > INV_WAVE_N)
     hipLaunchKernelGGL(k_inverse, dim3(nitems), dim3(256), 0, s, (const InvItem*)items, b, mode, mu, trace, status);
 }
 

@@ -140,9 +140,17 @@ struct GemmStage {
         for (int i = 0; i < mu; i += 2) {
           const int mh = std::min(2, mu - i);
           if (split == 1) {
-            const int group = wave ? 2 : 16;   // 32-column chunks per workgroup
-            for (int j = 0; j < nu; j += group)
-              tiles.push_back({id, b, i, j, 0, p.T, -1, mh, std::min(group, nu - j), 0});
+            if (wave) {
+              // one full 32-column chunk per wave (a wave can walk several: nn = 2 x chunks),
+              // a last 16-column unit on its own
+              const int full = nu / 2, per = 1;
+              for (int j = 0; j < full; j += per)
+                tiles.push_back({id, b, i, 2 * j, 0, p.T, -1, mh, 2 * std::min(per, full - j), 0});
+              if (nu % 2) tiles.push_back({id, b, i, 2 * full, 0, p.T, -1, mh, 1, 0});
+              continue;
+            }
+            for (int j = 0; j < nu; j += 16)   // up to eight 32-column chunks per workgroup
+              tiles.push_back({id, b, i, j, 0, p.T, -1, mh, std::min(16, nu - j), 0});
             continue;
           }
           for (int j = 0; j < nu; j += 2) {
@@ -164,7 +172,7 @@ struct GemmStage {
       for (int sh = 0; sh < 4; ++sh) {
         const int c0 = int(tiles.size());
         for (const GemmTile& t : all)
-          if ((t.mh == 2) * 2 + (t.nn == 2) == sh) tiles.push_back(t);
+          if ((t.mh == 2) * 2 + (t.nn >= 2) == sh) tiles.push_back(t);
         xcd_order(c0);
         r.shape[sh] = int(tiles.size()) - c0;
       }
@@ -225,6 +233,7 @@ struct ListStage {
   std::vector<Range> launches;
   void* d = nullptr;
   int start = 0;
+  int nmax = 0;   // inverse lists: largest matrix
   void close() {
     Range r;
     r.t0 = start;
@@ -622,6 +631,7 @@ int device_init(Ctx& c, void* stream) {
   d.scr_fwd.close();
   d.scr_bwd.close();
   d.scr_inv.close();
+  for (const InvItem& it : d.scr_inv.items) d.scr_inv.nmax = std::max(d.scr_inv.nmax, it.n);
   d.scr_herm.close();
 
   // ---------------- Dyson equation and mu (eq. dyson, N_e) ----------------
@@ -659,6 +669,8 @@ int device_init(Ctx& c, void* stream) {
   d.dys_bwd.close();
   d.dys_inv.close();
   d.mu_inv.close();
+  for (const InvItem& it : d.dys_inv.items) d.dys_inv.nmax = std::max(d.dys_inv.nmax, it.n);
+  d.mu_inv.nmax = d.dys_inv.nmax;
   d.mu_items.close();
   d.dys_herm.close();
   d.g0_items.close();
@@ -771,6 +783,8 @@ void timed(DevState& d, hipStream_t s, int cls, double macs, F f, double bytes =
   p.macs[cls] += macs;
   p.bytes[cls] += bytes;
 }
+
+int nmax_of(const ListStage<InvItem>& l) { return l.nmax; }
 
 Bases bases_of(DevState& d) {
   Bases b{};
@@ -1064,7 +1078,8 @@ int device_screened(Ctx& c, const void* P0, void* P, void* stream) {
   timed(d, s, PC_XFORM, d.scr_fwd.launches[0].macs,
         [&] { launch_brgemm(plan_of(d.scr_fwd, d.scr_fwd.launches[0]), b, d.partials, s); });
   timed(d, s, PC_INV, 0,
-        [&] { launch_inverse(d.scr_inv.d, int(d.scr_inv.items.size()), b, INV_P, nullptr, nullptr, d.status, s); });
+        [&] { launch_inverse(d.scr_inv.d, int(d.scr_inv.items.size()), nmax_of(d.scr_inv), b, INV_P, nullptr, nullptr,
+                       d.status, s); });
   timed(d, s, PC_XFORM, d.scr_bwd.launches[0].macs,
         [&] { launch_brgemm(plan_of(d.scr_bwd, d.scr_bwd.launches[0]), b, d.partials, s); });
   timed(d, s, PC_OTHER, 0, [&] { launch_herm(d.scr_herm.d, int(d.scr_herm.items.size()), b, s); });
@@ -1084,7 +1099,8 @@ int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G
   timed(d, s, PC_XFORM, d.dys_fwd.launches[0].macs,
         [&] { launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s); });
   timed(d, s, PC_INV, 0,
-        [&] { launch_inverse(d.dys_inv.d, int(d.dys_inv.items.size()), b, INV_G, mu, nullptr, d.status, s); });
+        [&] { launch_inverse(d.dys_inv.d, int(d.dys_inv.items.size()), nmax_of(d.dys_inv), b, INV_G, mu, nullptr, d.status,
+                       s); });
   timed(d, s, PC_XFORM, d.dys_bwd.launches[0].macs,
         [&] { launch_brgemm(plan_of(d.dys_bwd, d.dys_bwd.launches[0]), b, d.partials, s); });
   timed(d, s, PC_OTHER, 0, [&] { launch_herm(d.dys_herm.d, int(d.dys_herm.items.size()), b, s); });
@@ -1106,7 +1122,7 @@ int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double*
   launch_mu_init(d.scratch + 3, d.scratch, mu, s);
   const int n = int(d.mu_inv.items.size());
   for (int it = 0; it < 64; ++it) {
-    timed(d, s, PC_INV, 0, [&] { launch_inverse(d.mu_inv.d, n, b, INV_TRACE, mu, d.trace, d.status, s); });
+    timed(d, s, PC_INV, 0, [&] { launch_inverse(d.mu_inv.d, n, nmax_of(d.mu_inv), b, INV_TRACE, mu, d.trace, d.status, s); });
     timed(d, s, PC_OTHER, 0, [&] {
       launch_mu_update(d.mu_items.d, n, d.trace, Blast, c.prm.spin / c.nk, ntarget, d.scratch, mu, s);
     });
