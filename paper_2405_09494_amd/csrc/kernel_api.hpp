@@ -76,9 +76,9 @@ struct EigItem {
 void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag = 0,
                    bool fp32 = false, unsigned f32mask = 0);
 void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s);
-void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s,
+// gmax: largest packed block-diagonal factor (sum of squared block sizes)
+void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, int gmax, hipStream_t s,
                            bool fp32 = false);
-// gmax: largest packed block-diagonal matrix (sum of squared block sizes) among the factors
 void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, int gmax, hipStream_t s,
                           bool fp32);
 // Wave-tile complex GEMM over the same problem and tile lists (tiles of at most 32 x 32).

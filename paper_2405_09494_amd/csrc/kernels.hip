@@ -643,46 +643,50 @@ void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s) {
 // set of blocks (sizes from the block table `bt`, entry bt_off[blk_id]).
 // Left:  out[:][col] = blockdiag(G)^H * in[:][col] (columns of a row-major nb x ncols slab).
 
-constexpr int RB_ROWS = 64;
 
-// Right multiply of RB_ROWS rows of ncol (<= 32) columns by a block-diagonal matrix: thread
+// Right multiply of rows of ncol (<= 64) columns by a block-diagonal matrix: thread
 // (column c, row group g) forms out[r][c] = sum over k in the block of c of X[r][k] G[k][c] for
-// the rows r = g, g + 8, ...; each G element is read once and used for all those rows.
-template <typename V2>
+// the rows r = g, g + NG, ...; each G element is read once and used for all those rows.
+// CW = 32 (ncol <= 32, 64 rows per workgroup) or 64 (32 rows per workgroup).
+template <typename V2, int CW, bool GLDS>
 __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict__ segs, Bases bases,
                                                         const int* __restrict__ btab, int ncol) {
+  constexpr int NG = 256 / CW, ROWS = 8 * NG;
   extern __shared__ double2 lds_rr[];
   const RowSeg sg = segs[blockIdx.y];
-  const int r0 = blockIdx.x * RB_ROWS;
+  const int r0 = blockIdx.x * ROWS;
   if (r0 >= sg.nrows) return;
-  const int nrows = min(RB_ROWS, sg.nrows - r0);
+  const int nrows = min(ROWS, sg.nrows - r0);
   const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + int64_t(r0) * ncol;
   V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + int64_t(r0) * ncol;
   const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
   const int* bt = btab + sg.blk;  // bt[0] = count, then (off, size, poff) per block
-  V2* tile = reinterpret_cast<V2*>(lds_rr);               // nrows x ncol
-  V2* gs = tile + RB_ROWS * ncol;                          // packed blocks, ncol^2 at most
+  V2* tile = reinterpret_cast<V2*>(lds_rr);   // nrows x ncol, then (GLDS) the packed blocks of G
   const int nb = bt[0];
-  const int gsz = bt[3 * nb] + bt[3 * nb - 1] * bt[3 * nb - 1];   // poff + size^2 of the last block
-  for (int e = threadIdx.x; e < gsz; e += 256) gs[e] = G[e];
   for (int e = threadIdx.x; e < nrows * ncol; e += 256) tile[e] = in[e];
+  if (GLDS) {
+    V2* gs = tile + ROWS * ncol;
+    const int gsz = bt[3 * nb] + bt[3 * nb - 1] * bt[3 * nb - 1];   // poff + size^2 of the last block
+    for (int e = threadIdx.x; e < gsz; e += 256) gs[e] = G[e];
+    G = gs;
+  }
   __syncthreads();
-  const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int c = threadIdx.x % CW, g = threadIdx.x / CW;
   if (c >= ncol) return;
   int b = 0;
   while (b + 1 < nb && c >= bt[1 + 3 * (b + 1)]) ++b;
   const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b], cc = c - off;
-  V2 acc[RB_ROWS / 8];
+  V2 acc[8];
 #pragma unroll
-  for (int i = 0; i < RB_ROWS / 8; ++i) acc[i] = V2{0, 0};
+  for (int i = 0; i < 8; ++i) acc[i] = V2{0, 0};
   for (int k = 0; k < sz; ++k) {
-    const V2 gv = gs[po + k * sz + cc];
+    const V2 gv = G[po + k * sz + cc];
 #pragma unroll
-    for (int i = 0; i < RB_ROWS / 8; ++i) cfma(acc[i], tile[(g + 8 * i) * ncol + off + k], gv);
+    for (int i = 0; i < 8; ++i) cfma(acc[i], tile[min(g + NG * i, nrows - 1) * ncol + off + k], gv);
   }
 #pragma unroll
-  for (int i = 0; i < RB_ROWS / 8; ++i) {
-    const int r = g + 8 * i;
+  for (int i = 0; i < 8; ++i) {
+    const int r = g + NG * i;
     if (r < nrows) out[r * ncol + c] = acc[i];
   }
 }
@@ -692,9 +696,9 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
 // tile is at most 64 columns wide: lane = column, wave w = rows w, w + 4, ...; each Green's
 // function element is read once per lane and used for all of its rows, and the intermediate
 // stays in LDS.
-template <typename V2>
+template <typename V2, bool GLDS, int RPW>
 __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict__ segs, Bases bases,
-                                                       const int* __restrict__ btab, int n) {
+                                                       const int* __restrict__ btab, int n, int gmax) {
   extern __shared__ double2 lds_rb[];
   const RowSeg sg = segs[blockIdx.y];
   const int nq = rbb_nq(n), w = nq * n;
@@ -705,18 +709,22 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
   const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
   V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
   const V2* Gl = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
-  const V2* Gr = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off2;
+  const V2* Gr = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off2;   // global or, below, LDS
   const int* btl = btab + sg.blk;
   const int* btr = btab + sg.blk2;
-  V2* tile = reinterpret_cast<V2*>(lds_rb);   // n x w
-  V2* gl = tile + n * w;                      // packed blocks of Gl, then of Gr
+  V2* tile = reinterpret_cast<V2*>(lds_rb);   // n x w, then (GLDS) the packed blocks of Gl and Gr
   const int nbl = btl[0], nbr = btr[0];
-  const int szl = btl[3 * nbl] + btl[3 * nbl - 1] * btl[3 * nbl - 1];
-  const int szr = btr[3 * nbr] + btr[3 * nbr - 1] * btr[3 * nbr - 1];
-  V2* gr = gl + szl;
-  int* info = reinterpret_cast<int*>(gr + szr);   // per index: (off, size, poff) of its block, left then right
-  for (int e = threadIdx.x; e < szl; e += 256) gl[e] = Gl[e];
-  for (int e = threadIdx.x; e < szr; e += 256) gr[e] = Gr[e];
+  int* info = reinterpret_cast<int*>(tile + n * w + (GLDS ? 2 * gmax : 0));   // per index: (off, size, poff) of its block
+  if (GLDS) {
+    V2* gl = tile + n * w;
+    V2* gr = gl + gmax;
+    const int szl = btl[3 * nbl] + btl[3 * nbl - 1] * btl[3 * nbl - 1];
+    const int szr = btr[3 * nbr] + btr[3 * nbr - 1] * btr[3 * nbr - 1];
+    for (int e = threadIdx.x; e < szl; e += 256) gl[e] = Gl[e];
+    for (int e = threadIdx.x; e < szr; e += 256) gr[e] = Gr[e];
+    Gl = gl;
+    Gr = gr;
+  }
   for (int c = threadIdx.x; c < n; c += 256) {
     int bl = 0, br = 0;
     while (bl + 1 < nbl && c >= btl[1 + 3 * (bl + 1)]) ++bl;
@@ -735,7 +743,7 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
     if (lane < w) tile[r * w + lane] = v;
   }
   __syncthreads();
-  constexpr int RPW = 8;   // rows per wave: n <= 32
+  // RPW rows per wave: n <= 4 RPW
   V2 acc[RPW];
   // left: Y[a'][col] = sum over a in the block of a' of conj(Gl[a][a']) X[a][col]
 #pragma unroll
@@ -747,7 +755,7 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
       const int off = __builtin_amdgcn_readfirstlane(info[3 * ap]);
       const int sz = __builtin_amdgcn_readfirstlane(info[3 * ap + 1]);
       const int po = __builtin_amdgcn_readfirstlane(info[3 * ap + 2]), rr = ap - off;
-      for (int k = 0; k < sz; ++k) cfma_conj(s, tile[(off + k) * w + lane], gl[po + k * sz + rr]);
+      for (int k = 0; k < sz; ++k) cfma_conj(s, tile[(off + k) * w + lane], Gl[po + k * sz + rr]);
     }
     acc[i] = s;
   }
@@ -765,7 +773,7 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
 #pragma unroll
   for (int i = 0; i < RPW; ++i) acc[i] = V2{0, 0};
   for (int k = 0; k < sz; ++k) {
-    const V2 g = gr[po + cc * sz + k];
+    const V2 g = Gr[po + cc * sz + k];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int a = wave + 4 * i;
@@ -779,18 +787,49 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
   }
 }
 
-void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s,
+// Green's function blocks are staged in LDS when they fit next to the tile (LDS_CAP bytes).
+constexpr size_t LDS_CAP = 64 * 1024;
+
+template <typename V2, int CW>
+void launch_right_t(dim3 g, size_t el, size_t gmax, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab,
+                    int ncol) {
+  const size_t with = (el + gmax) * sizeof(V2);
+  if (with <= LDS_CAP) hipLaunchKernelGGL((k_rowblock_right<V2, CW, true>), g, dim3(256), with, s, sg, b, btab, ncol);
+  else hipLaunchKernelGGL((k_rowblock_right<V2, CW, false>), g, dim3(256), el * sizeof(V2), s, sg, b, btab, ncol);
+}
+
+void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, int gmax, hipStream_t s,
                            bool fp32) {
   if (l.nseg == 0) return;
-  const dim3 g((l.maxrows + RB_ROWS - 1) / RB_ROWS, l.nseg);
-  const size_t el = size_t(RB_ROWS) * ncol + size_t(ncol) * ncol;
-  const size_t ex = ncol * sizeof(int) + 16;
-  if (fp32)
-    hipLaunchKernelGGL(k_rowblock_right<float2>, g, dim3(256), el * sizeof(float2) + ex, s, (const RowSeg*)l.segs, b,
-                       btab, ncol);
+  const bool wide = ncol > 32;
+  const int rows = wide ? 32 : 64;
+  const dim3 g((l.maxrows + rows - 1) / rows, l.nseg);
+  const size_t el = size_t(rows) * ncol;
+  const RowSeg* sg = (const RowSeg*)l.segs;
+  if (fp32) {
+    if (wide) launch_right_t<float2, 64>(g, el, gmax, s, sg, b, btab, ncol);
+    else launch_right_t<float2, 32>(g, el, gmax, s, sg, b, btab, ncol);
+  } else {
+    if (wide) launch_right_t<double2, 64>(g, el, gmax, s, sg, b, btab, ncol);
+    else launch_right_t<double2, 32>(g, el, gmax, s, sg, b, btab, ncol);
+  }
+}
+
+template <typename V2, int RPW>
+void launch_both_r(dim3 g, int n, int w, int gmax, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
+  const size_t ex = 6 * n * sizeof(int) + 16;
+  const size_t with = (size_t(n) * w + 2 * size_t(gmax)) * sizeof(V2) + ex;
+  if (with <= LDS_CAP)
+    hipLaunchKernelGGL((k_rowblock_both<V2, true, RPW>), g, dim3(256), with, s, sg, b, btab, n, gmax);
   else
-    hipLaunchKernelGGL(k_rowblock_right<double2>, g, dim3(256), el * sizeof(double2) + ex, s, (const RowSeg*)l.segs,
-                       b, btab, ncol);
+    hipLaunchKernelGGL((k_rowblock_both<V2, false, RPW>), g, dim3(256), size_t(n) * w * sizeof(V2) + ex, s, sg, b,
+                       btab, n, gmax);
+}
+
+template <typename V2>
+void launch_both_t(dim3 g, int n, int w, int gmax, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
+  if (n <= 32) launch_both_r<V2, 8>(g, n, w, gmax, s, sg, b, btab);
+  else launch_both_r<V2, 16>(g, n, w, gmax, s, sg, b, btab);
 }
 
 void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, int gmax, hipStream_t s,
@@ -798,16 +837,10 @@ void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, 
   if (l.nseg == 0) return;
   const int w = rbb_nq(n) * n;
   const dim3 g((l.maxrows + w - 1) / w, l.nseg);
-  const size_t el = size_t(n) * w + 2 * size_t(gmax);
-  const size_t ex = 6 * n * sizeof(int) + 16;
-  if (fp32)
-    hipLaunchKernelGGL(k_rowblock_both<float2>, g, dim3(256), el * sizeof(float2) + ex, s, (const RowSeg*)l.segs, b,
-                       btab, n);
-  else
-    hipLaunchKernelGGL(k_rowblock_both<double2>, g, dim3(256), el * sizeof(double2) + ex, s, (const RowSeg*)l.segs,
-                       b, btab, n);
+  const RowSeg* sg = (const RowSeg*)l.segs;
+  if (fp32) launch_both_t<float2>(g, n, w, gmax, s, sg, b, btab);
+  else launch_both_t<double2>(g, n, w, gmax, s, sg, b, btab);
 }
-
 
 // ----------------------------------------------------------------------------
 // Packed-block helpers.

@@ -467,8 +467,8 @@ int device_init(Ctx& c, void* stream) {
   for (int i = 0; i < nib; ++i)
     for (int sz : c.bao[i].size) sumsq_ao[i] += double(sz) * sz;
   const double pscale = -c.prm.spin / nk;
-  if (no > 32) {   // the block multiplies give each orbital column one lane
-    c.err = "orbital basis larger than 32 functions";
+  if (no > 64) {   // the block multiplies give each orbital column one lane
+    c.err = "orbital basis larger than 64 functions";
     return GWSYM_ESHAPE;
   }
   // P0^q(tau_j)[Q, Q'] = -(s/Nk) sum_k sum_(a,b) Vp(Q)_ab conj(W(Q')_ab) with
@@ -1054,7 +1054,7 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
     timed(d, s, PC_SA, ra.macs, [&] { launch_wgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, f32, mask); }, ra.bytes);
     const Range& rr = d.s_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
-    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s, f32); }, rr.bytes);
+    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, d.gmax, s, f32); }, rr.bytes);
     const Range& rc = d.s_gemmC.launches[l];
     timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, f32, mask); }, rc.bytes);
     const Range& rp = d.s_pack.launches[l];

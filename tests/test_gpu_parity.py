@@ -45,7 +45,8 @@ def test_g0(name, mode):
 
 CASES = [("cfg0", "full"), ("cfg0", "block"), ("small_sc2", "block"), ("small_rocksalt", "block"),
          ("small_rocksalt", "rotate"), ("small_diamond", "block"), ("small_diamond", "rotate"),
-         ("small_diamond", "full"), ("small_sc4", "block")]
+         ("small_diamond", "full"), ("small_sc4", "block"), ("wide_rocksalt", "block"), ("wide_diamond", "block"),
+         ("wide_diamond", "rotate")]
 
 
 @pytest.mark.parametrize("name,mode", CASES)
@@ -106,7 +107,7 @@ def test_deterministic_rerun():
 TOL32 = 1e-6
 
 
-@pytest.mark.parametrize("name", ["cfg0", "small_sc4", "small_diamond"])
+@pytest.mark.parametrize("name", ["cfg0", "small_sc4", "small_diamond", "wide_diamond"])
 def test_fp32_contractions(name):
     say(f"[fp32] {name}")
     run = GpuRun(name, MODES["block"], precision=1)
