@@ -232,6 +232,9 @@ def workload(name: str) -> Workload:
     if name == "small_diamond4":
         return Workload(name, "diamond", 4, shells_on_atoms([S, P], 2),
                         shells_on_atoms([S, P, D], 2), 8, 20.0, BASE_SEED + 14)
+    if name == "gamma_sc":         # a single k point (Gamma only)
+        return Workload(name, "sc", 1, shells_on_atoms([S, P, D], 1),
+                        shells_on_atoms(_AUX25 * 2, 1), 16, 20.0, BASE_SEED + 17)
     if name == "wide_rocksalt":    # cfg2 orbital basis (nao 52 > 32), small mesh and aux basis
         return Workload(name, "rocksalt", 2, shells_on_atoms(_AO26, 2),
                         shells_on_atoms([S, P, D, F_], 2), 16, 30.0, BASE_SEED + 15)

@@ -153,7 +153,9 @@ int64_t gwsym_table_size(const gwsym_ctx* ctx, const char* name);
 int gwsym_get(const gwsym_ctx* ctx, const char* name, void* out, int64_t nbytes);
 
 /* Allocates the device tables and workspaces on the current HIP device and uploads the
- * symmetry tables.  Must follow gwsym_build_symmetry_basis.  Synchronises `stream`. */
+ * symmetry tables.  Must follow gwsym_build_symmetry_basis.  Synchronises `stream`.
+ * Size limits (GWSYM_ESHAPE otherwise): nao <= 64; orbital blocks <= 60 functions (free
+ * G0); auxiliary blocks <= 512 functions (screened-interaction inverse). */
 int gwsym_device_init(gwsym_ctx* ctx, void* stream);
 
 /* Sec. 4.2-4.3 / eq. C_blk: takes V^{k0,k'}(Q) for every representative k0 (in "ibz"

@@ -10,7 +10,9 @@ def crystal_arrays(cr):
     return cr.lattice, cr.positions, rot, trans
 
 
-def make_context(wl, mode=None, precision=0, half_tau=True, tau_chunk=0, build=True):
+def make_context(wl, mode=None, precision=0, half_tau=True, tau_chunk=0, build=True, identity_only=False):
+    """identity_only: give the library the trivial group (every block is the whole matrix,
+    every mesh point is irreducible) although the inputs have the crystal's symmetry."""
     from paper_2405_09494_amd import gwsym
     if mode is None:
         mode = gwsym.MODE_BLOCK
@@ -18,6 +20,8 @@ def make_context(wl, mode=None, precision=0, half_tau=True, tau_chunk=0, build=T
     if build:
         cr = crystal(wl.crystal)
         lat, pos, rot, trans = crystal_arrays(cr)
+        if identity_only:
+            rot, trans = rot[:1], trans[:1]
         ctx.build_symmetry_basis(lat, pos, rot, trans, wl.n, wl.ao, wl.aux)
     return ctx
 

@@ -80,6 +80,23 @@ def test_iteration(name, mode):
     assert e < TOL
 
 
+@pytest.mark.parametrize("name,mode,identity_only", [("gamma_sc", "block", False), ("gamma_sc", "full", False),
+                                                    ("small_rocksalt", "block", True)])
+def test_degenerate(name, mode, identity_only):
+    """A single k point, and the trivial group (one block per matrix, every point irreducible)."""
+    say(f"[degenerate] {name} {mode} identity_only={identity_only}")
+    run = GpuRun(name, MODES[mode], identity_only=identity_only)
+    ref = oracle_run(name)
+    r = ref["iters"][0]
+    run.g0()
+    c = run.ctx
+    c.iteration(run.F, run.G, run.P0, run.P, run.S, run.mu, ref["n_target"] or 0.0)
+    for kind, buf, key in ((2, run.P0, "P0"), (2, run.P, "P"), (1, run.S, "Sigma"), (1, run.G, "G")):
+        e = rel(run.full(kind, buf), r[key])
+        say(f"  {key} {e:.2e}")
+        assert e < TOL
+
+
 def test_full_tau_without_mirror():
     say("[no half tau] small_rocksalt block")
     run = GpuRun("small_rocksalt", 2, half_tau=False, tau_chunk=5)
