@@ -441,6 +441,7 @@ int device_init(Ctx& c, void* stream) {
     J = int(std::max(1.0, std::min(double(nt), budget / double(slab))));
   }
   J = std::min(J, nt);
+  if (c.prm.half_tau && nt >= 2) J = std::max(J, 2);   // a tau and its mirror share a chunk
   d.tau_chunk = J;
   const int nthalf = c.prm.half_tau ? (nt + 1) / 2 : nt;
 
@@ -537,74 +538,94 @@ int device_init(Ctx& c, void* stream) {
     if (nb > 0) bins_ao[i].push_back({r0, nb});
   }
   // Y(k', s') = P_blk^T Vs (per auxiliary block), Z = Y G^{k'}(tau_j) (block multiply),
-  // Sigma = -(1/Nk) sum_(k', s') Z Vs^H over all orbital blocks of k0 at once, then the
-  // diagonal blocks are gathered into Sigma_blk; only the block work is counted.
+  // Sigma = -(1/Nk) sum_(k', s') Z Vs^H on the diagonal squares of the bins, then the diagonal
+  // blocks are gathered into Sigma_blk; only the block work is counted.
+  // tau units: with time reversal P(beta - tau) = P(tau) (the reading that mirrors P0), so
+  // Y(tau) = Y(beta - tau): a unit is a tau of the first half with its mirror, Y is formed
+  // once per unit, and the block multiply, the orbital contraction and the gather run for both.
+  std::vector<std::pair<int, int>> units;   // (j, mirror or -1); the j are consecutive
+  if (c.prm.half_tau) {
+    for (int j = 0; j < (nt + 1) / 2; ++j) units.push_back({j, nt - 1 - j != j ? nt - 1 - j : -1});
+  } else {
+    for (int j = 0; j < nt; ++j) units.push_back({j, -1});
+  }
   for (int i = 0; i < nib; ++i) {
     const int k0 = c.ibz[i];
     const Blocks& BO = c.bao[i];
-    for (int j0 = 0; j0 < nt; j0 += J) {
-      const int j1 = std::min(nt, j0 + J);
-      for (int j = j0; j < j1; ++j) {
-        const int jj = j - j0;
-        for (int kp = 0; kp < nk; ++kp) {
-          const int q = mesh.sub(k0, kp), iq = c.rep[q], ik = c.rep[kp];
-          const Blocks& BQ = c.baux[iq];
-          const i64 vs = (i64(i) * nk + kp) * na * no * no;
-          const i64 wo = (i64(jj) * nk + kp) * na * no * no;
-          RowSeg r{};
-          r.inbuf = B_W1; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
-          r.in_off = wo; r.out_off = wo; r.g_off = c.g_off[ik] + i64(j) * c.bao[ik].packed; r.nrows = na * no;
-          d.s_right.add(r, double(na) * no * sumsq_ao[ik], double(na) * no * no);
-        }
-        if (j == j0) {
-          // Y = P_blk^T Vs with the rows (tau, s') of all tau of the chunk in one problem per
-          // (k', auxiliary block): the Vs rows are read once for every tau
-          const int jc = j1 - j0;
-          for (int kp = 0; kp < nk; ++kp) {
-            const int q = mesh.sub(k0, kp), iq = c.rep[q];
-            const Blocks& BQ = c.baux[iq];
-            const i64 vs = (i64(i) * nk + kp) * na * no * no;
-            for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
-              const int m = BQ.size[sg], off = BQ.off[sg];
-              GemmProblem p = gp(jc * m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j0) * BQ.packed + BQ.poff[sg], m, 0, 0,
-                                 OP_T, B_VS, vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1,
-                                 i64(kp) * na * no * no + i64(off) * no * no, i64(no) * no, 0);
-              p.rdiv = m;
-              p.sArb = BQ.packed;
-              p.sCrb = slab;
-              d.s_gemmA.add(p);
-            }
-          }
-        }
-        // only the diagonal blocks of Sigma are kept: consecutive orbital blocks are grouped into
-        // bins of at most 16 rows and each bin's diagonal square is one problem, with the rows
-        // (tau, a) of all tau of the chunk stacked
-        if (j == j0) {
-          const int jc = j1 - j0;
-          for (const auto& bn : bins_ao[i]) {
-            const int r0 = bn.first, nb = bn.second;
-            GemmProblem p = gp(jc * nb, nb, no, nk * na, 1, B_W2, i64(r0) * no, no, i64(no) * no, 0, OP_N, B_VS,
-                               i64(i) * nk * na * no * no + i64(r0) * no, no, i64(no) * no, 0, OP_H, B_SCR,
-                               i64(r0) * no + r0, no, 0, -1.0 / nk);
-            p.rdiv = nb;
-            p.sArb = slab;
-            p.sCrb = i64(no) * no;
-            double algo = 0;
-            for (size_t rb = 0; rb < BO.size.size(); ++rb)
-              if (BO.off[rb] >= r0 && BO.off[rb] < r0 + nb) algo += double(BO.size[rb]) * BO.size[rb];
-            d.s_gemmC.add(p, double(jc) * algo * no * double(nk) * na);
-          }
-        }
-        for (size_t rb = 0; rb < BO.size.size(); ++rb) {
-          const int n = BO.size[rb], off = BO.off[rb];
-          d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(jj) * no * no + i64(off) * no + off,
-                                    c.g_off[i] + i64(j) * BO.packed + BO.poff[rb], no});
+    for (size_t u0 = 0; u0 < units.size();) {
+      // units of this chunk: at most J tau (workspace slabs) in all
+      size_t u1 = u0;
+      int nslot = 0;
+      while (u1 < units.size() && nslot + (units[u1].second >= 0 ? 2 : 1) <= J) nslot += units[u1++].second >= 0 ? 2 : 1;
+      const int nu = int(u1 - u0), j0 = units[u0].first;
+      std::vector<int> slot_tau;   // tau of each workspace slot
+      std::vector<int> slot_unit;  // unit (Y slab) of each slot
+      for (int uu = 0; uu < nu; ++uu) {
+        slot_tau.push_back(units[u0 + uu].first);
+        slot_unit.push_back(uu);
+        if (units[u0 + uu].second >= 0) {
+          slot_tau.push_back(units[u0 + uu].second);
+          slot_unit.push_back(uu);
         }
       }
+      // Y = P_blk^T Vs with the rows (unit, s') in one problem per (k', auxiliary block): the Vs
+      // rows are read once for every tau of the chunk
+      for (int kp = 0; kp < nk; ++kp) {
+        const int q = mesh.sub(k0, kp), iq = c.rep[q];
+        const Blocks& BQ = c.baux[iq];
+        const i64 vs = (i64(i) * nk + kp) * na * no * no;
+        for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
+          const int m = BQ.size[sg], off = BQ.off[sg];
+          GemmProblem p = gp(nu * m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j0) * BQ.packed + BQ.poff[sg], m, 0, 0,
+                             OP_T, B_VS, vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1,
+                             i64(kp) * na * no * no + i64(off) * no * no, i64(no) * no, 0);
+          p.rdiv = m;
+          p.sArb = BQ.packed;
+          p.sCrb = slab;
+          d.s_gemmA.add(p);
+        }
+      }
+      // Z(tau) = Y(unit) G^{k'}(tau) for every tau of the chunk
+      for (int sl = 0; sl < nslot; ++sl) {
+        const int j = slot_tau[sl];
+        for (int kp = 0; kp < nk; ++kp) {
+          const int ik = c.rep[kp];
+          RowSeg r{};
+          r.inbuf = B_W1; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
+          r.in_off = (i64(slot_unit[sl]) * nk + kp) * na * no * no;
+          r.out_off = (i64(sl) * nk + kp) * na * no * no;
+          r.g_off = c.g_off[ik] + i64(j) * c.bao[ik].packed;
+          r.nrows = na * no;
+          d.s_right.add(r, double(na) * no * sumsq_ao[ik], double(na) * no * no);
+        }
+      }
+      // only the diagonal blocks of Sigma are kept: consecutive orbital blocks are grouped into
+      // bins of at most 16 rows and each bin's diagonal square is one problem, with the rows
+      // (slot, a) of all tau of the chunk stacked
+      for (const auto& bn : bins_ao[i]) {
+        const int r0 = bn.first, nb = bn.second;
+        GemmProblem p = gp(nslot * nb, nb, no, nk * na, 1, B_W2, i64(r0) * no, no, i64(no) * no, 0, OP_N, B_VS,
+                           i64(i) * nk * na * no * no + i64(r0) * no, no, i64(no) * no, 0, OP_H, B_SCR,
+                           i64(r0) * no + r0, no, 0, -1.0 / nk);
+        p.rdiv = nb;
+        p.sArb = slab;
+        p.sCrb = i64(no) * no;
+        double algo = 0;
+        for (size_t rb = 0; rb < BO.size.size(); ++rb)
+          if (BO.off[rb] >= r0 && BO.off[rb] < r0 + nb) algo += double(BO.size[rb]) * BO.size[rb];
+        d.s_gemmC.add(p, double(nslot) * algo * no * double(nk) * na);
+      }
+      for (int sl = 0; sl < nslot; ++sl)
+        for (size_t rb = 0; rb < BO.size.size(); ++rb) {
+          const int n = BO.size[rb], off = BO.off[rb];
+          d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(sl) * no * no + i64(off) * no + off,
+                                    c.g_off[i] + i64(slot_tau[sl]) * BO.packed + BO.poff[rb], no});
+        }
       d.s_gemmA.close();
       d.s_right.close();
       d.s_gemmC.close();
       d.s_pack.close();
+      u0 = u1;
     }
   }
 

@@ -64,8 +64,11 @@ def run(d, precision):
     torch.cuda.synchronize()
     p0 = full.view(nk, nt, na, na)[d["q"], d["j"]].cpu().numpy()
     del full
+    # the stand-in P is placed at tau_js and at beta - tau_js (P(tau) = P(beta - tau), the
+    # bosonic symmetry with time reversal that the half-tau mode relies on), zero elsewhere
     Pin = torch.zeros((len(d["ibz"]), nt, na, na), dtype=torch.complex128, device=dev)
     Pin[:, d["js"]] = d["X"][torch.as_tensor(d["ibz"], device=dev)]
+    Pin[:, nt - 1 - d["js"]] = d["X"][torch.as_tensor(d["ibz"], device=dev)]
     ctx.to_block(2, Pin, Pb)
     ctx.self_energy(G, Pb, S)
     sfull = torch.zeros(nk * nt * no * no, dtype=torch.complex128, device=dev)
