@@ -25,7 +25,8 @@ struct GemmPlanDev {
 
 // rows [0, nrows) of a row-major slab (right multiply), or the slab width (left multiply)
 // One slab for a block-diagonal multiply.  Right multiply: nrows rows of ncol columns, each
-// row times the block-diagonal matrix at g_off.  Left multiply: nb_rows rows of nrows
+// row times the block-diagonal matrix at g_off (and, with out_off2 >= 0, also times the one at
+// g_off2 with the same blocks, into out_off2).  Left multiply: nb_rows rows of nrows
 // columns, G^H (at g_off) applied from the left.  Both-sided multiply: nb_rows rows of
 // nrows columns made of nrows / nb_rows square nb_rows x nb_rows matrices side by side, each
 // X -> Gl^H X Gr^H with Gl at (g_off, blk) and Gr at (g_off2, blk2).
@@ -34,6 +35,7 @@ struct RowSeg {
   int64_t in_off, out_off, g_off;
   int nrows, blk2;
   int64_t g_off2;
+  int64_t out_off2;   // right multiply: >= 0 writes a second product, by the matrix at g_off2
 };
 
 // n x n matrices per workgroup of the both-sided block multiply (at most 64 columns, n <= 32)

@@ -660,8 +660,10 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
   const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + int64_t(r0) * ncol;
   V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + int64_t(r0) * ncol;
   const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
+  const bool dual = sg.out_off2 >= 0;
+  const V2* G2 = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + (dual ? sg.g_off2 : sg.g_off);
   const int* bt = btab + sg.blk;  // bt[0] = count, then (off, size, poff) per block
-  V2* tile = reinterpret_cast<V2*>(lds_rr);   // nrows x ncol, then (GLDS) the packed blocks of G
+  V2* tile = reinterpret_cast<V2*>(lds_rr);   // nrows x ncol, then (GLDS) the packed blocks of G (and G2)
   const int nb = bt[0];
   for (int e = threadIdx.x; e < nrows * ncol; e += 256) tile[e] = in[e];
   if (GLDS) {
@@ -669,6 +671,11 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
     const int gsz = bt[3 * nb] + bt[3 * nb - 1] * bt[3 * nb - 1];   // poff + size^2 of the last block
     for (int e = threadIdx.x; e < gsz; e += 256) gs[e] = G[e];
     G = gs;
+    if (dual) {
+      V2* gs2 = gs + gsz;
+      for (int e = threadIdx.x; e < gsz; e += 256) gs2[e] = G2[e];
+      G2 = gs2;
+    }
   }
   __syncthreads();
   const int c = threadIdx.x % CW, g = threadIdx.x / CW;
@@ -679,10 +686,31 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
   V2 acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = V2{0, 0};
-  for (int k = 0; k < sz; ++k) {
-    const V2 gv = G[po + k * sz + cc];
+  if (!dual) {
+    for (int k = 0; k < sz; ++k) {
+      const V2 gv = G[po + k * sz + cc];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) cfma(acc[i], tile[min(g + NG * i, nrows - 1) * ncol + off + k], gv);
+      for (int i = 0; i < 8; ++i) cfma(acc[i], tile[min(g + NG * i, nrows - 1) * ncol + off + k], gv);
+    }
+  } else {
+    V2 acc2[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc2[i] = V2{0, 0};
+    for (int k = 0; k < sz; ++k) {
+      const V2 gv = G[po + k * sz + cc], gv2 = G2[po + k * sz + cc];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const V2 x = tile[min(g + NG * i, nrows - 1) * ncol + off + k];
+        cfma(acc[i], x, gv);
+        cfma(acc2[i], x, gv2);
+      }
+    }
+    V2* out2 = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off2 + int64_t(r0) * ncol;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int r = g + NG * i;
+      if (r < nrows) out2[r * ncol + c] = acc2[i];
+    }
   }
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -793,7 +821,7 @@ constexpr size_t LDS_CAP = 64 * 1024;
 template <typename V2, int CW>
 void launch_right_t(dim3 g, size_t el, size_t gmax, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab,
                     int ncol) {
-  const size_t with = (el + gmax) * sizeof(V2);
+  const size_t with = (el + 2 * gmax) * sizeof(V2);
   if (with <= LDS_CAP) hipLaunchKernelGGL((k_rowblock_right<V2, CW, true>), g, dim3(256), with, s, sg, b, btab, ncol);
   else hipLaunchKernelGGL((k_rowblock_right<V2, CW, false>), g, dim3(256), el * sizeof(V2), s, sg, b, btab, ncol);
 }

@@ -585,18 +585,25 @@ int device_init(Ctx& c, void* stream) {
           d.s_gemmA.add(p);
         }
       }
-      // Z(tau) = Y(unit) G^{k'}(tau) for every tau of the chunk
+      // Z(tau) = Y(unit) G^{k'}(tau) for every tau of the chunk; a unit's Y is read once for
+      // both of its tau
       for (int sl = 0; sl < nslot; ++sl) {
-        const int j = slot_tau[sl];
+        if (sl > 0 && slot_unit[sl] == slot_unit[sl - 1]) continue;   // the mirror slot, done below
+        const bool pair = sl + 1 < nslot && slot_unit[sl + 1] == slot_unit[sl];
         for (int kp = 0; kp < nk; ++kp) {
           const int ik = c.rep[kp];
           RowSeg r{};
           r.inbuf = B_W1; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
           r.in_off = (i64(slot_unit[sl]) * nk + kp) * na * no * no;
           r.out_off = (i64(sl) * nk + kp) * na * no * no;
-          r.g_off = c.g_off[ik] + i64(j) * c.bao[ik].packed;
+          r.g_off = c.g_off[ik] + i64(slot_tau[sl]) * c.bao[ik].packed;
+          r.out_off2 = -1;
+          if (pair) {
+            r.out_off2 = (i64(sl + 1) * nk + kp) * na * no * no;
+            r.g_off2 = c.g_off[ik] + i64(slot_tau[sl + 1]) * c.bao[ik].packed;
+          }
           r.nrows = na * no;
-          d.s_right.add(r, double(na) * no * sumsq_ao[ik], double(na) * no * no);
+          d.s_right.add(r, double(na) * no * sumsq_ao[ik] * (pair ? 2 : 1), double(na) * no * no * (pair ? 1.5 : 1));
         }
       }
       // only the diagonal blocks of Sigma are kept: consecutive orbital blocks are grouped into
