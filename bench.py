@@ -311,25 +311,32 @@ def main():
         log(f"[bench] full: {s_full:.3f} s/iteration, Sigma block vs full {err:.2e}")
         del full
 
-    # ---- the same block path with FP32 contractions (FP64 transforms, inverses and mu) ----
+    # ---- the same block path with reduced-precision contractions (FP64 transforms, inverses
+    # and mu): FP32 operands on the FP32 MFMA, and split-bfloat16 products on the bfloat16 MFMA
     if not args.no_fp32:
-        f32 = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=gwsym.FP32), F_all, V_all,
-                   torch, dev, graph=bool(args.graph))
-        s_f32 = time_steps(f32, args.steps, args.warmup, torch)
-        for pth in (blk, f32):   # one iteration from the same G0 in both precisions
-            pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)
-            pth.step()
-        torch.cuda.synchronize()
-        a, b = f32.full(1, f32.S), blk.full(1, blk.S)
-        err32 = float((a - b).abs().max() / b.abs().max())
-        ga, gb = f32.full(1, f32.G), blk.full(1, blk.G)
-        nk_, nt_, no_ = blk.ctx.nk, blk.ctx.ntau, blk.ctx.nao
-        occ = lambda g: -torch.diagonal(g.view(nk_, nt_, no_, no_)[:, -1], dim1=-2, dim2=-1).real
-        occ_err = float((occ(ga) - occ(gb)).abs().max())
-        out["fp32_contractions"] = {"s_per_iteration": s_f32, "speedup_vs_fp64_block": s_blk / s_f32,
-                                    "sigma_rel_err_vs_fp64": err32, "occupation_max_abs_err_vs_fp64": occ_err}
-        log(f"[bench] fp32 contractions: {s_f32:.4f} s/iteration, Sigma vs fp64 {err32:.2e}, occupations {occ_err:.2e}")
-        del f32
+        for key, prec in (("fp32_contractions", gwsym.FP32), ("bf16x6_contractions", gwsym.BF16X6),
+                          ("bf16x3_contractions", gwsym.BF16X3)):
+            red = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=prec), F_all, V_all,
+                       torch, dev, graph=bool(args.graph))
+            s_red = time_steps(red, args.steps, args.warmup, torch)
+            for pth in (blk, red):   # one iteration from the same G0 in both precisions
+                pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)
+                pth.step()
+            torch.cuda.synchronize()
+            a, b = red.full(1, red.S), blk.full(1, blk.S)
+            err_s = float((a - b).abs().max() / b.abs().max())
+            a, b = red.full(2, red.P0), blk.full(2, blk.P0)
+            err_p0 = float((a - b).abs().max() / b.abs().max())
+            ga, gb = red.full(1, red.G), blk.full(1, blk.G)
+            nk_, nt_, no_ = blk.ctx.nk, blk.ctx.ntau, blk.ctx.nao
+            occ = lambda g: -torch.diagonal(g.view(nk_, nt_, no_, no_)[:, -1], dim1=-2, dim2=-1).real
+            occ_err = float((occ(ga) - occ(gb)).abs().max())
+            out[key] = {"s_per_iteration": s_red, "speedup_vs_fp64_block": s_blk / s_red,
+                        "p0_rel_err_vs_fp64": err_p0, "sigma_rel_err_vs_fp64": err_s,
+                        "occupation_max_abs_err_vs_fp64": occ_err}
+            log(f"[bench] {key}: {s_red:.4f} s/iteration, P0 vs fp64 {err_p0:.2e}, Sigma {err_s:.2e}, "
+                f"occupations {occ_err:.2e}")
+            del red
 
     if not args.no_cpu:
         ibz = blk.ctx.table("ibz")

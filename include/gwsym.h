@@ -69,10 +69,17 @@ typedef enum {
   GWSYM_MODE_BLOCK = 2   /* irreducible wedge and isotypic blocks (eq. mat_blk, eq. C_blk) */
 } gwsym_mode;
 
+/* Arithmetic of the P0 and Sigma contractions (eq. P0, eq. sigma).  In every mode the
+   Fourier transforms, the Dyson inverses, the chemical-potential search and the G transform
+   stay FP64, and every tensor passed through this interface is complex128. */
 typedef enum {
-  GWSYM_FP64 = 0,        /* contractions in FP64 on MFMA */
-  GWSYM_FP32 = 1         /* contractions with FP32 operands and FP32 MFMA accumulation;
-                            transforms, inverses and mu stay FP64 */
+  GWSYM_FP64 = 0,        /* FP64 operands on the FP64 MFMA */
+  GWSYM_FP32 = 1,        /* FP32 operands, FP32 MFMA accumulation per tile, split sums in FP64 */
+  GWSYM_BF16X6 = 2,      /* FP32 operands, each split into three bfloat16 pieces x = hi + mid + lo
+                            (round to nearest even from the remainder); the six piece products
+                            with piece indices adding to at most 2 on the bfloat16 MFMA, FP32
+                            accumulation: FP32-level error */
+  GWSYM_BF16X3 = 3       /* two pieces hi + lo and three products: faster, about 1e-5 relative */
 } gwsym_precision;
 
 typedef struct {

@@ -21,7 +21,7 @@ int check_params(const gwsym_params* p, std::string& err) {
   if (p->nw < 1) return err = "nw must be >= 1", GWSYM_EINVAL;
   if (2 * p->nw - 1 < p->ntau) return err = "need 2 nw - 1 >= ntau for the inverse transform", GWSYM_EINVAL;
   if (p->mode < 0 || p->mode > 2) return err = "unknown mode", GWSYM_EINVAL;
-  if (p->precision < 0 || p->precision > 1) return err = "unknown precision", GWSYM_EINVAL;
+  if (p->precision < GWSYM_FP64 || p->precision > GWSYM_BF16X3) return err = "unknown precision", GWSYM_EINVAL;
   if (p->tau_chunk < 0) return err = "tau_chunk must be >= 0", GWSYM_EINVAL;
   if (!(p->spin > 0)) return err = "spin factor must be positive", GWSYM_EINVAL;
   return GWSYM_OK;

@@ -84,7 +84,9 @@ void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab,
 void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, int gmax, hipStream_t s,
                           bool fp32);
 // Wave-tile complex GEMM over the same problem and tile lists (tiles of at most 32 x 32).
-void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, bool fp32,
+// arith: 0 FP64 operands and MFMA; on float2 operands 1 FP32 MFMA, 2 three-piece and
+// 3 two-piece bfloat16 splits on the bfloat16 MFMA with FP32 accumulation
+void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, int arith,
                   unsigned f32mask);
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);

@@ -377,17 +377,78 @@ void launch_reduce_tag(const GemmPlanDev& p, const Bases& b, void* partials, hip
 // ----------------------------------------------------------------------------
 // Wave-tile grouped complex GEMM for the contractions: one wave per workgroup owns an output
 // tile of 16 or 32 rows by 16 or 32 columns (M2, N2) over its outer range.  The MFMA operands
-// come straight from global memory: in a step over four k values lane l holds row (column)
+// come straight from global memory: in a sub-step over four k values lane l holds row (column)
 // l % 16 of each 16-row quarter at k = 4 s + l / 16, so four lanes read 64 contiguous bytes of
-// a row.  The k steps of all outer indices of the tile form one sequence, taken two at a time
-// with the next pair in flight; the loop body has no branches (the last step of an odd count
-// and k values beyond K are zeroed through the B operand).  Rows and columns beyond the
-// problem read clamped, in-range addresses and are never stored.  No LDS, no barriers.
+// a row.  The sub-steps of all outer indices of the tile form one sequence, taken GS at a time
+// with the next group in flight; the loop body has no branches (sub-steps past the end of the
+// sequence and k values beyond K are zeroed through the B operand).  Rows and columns beyond
+// the problem read clamped, in-range addresses and are never stored.  No LDS, no barriers.
+//
+// Arithmetic (AR): 0 FP64 MFMA, 1 FP32 MFMA, and the split-bfloat16 forms on FP32 operands:
+// 2 splits each FP32 value into three bfloat16 pieces (hi + mid + lo, each rounded to nearest
+// even from the remainder of the previous ones) and sums the six piece products whose piece
+// indices add to at most 2; 3 splits into two pieces and sums three products.  Both accumulate
+// in FP32 on the 16 x 16 x 32 bfloat16 MFMA.  A group of eight sub-steps feeds one such MFMA:
+// lane l passes its eight values of the group as its eight k slots, for A and B alike, so
+// the slot-to-k assignment is the same on both sides and the sum over k is unchanged.
 
-template <typename R, int TAG, bool M2, bool N2>
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+template <int AR> struct WArith;
+template <> struct WArith<0> { using R = double; static constexpr int GS = 2, NS = 0; };
+template <> struct WArith<1> { using R = float; static constexpr int GS = 2, NS = 0; };
+template <> struct WArith<2> { using R = float; static constexpr int GS = 8, NS = 3; };
+template <> struct WArith<3> { using R = float; static constexpr int GS = 8, NS = 2; };
+
+// x = p[0] + p[1] + ... + rest: each piece is the bfloat16 nearest to what the pieces before
+// it leave over
+template <int NS>
+__device__ __forceinline__ void bf_split(const float (&x)[8], bf8 (&p)[NS]) {
+  float r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = x[i];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) p[s][i] = __bf16(r[i]);
+    if (s + 1 < NS) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) r[i] -= float(p[s][i]);
+    }
+  }
+}
+__device__ __forceinline__ bf8 bf_neg(bf8 v) {
+  u4 u = __builtin_bit_cast(u4, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf8, u);
+}
+__device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// c_re += a b_re-part sums and c_im likewise for one 16 x 16 quarter pair, from the pieces of
+// a = ar + i ai (with an = -ai) and b = br + i bi; the smaller piece products go first
+template <int NS>
+__device__ __forceinline__ void bf_cmac(const bf8 (&ar)[NS], const bf8 (&ai)[NS], const bf8 (&an)[NS],
+                                        const bf8 (&br)[NS], const bf8 (&bi)[NS], f4& cr, f4& ci) {
+#pragma unroll
+  for (int d = NS - 1; d >= 0; --d)
+#pragma unroll
+    for (int i = 0; i <= d; ++i) {
+      const int j = d - i;
+      cr = mfma_bf(ar[i], br[j], cr);
+      cr = mfma_bf(an[i], bi[j], cr);
+      ci = mfma_bf(ar[i], bi[j], ci);
+      ci = mfma_bf(ai[i], br[j], ci);
+    }
+}
+
+template <int AR, int TAG, bool M2, bool N2>
 __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ probs,
                                               const GemmTile* __restrict__ tiles, Bases bases,
                                               double2* __restrict__ partials, unsigned f32mask) {
+  using R = typename WArith<AR>::R;
+  constexpr int GS = WArith<AR>::GS, NS = WArith<AR>::NS;
   using V2 = typename Cx<R>::V2;
   using A4 = typename Cx<R>::A4;
   const GemmTile tl = tiles[blockIdx.x];
@@ -414,17 +475,17 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   const int64_t ak = aT ? P.lda : 1;
   const int64_t bk = bT ? 1 : P.ldb;
   // a tile of an N2 class covers nn / 2 consecutive 32-column chunks, walked in one sequence of
-  // K-step pairs so that the first loads of a chunk overlap the last MFMAs of the one before
+  // sub-step groups so that the first loads of a chunk overlap the last MFMAs of the one before
   const int nchunk = N2 ? (tl.nn >> 1) : 1;
-  const int nsub = (tl.t1 - tl.t0) * nk4, npair = (nsub + 1) >> 1, total = npair * nchunk;
+  const int nsub = (tl.t1 - tl.t0) * nk4, ngrp = (nsub + GS - 1) / GS, total = ngrp * nchunk;
   A4 c00r = {0, 0, 0, 0}, c00i = c00r, c01r = c00r, c01i = c00r, c10r = c00r, c10i = c00r, c11r = c00r, c11i = c00r;
   // fetch position: chunk, outer index t and k step j of the next sub-step; the mask zeroes
-  // k >= K and the sub-step past the end of a chunk's odd count
+  // k >= K and the sub-steps past the end of a chunk's sequence
   int fc = 0, ft = tl.t0, fj = 0, fs = 0;
   int64_t fbx0 = bcol(min(n0 + li, P.N - 1)), fbx1 = bcol(min(n0 + 16 + li, P.N - 1));
-  V2 fa[2][2], fb[2][2];
-  R fm[2];
-  auto fetch1 = [&](int h) {
+  V2 fa[GS][2], fb[GS][2];
+  R fm[GS];
+  auto fetch1 = [&](int h) __attribute__((always_inline)) {
     const bool live = fs < nsub;
     const int t = live ? ft : tl.t1 - 1;
     const int k = 4 * fj + kq;
@@ -441,7 +502,7 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       fj = 0;
       ++ft;
     }
-    if (fs == 2 * npair && fc + 1 < nchunk) {   // on to the next chunk
+    if (fs == GS * ngrp && fc + 1 < nchunk) {   // on to the next chunk
       ++fc;
       fs = 0;
       fj = 0;
@@ -450,6 +511,10 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       fbx0 = bcol(min(nc + li, P.N - 1));
       fbx1 = bcol(min(nc + 16 + li, P.N - 1));
     }
+  };
+  auto fetch = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < GS; ++h) fetch1(h);
   };
   const double2 al = make_double2(P.alpha_re, P.alpha_im);
   const bool cf32 = (f32mask >> P.cbuf) & 1u;
@@ -485,61 +550,92 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       }
     }
   };
-  if (total > 0) {
-    fetch1(0);
-    fetch1(1);
-  }
-  int cc = 0, cp = 0;   // chunk and pair being computed
+  if (total > 0) fetch();
+  int cc = 0, cp = 0;   // chunk and group being computed
   for (int st = 0; st < total; ++st) {
-    V2 a[2][2], b[2][2];
-    R m[2];
+    V2 a[GS][2], b[GS][2];
+    R m[GS];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < GS; ++h) {
       a[h][0] = fa[h][0];
       a[h][1] = M2 ? fa[h][1] : fa[h][0];
       b[h][0] = fb[h][0];
       b[h][1] = N2 ? fb[h][1] : fb[h][0];
       m[h] = fm[h];
     }
-    if (st + 1 < total) {
-      fetch1(0);
-      fetch1(1);
-    }
+    if (st + 1 < total) fetch();
+    if constexpr (NS == 0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const R a0r = R(a[h][0].x), a0i = R(a[h][0].y) * sA, a1r = R(a[h][1].x), a1i = R(a[h][1].y) * sA;
-      const R b0r = R(b[h][0].x) * m[h], b0i = R(b[h][0].y) * (sB * m[h]);
-      const R b1r = R(b[h][1].x) * m[h], b1i = R(b[h][1].y) * (sB * m[h]);
-      c00r = mfma16(a0r, b0r, c00r);
-      c00i = mfma16(a0r, b0i, c00i);
-      if (N2) {
-        c01r = mfma16(a0r, b1r, c01r);
-        c01i = mfma16(a0r, b1i, c01i);
+      for (int h = 0; h < GS; ++h) {
+        const R a0r = R(a[h][0].x), a0i = R(a[h][0].y) * sA, a1r = R(a[h][1].x), a1i = R(a[h][1].y) * sA;
+        const R b0r = R(b[h][0].x) * m[h], b0i = R(b[h][0].y) * (sB * m[h]);
+        const R b1r = R(b[h][1].x) * m[h], b1i = R(b[h][1].y) * (sB * m[h]);
+        c00r = mfma16(a0r, b0r, c00r);
+        c00i = mfma16(a0r, b0i, c00i);
+        if (N2) {
+          c01r = mfma16(a0r, b1r, c01r);
+          c01i = mfma16(a0r, b1i, c01i);
+        }
+        if (M2) {
+          c10r = mfma16(a1r, b0r, c10r);
+          c10i = mfma16(a1r, b0i, c10i);
+        }
+        if (M2 && N2) {
+          c11r = mfma16(a1r, b1r, c11r);
+          c11i = mfma16(a1r, b1i, c11i);
+        }
+        c00r = mfma16(-a0i, b0i, c00r);
+        c00i = mfma16(a0i, b0r, c00i);
+        if (N2) {
+          c01r = mfma16(-a0i, b1i, c01r);
+          c01i = mfma16(a0i, b1r, c01i);
+        }
+        if (M2) {
+          c10r = mfma16(-a1i, b0i, c10r);
+          c10i = mfma16(a1i, b0r, c10i);
+        }
+        if (M2 && N2) {
+          c11r = mfma16(-a1i, b1i, c11r);
+          c11i = mfma16(a1i, b1r, c11i);
+        }
       }
-      if (M2) {
-        c10r = mfma16(a1r, b0r, c10r);
-        c10i = mfma16(a1r, b0i, c10i);
+    } else {
+      // pieces of the B quarters (mask and conjugation applied first), then of each A quarter
+      bf8 br[2][NS], bi[2][NS];
+#pragma unroll
+      for (int q = 0; q < (N2 ? 2 : 1); ++q) {
+        float xr[8], xi[8];
+#pragma unroll
+        for (int h = 0; h < GS; ++h) {
+          xr[h] = b[h][q].x * m[h];
+          xi[h] = b[h][q].y * (sB * m[h]);
+        }
+        bf_split<NS>(xr, br[q]);
+        bf_split<NS>(xi, bi[q]);
       }
-      if (M2 && N2) {
-        c11r = mfma16(a1r, b1r, c11r);
-        c11i = mfma16(a1r, b1i, c11i);
-      }
-      c00r = mfma16(-a0i, b0i, c00r);
-      c00i = mfma16(a0i, b0r, c00i);
-      if (N2) {
-        c01r = mfma16(-a0i, b1i, c01r);
-        c01i = mfma16(a0i, b1r, c01i);
-      }
-      if (M2) {
-        c10r = mfma16(-a1i, b0i, c10r);
-        c10i = mfma16(a1i, b0r, c10i);
-      }
-      if (M2 && N2) {
-        c11r = mfma16(-a1i, b1i, c11r);
-        c11i = mfma16(a1i, b1r, c11i);
+#pragma unroll
+      for (int q = 0; q < (M2 ? 2 : 1); ++q) {
+        float xr[8], xi[8];
+#pragma unroll
+        for (int h = 0; h < GS; ++h) {
+          xr[h] = a[h][q].x;
+          xi[h] = a[h][q].y * sA;
+        }
+        bf8 ar[NS], ai[NS], an[NS];
+        bf_split<NS>(xr, ar);
+        bf_split<NS>(xi, ai);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) an[s] = bf_neg(ai[s]);
+        if (q == 0) {
+          bf_cmac<NS>(ar, ai, an, br[0], bi[0], c00r, c00i);
+          if (N2) bf_cmac<NS>(ar, ai, an, br[1], bi[1], c01r, c01i);
+        } else {
+          bf_cmac<NS>(ar, ai, an, br[0], bi[0], c10r, c10i);
+          if (N2) bf_cmac<NS>(ar, ai, an, br[1], bi[1], c11r, c11i);
+        }
       }
     }
-    if (++cp == npair) {
+    if (++cp == ngrp) {
       // end of a chunk: store it and start the next from zero
       const int cn0 = n0 + 32 * cc;
       store(cn0, 0, 0, c00r, c00i);
@@ -560,7 +656,7 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   }
 }
 
-template <typename R, int TAG>
+template <int AR, int TAG>
 void launch_wgemm_tag(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, unsigned mask) {
   const GemmProblem* pr = (const GemmProblem*)p.probs;
   const GemmTile* tl = (const GemmTile*)p.tiles;
@@ -573,30 +669,34 @@ void launch_wgemm_tag(const GemmPlanDev& p, const Bases& b, void* partials, hipS
     const dim3 g(n), t(64);
     const GemmTile* ts = tl + at;
     switch (sh) {
-      case 0: hipLaunchKernelGGL((k_wgemm<R, TAG, false, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
-      case 1: hipLaunchKernelGGL((k_wgemm<R, TAG, false, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
-      case 2: hipLaunchKernelGGL((k_wgemm<R, TAG, true, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
-      default: hipLaunchKernelGGL((k_wgemm<R, TAG, true, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 0: hipLaunchKernelGGL((k_wgemm<AR, TAG, false, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 1: hipLaunchKernelGGL((k_wgemm<AR, TAG, false, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 2: hipLaunchKernelGGL((k_wgemm<AR, TAG, true, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      default: hipLaunchKernelGGL((k_wgemm<AR, TAG, true, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
     }
     at += n;
   }
 }
 
-template <typename R>
+template <int AR>
 void launch_wgemm_t(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, unsigned mask) {
   switch (tag) {
-    case 1: launch_wgemm_tag<R, 1>(p, b, partials, s, mask); break;
-    case 2: launch_wgemm_tag<R, 2>(p, b, partials, s, mask); break;
-    case 3: launch_wgemm_tag<R, 3>(p, b, partials, s, mask); break;
-    default: launch_wgemm_tag<R, 0>(p, b, partials, s, mask); break;
+    case 1: launch_wgemm_tag<AR, 1>(p, b, partials, s, mask); break;
+    case 2: launch_wgemm_tag<AR, 2>(p, b, partials, s, mask); break;
+    case 3: launch_wgemm_tag<AR, 3>(p, b, partials, s, mask); break;
+    default: launch_wgemm_tag<AR, 0>(p, b, partials, s, mask); break;
   }
 }
 
-void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, bool fp32,
+void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, int arith,
                   unsigned f32mask) {
   if (p.ntiles > 0) {
-    if (fp32) launch_wgemm_t<float>(p, b, partials, s, tag, f32mask);
-    else launch_wgemm_t<double>(p, b, partials, s, tag, f32mask);
+    switch (arith) {
+      case 1: launch_wgemm_t<1>(p, b, partials, s, tag, f32mask); break;
+      case 2: launch_wgemm_t<2>(p, b, partials, s, tag, f32mask); break;
+      case 3: launch_wgemm_t<3>(p, b, partials, s, tag, f32mask); break;
+      default: launch_wgemm_t<0>(p, b, partials, s, tag, f32mask); break;
+    }
   }
   launch_reduce_tag(p, b, partials, s, tag, f32mask);
 }

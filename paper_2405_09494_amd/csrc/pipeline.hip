@@ -965,7 +965,7 @@ int device_load_V(Ctx& c, const void* Vin, void* stream) {
     launch_brgemm(plan_of(g2, g2.launches[l]), b, d.partials, s);
     launch_brgemm(plan_of(g3, g3.launches[l]), b, d.partials, s);
   }
-  if (c.prm.precision == GWSYM_FP32) {
+  if (c.prm.precision != GWSYM_FP64) {
     const size_t n = size_t(nib) * nk * pe;
     if (!d.VP32) {
       if ((st = dalloc(c, d, &d.VP32, n * 8))) return st;
@@ -1035,8 +1035,10 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
   Bases b = bases_of(d);
   b.p[B_G] = const_cast<void*>(G);
   b.p[B_OUT] = P0;
-  // FP32 contractions: FP32 copies of V (made once) and of G (here); W2 holds float2
-  const bool f32 = c.prm.precision == GWSYM_FP32;
+  // FP32 and split-bfloat16 contractions: FP32 copies of V (made once) and of G (here); W2
+  // holds float2
+  const bool f32 = c.prm.precision != GWSYM_FP64;
+  const int arith = c.prm.precision;
   unsigned mask = 0;
   if (f32) {
     launch_to_f32(G, d.G32, c.g_off[c.nibz], s);
@@ -1049,7 +1051,7 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
     RowSegList L{static_cast<RowSeg*>(d.p0_both.d) + rb.t0, rb.nt, rb.r0};
     timed(d, s, PC_LEFT, rb.macs, [&] { launch_rowblock_both(L, b, d.btab, c.nao, d.gmax, s, f32); }, rb.bytes);
     const Range& rg = d.p0_gemm.launches[l];
-    timed(d, s, PC_P0, rg.macs, [&] { launch_wgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, f32, mask); }, rg.bytes);
+    timed(d, s, PC_P0, rg.macs, [&] { launch_wgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, arith, mask); }, rg.bytes);
   }
   const Range& m = d.p0_mirror.launches[0];
   timed(d, s, PC_OTHER, 0, [&] { launch_copy(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s); });
@@ -1067,7 +1069,8 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
   b.p[B_G] = const_cast<void*>(G);
   b.p[B_P] = const_cast<void*>(P);
   b.p[B_OUT] = S;
-  const bool f32 = c.prm.precision == GWSYM_FP32;
+  const bool f32 = c.prm.precision != GWSYM_FP64;
+  const int arith = c.prm.precision;
   unsigned mask = 0;
   if (f32) {
     launch_to_f32(G, d.G32, c.g_off[c.nibz], s);
@@ -1079,12 +1082,12 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
   }
   for (size_t l = 0; l < d.s_gemmA.launches.size(); ++l) {
     const Range& ra = d.s_gemmA.launches[l];
-    timed(d, s, PC_SA, ra.macs, [&] { launch_wgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, f32, mask); }, ra.bytes);
+    timed(d, s, PC_SA, ra.macs, [&] { launch_wgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, arith, mask); }, ra.bytes);
     const Range& rr = d.s_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
     timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, d.gmax, s, f32); }, rr.bytes);
     const Range& rc = d.s_gemmC.launches[l];
-    timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, f32, mask); }, rc.bytes);
+    timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, arith, mask); }, rc.bytes);
     const Range& rp = d.s_pack.launches[l];
     timed(d, s, PC_OTHER, 0, [&] { launch_pack(static_cast<CopySeg*>(d.s_pack.d) + rp.t0, rp.nt, b, s); });
   }

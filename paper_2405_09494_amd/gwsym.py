@@ -19,7 +19,7 @@ if not os.path.exists(_LIB_PATH):
 lib = C.CDLL(_LIB_PATH)
 
 MODE_FULL, MODE_ROTATE, MODE_BLOCK = 0, 1, 2
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X6, BF16X3 = 0, 1, 2, 3
 KIND_F, KIND_G, KIND_P = 0, 1, 2
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ESINGULAR", -6: "ENOCONV",

@@ -3,7 +3,7 @@ ntau 64) in the launch configuration the benchmark times (block mode, default ta
 half-tau mirror), on outputs the oracle computes one at a time: one P0^q(tau_j) over every
 k (eq. P0) and one Sigma^k(tau_j) over every q (eq. sigma).  The Sigma check feeds a seeded,
 symmetric stand-in for P at one tau (zero elsewhere), so every oracle input comes from the
-generator.  Bars: 1e-10 relative in FP64, 1e-6 with FP32 contractions."""
+generator.  Bars: 1e-10 relative in FP64, 1e-6 with FP32 or three-piece bfloat16 contractions."""
 import numpy as np
 import pytest
 import torch
@@ -89,6 +89,14 @@ def test_cfg1_sampled_fp64(cfg1):
 def test_cfg1_sampled_fp32(cfg1):
     say("[full size] fp32 contractions")
     p0, s = run(cfg1, 1)
+    e0, es = rel(p0, cfg1["ref_p0"]), rel(s, cfg1["ref_s"])
+    say(f"  P0 {e0:.2e} Sigma {es:.2e}")
+    assert e0 < 1e-6 and es < 1e-6
+
+
+def test_cfg1_sampled_bf16x6(cfg1):
+    say("[full size] bf16 x6 contractions")
+    p0, s = run(cfg1, 2)
     e0, es = rel(p0, cfg1["ref_p0"]), rel(s, cfg1["ref_s"])
     say(f"  P0 {e0:.2e} Sigma {es:.2e}")
     assert e0 < 1e-6 and es < 1e-6
