@@ -207,7 +207,10 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip the full-matrix FP64 comparison")
     ap.add_argument("--graph", type=int, default=1, help="1 (default): replay each iteration from a captured HIP graph; 0: eager launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-contraction run of the block path")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the runs of the block path with FP32 and split-bfloat16 contractions")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1 (default): the block paths time candidate launch plans first and keep the fastest")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a plain copy kernel "
                          "of known traffic, to scale hardware byte counters)")
@@ -246,6 +249,12 @@ def main():
     blk = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk), F_all, V_all, torch, dev,
                graph=bool(args.graph))
     log(f"[bench] block path set up in {time.perf_counter() - t:.1f} s; N_target={blk.n_target:.6f}")
+    tuning, tune_s = blk.ctx.get_tuning(), 0.0
+    if args.autotune:
+        t = time.perf_counter()
+        tuning = blk.ctx.autotune()
+        tune_s = time.perf_counter() - t
+        log(f"[bench] autotuned in {tune_s:.1f} s: {tuning}")
     s_blk = time_steps(blk, args.steps, args.warmup, torch)
     log(f"[bench] block: {s_blk:.4f} s/iteration")
     prof = profile_step(blk, torch)
@@ -288,6 +297,7 @@ def main():
            "contraction_tflops": flops_iter / (contr_ms * 1e-3) / 1e12 if contr_ms > 0 else None,
            "algorithmic_flops_per_iteration": flops_iter,
            "profile_ms": {k: v[0] for k, v in prof.items()},
+           "launch_plan": tuning, "autotune_s": tune_s,
            "kernels": kernels,
            "roofline": roof}
 
@@ -318,6 +328,7 @@ def main():
                           ("bf16x3_contractions", gwsym.BF16X3)):
             red = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=prec), F_all, V_all,
                        torch, dev, graph=bool(args.graph))
+            red_tuning = red.ctx.autotune() if args.autotune else red.ctx.get_tuning()
             s_red = time_steps(red, args.steps, args.warmup, torch)
             for pth in (blk, red):   # one iteration from the same G0 in both precisions
                 pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)
@@ -331,11 +342,14 @@ def main():
             nk_, nt_, no_ = blk.ctx.nk, blk.ctx.ntau, blk.ctx.nao
             occ = lambda g: -torch.diagonal(g.view(nk_, nt_, no_, no_)[:, -1], dim1=-2, dim2=-1).real
             occ_err = float((occ(ga) - occ(gb)).abs().max())
+            prof_red = profile_step(red, torch)
             out[key] = {"s_per_iteration": s_red, "speedup_vs_fp64_block": s_blk / s_red,
                         "p0_rel_err_vs_fp64": err_p0, "sigma_rel_err_vs_fp64": err_s,
-                        "occupation_max_abs_err_vs_fp64": occ_err}
+                        "occupation_max_abs_err_vs_fp64": occ_err, "launch_plan": red_tuning,
+                        "profile_ms": {k: v[0] for k, v in prof_red.items()}}
             log(f"[bench] {key}: {s_red:.4f} s/iteration, P0 vs fp64 {err_p0:.2e}, Sigma {err_s:.2e}, "
                 f"occupations {occ_err:.2e}")
+            log(f"[bench] {key} profile: " + ", ".join(f"{k} {v[0]:.1f} ms" for k, v in prof_red.items()))
             del red
 
     if not args.no_cpu:

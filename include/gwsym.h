@@ -221,6 +221,38 @@ int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, cons
 int gwsym_iteration(gwsym_ctx* ctx, const void* F_blk, void* G_blk, void* P0_blk, void* P_blk, void* Sigma_blk,
                     double* mu, double n_target, int use_graph, void* stream);
 
+/* Launch plan of the contractions (eq. P0 and eq. sigma work lists).  Index 0 is the
+ * polarization GEMM, 1 the self-energy auxiliary GEMM (P^T V), 2 the self-energy orbital
+ * GEMM (on the diagonal blocks).  Every choice leaves the results unchanged up to rounding
+ * order. */
+typedef struct {
+  int tau_chunk;      /* tau points per contraction launch (the workspaces hold this many
+                         tau slabs of nk * naux * nao^2 complex numbers each) */
+  int wg_target[3];   /* workgroups a launch aims for: outer sums are split (and the parts
+                         summed in a fixed order) until the tile list reaches this size */
+  int cols[3];        /* output columns per wave tile: 32 or 64 */
+  int xcd_order[3];   /* 1: tiles sharing operand rows queued on one XCD in sequence; 0: plain */
+  int kdepth[3];      /* split-bfloat16 modes: k values per bfloat16 MFMA, 16 or 32; 0 picks
+                         per launch (16 where 32 would pad more than a quarter of the sums) */
+} gwsym_tuning;
+
+/* Autotuner: times candidate launch plans of the polarization and self-energy on this GPU
+ * with the loaded V and keeps the fastest: first the tau chunk (powers of two up to the
+ * half-tau count, within a workspace budget of a quarter of free device memory and 16 GB
+ * per workspace), then per GEMM stage the workgroup target, tile width, XCD order and (in
+ * the split-bfloat16 modes) the k depth, one at a time.  Must follow gwsym_load_V.
+ * Allocates and frees temporary device buffers (zero G and P inputs) and may grow the
+ * workspaces; synchronises `stream`.  *out (host, may be NULL) receives the chosen plan. */
+int gwsym_autotune(gwsym_ctx* ctx, void* stream, gwsym_tuning* out);
+
+/* The plan in use (host struct). */
+int gwsym_get_tuning(const gwsym_ctx* ctx, gwsym_tuning* out);
+
+/* Rebuilds the contraction plans from *t (host) without timing, e.g. a plan cached from an
+ * earlier gwsym_autotune for the same workload and device.  Must follow gwsym_device_init.
+ * GWSYM_EINVAL for out-of-range fields; synchronises `stream`. */
+int gwsym_set_tuning(gwsym_ctx* ctx, const gwsym_tuning* t, void* stream);
+
 /* Algorithm and executed complex multiply-accumulate counts of the last
  * polarization / self_energy call, for throughput accounting (host).
  * out[0] = P0 MACs, out[1] = Sigma MACs (as executed, padding excluded). */
@@ -229,8 +261,8 @@ int gwsym_flop_counts(const gwsym_ctx* ctx, double* out2);
 /* Live timing of the launches the context enqueues, with HIP events recorded on the
  * launch stream around every launch (enable != 0) or not at all (enable = 0, default).
  * Classes: 0 polarization contraction (grouped GEMM), 1 self-energy auxiliary contraction,
- * 2 self-energy orbital contraction, 3 block-diagonal row multiply, 4 block-diagonal column
- * multiply, 5 Matsubara transforms, 6 batched inverses, 7 other. */
+ * 2 self-energy orbital contraction, 3 block-diagonal multiply from the right, 4 two-sided
+ * block-diagonal multiply, 5 Matsubara transforms, 6 batched inverses, 7 other. */
 int gwsym_profile(gwsym_ctx* ctx, int enable);
 
 /* Waits for the recorded events and returns, per class (arrays of 8, host): total

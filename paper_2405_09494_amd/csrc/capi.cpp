@@ -105,6 +105,14 @@ int gwsym_create(const gwsym_params* params, gwsym_ctx** out) {
   gwsym_ctx* ctx = new (std::nothrow) gwsym_ctx();
   if (!ctx) return GWSYM_ENOMEM;
   ctx->c.prm = *params;
+  gwsym_tuning& t = ctx->c.tune;
+  t.tau_chunk = params->tau_chunk;
+  for (int g = 0; g < 3; ++g) {
+    t.wg_target[g] = 8192;
+    t.cols[g] = 32;
+    t.xcd_order[g] = 1;
+    t.kdepth[g] = 0;
+  }
   *out = ctx;
   return GWSYM_OK;
 }
@@ -259,6 +267,35 @@ int gwsym_profile_read(gwsym_ctx* ctx, double* ms, int64_t* launches, double* ma
   NEED(ctx->c.dev, GWSYM_ESTATE, "gwsym_device_init must come first");
   NEED(ms && launches && macs && bytes, GWSYM_EINVAL, "NULL buffer");
   return device_profile_read(ctx->c, ms, launches, macs, bytes);
+}
+
+int gwsym_autotune(gwsym_ctx* ctx, void* stream, gwsym_tuning* out) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");
+  const int st = device_autotune(ctx->c, stream);
+  if (st == GWSYM_OK && out) *out = ctx->c.tune;
+  return st;
+}
+
+int gwsym_get_tuning(const gwsym_ctx* ctx, gwsym_tuning* out) {
+  if (!ctx || !out) return GWSYM_EINVAL;
+  *out = ctx->c.tune;
+  return GWSYM_OK;
+}
+
+int gwsym_set_tuning(gwsym_ctx* ctx, const gwsym_tuning* t, void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(t, GWSYM_EINVAL, "NULL tuning");
+  NEED(ctx->c.dev, GWSYM_ESTATE, "gwsym_device_init must come first");
+  NEED(t->tau_chunk >= 0, GWSYM_EINVAL, "tau_chunk must be >= 0");
+  for (int g = 0; g < 3; ++g) {
+    NEED(t->wg_target[g] >= 256 && t->wg_target[g] <= (1 << 20), GWSYM_EINVAL, "wg_target out of [256, 2^20]");
+    NEED(t->cols[g] == 32 || t->cols[g] == 64, GWSYM_EINVAL, "cols must be 32 or 64");
+    NEED(t->xcd_order[g] == 0 || t->xcd_order[g] == 1, GWSYM_EINVAL, "xcd_order must be 0 or 1");
+    NEED(t->kdepth[g] == 0 || t->kdepth[g] == 16 || t->kdepth[g] == 32, GWSYM_EINVAL, "kdepth must be 0, 16 or 32");
+  }
+  ctx->c.tune = *t;
+  return device_replan(ctx->c, stream);
 }
 
 int gwsym_flop_counts(const gwsym_ctx* ctx, double* out2) {

@@ -108,6 +108,7 @@ enum Buf : int {
 
 struct Ctx {
   gwsym_params prm{};
+  gwsym_tuning tune{};                     // contraction launch plan (device_init, autotune)
   std::string err;
   bool built = false, dev = false, vloaded = false;
 
@@ -171,6 +172,8 @@ int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G
 int device_iteration(Ctx& c, const void* F, void* G, void* P0, void* P, void* S, double* mu, double ntarget,
                      int use_graph, void* stream);
 int device_profile(Ctx& c, int enable);
+int device_replan(Ctx& c, void* stream);
+int device_autotune(Ctx& c, void* stream);
 int device_profile_read(Ctx& c, double* ms, int64_t* launches, double* macs, double* bytes);
 
 }  // namespace gw

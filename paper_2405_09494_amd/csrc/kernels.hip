@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernel_api.hpp"
 
@@ -390,31 +391,41 @@ void launch_reduce_tag(const GemmPlanDev& p, const Bases& b, void* partials, hip
 // indices add to at most 2; 3 splits into two pieces and sums three products.  Both accumulate
 // in FP32 on the 16 x 16 x 32 bfloat16 MFMA.  A group of eight sub-steps feeds one such MFMA:
 // lane l passes its eight values of the group as its eight k slots, for A and B alike, so
-// the slot-to-k assignment is the same on both sides and the sum over k is unchanged.
+// the slot-to-k assignment is the same on both sides and the sum over k is unchanged.  Where
+// the sub-step sequences are short (a small K and one outer index), groups of four on the
+// 16 x 16 x 16 bfloat16 MFMA waste less on padding (AR 4 and 5, the same splits).
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
 
 template <int AR> struct WArith;
 template <> struct WArith<0> { using R = double; static constexpr int GS = 2, NS = 0; };
 template <> struct WArith<1> { using R = float; static constexpr int GS = 2, NS = 0; };
 template <> struct WArith<2> { using R = float; static constexpr int GS = 8, NS = 3; };
 template <> struct WArith<3> { using R = float; static constexpr int GS = 8, NS = 2; };
+template <> struct WArith<4> { using R = float; static constexpr int GS = 4, NS = 3; };
+template <> struct WArith<5> { using R = float; static constexpr int GS = 4, NS = 2; };
+template <int GS> struct BfV;
+template <> struct BfV<8> { using T = bf8; };
+template <> struct BfV<4> { using T = bf4; };
 
 // x = p[0] + p[1] + ... + rest: each piece is the bfloat16 nearest to what the pieces before
 // it leave over
-template <int NS>
-__device__ __forceinline__ void bf_split(const float (&x)[8], bf8 (&p)[NS]) {
-  float r[8];
+template <int NS, int GS, typename V>
+__device__ __forceinline__ void bf_split(const float (&x)[GS], V (&p)[NS]) {
+  float r[GS];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r[i] = x[i];
+  for (int i = 0; i < GS; ++i) r[i] = x[i];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) p[s][i] = __bf16(r[i]);
+    for (int i = 0; i < GS; ++i) p[s][i] = __bf16(r[i]);
     if (s + 1 < NS) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) r[i] -= float(p[s][i]);
+      for (int i = 0; i < GS; ++i) r[i] -= float(p[s][i]);
     }
   }
 }
@@ -423,14 +434,22 @@ __device__ __forceinline__ bf8 bf_neg(bf8 v) {
   u ^= 0x80008000u;
   return __builtin_bit_cast(bf8, u);
 }
+__device__ __forceinline__ bf4 bf_neg(bf4 v) {
+  u2 u = __builtin_bit_cast(u2, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf4, u);
+}
 __device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma_bf(bf4 a, bf4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0, 0);
+}
 // c_re += a b_re-part sums and c_im likewise for one 16 x 16 quarter pair, from the pieces of
 // a = ar + i ai (with an = -ai) and b = br + i bi; the smaller piece products go first
-template <int NS>
-__device__ __forceinline__ void bf_cmac(const bf8 (&ar)[NS], const bf8 (&ai)[NS], const bf8 (&an)[NS],
-                                        const bf8 (&br)[NS], const bf8 (&bi)[NS], f4& cr, f4& ci) {
+template <int NS, typename V>
+__device__ __forceinline__ void bf_cmac(const V (&ar)[NS], const V (&ai)[NS], const V (&an)[NS],
+                                        const V (&br)[NS], const V (&bi)[NS], f4& cr, f4& ci) {
 #pragma unroll
   for (int d = NS - 1; d >= 0; --d)
 #pragma unroll
@@ -479,6 +498,39 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   const int nchunk = N2 ? (tl.nn >> 1) : 1;
   const int nsub = (tl.t1 - tl.t0) * nk4, ngrp = (nsub + GS - 1) / GS, total = ngrp * nchunk;
   A4 c00r = {0, 0, 0, 0}, c00i = c00r, c01r = c00r, c01i = c00r, c10r = c00r, c10i = c00r, c11r = c00r, c11i = c00r;
+  // FP32 forms: the FP32 accumulators are added into FP64 sums every 256 k values of the
+  // sequence, so the rounding of a tile's sum does not grow with the length of its outer range
+  constexpr bool F32 = !std::is_same<R, double>::value;
+  constexpr int FLUSH = 256 / (4 * GS);   // groups per FP32 partial sum
+  d4 s00r = {0, 0, 0, 0}, s00i = s00r, s01r = s00r, s01i = s00r, s10r = s00r, s10i = s00r, s11r = s00r, s11i = s00r;
+  int since = 0;
+  auto flush = [&]() __attribute__((always_inline)) {
+    if constexpr (F32) {
+      const A4 z = {0, 0, 0, 0};
+      s00r += __builtin_convertvector(c00r, d4);
+      s00i += __builtin_convertvector(c00i, d4);
+      c00r = z;
+      c00i = z;
+      if (N2) {
+        s01r += __builtin_convertvector(c01r, d4);
+        s01i += __builtin_convertvector(c01i, d4);
+        c01r = z;
+        c01i = z;
+      }
+      if (M2) {
+        s10r += __builtin_convertvector(c10r, d4);
+        s10i += __builtin_convertvector(c10i, d4);
+        c10r = z;
+        c10i = z;
+      }
+      if (M2 && N2) {
+        s11r += __builtin_convertvector(c11r, d4);
+        s11i += __builtin_convertvector(c11i, d4);
+        c11r = z;
+        c11i = z;
+      }
+    }
+  };
   // fetch position: chunk, outer index t and k step j of the next sub-step; the mask zeroes
   // k >= K and the sub-steps past the end of a chunk's sequence
   int fc = 0, ft = tl.t0, fj = 0, fs = 0;
@@ -527,17 +579,17 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       const int gr = m0 + qm * 16 + mrow(R(0), lane, j), rb = gr / P.rdiv;
       roffs[qm][j] = cbase + rb * P.sCrb + int64_t(gr - rb * P.rdiv) * P.ldc;
     }
-  auto store = [&](int cn0, int qm, int qn, const A4& cr, const A4& ci) {
+  auto store = [&](int cn0, int qm, int qn, const d4& cr, const d4& ci) {
     const int gc = cn0 + qn * 16 + li, cb = gc / P.cdiv;
     const int64_t coff = cb * P.sCcb + (gc - cb * P.cdiv);
     for (int j = 0; j < 4; ++j) {
       const int row = qm * 16 + mrow(R(0), lane, j), col = qn * 16 + li;
       if (tl.slot >= 0) {
-        partials[int64_t(tl.slot) * TM * TN + row * TN + col] = make_double2(double(cr[j]), double(ci[j]));
+        partials[int64_t(tl.slot) * TM * TN + row * TN + col] = make_double2(cr[j], ci[j]);
         continue;
       }
       if (m0 + row >= P.M || gc >= P.N) continue;
-      double2 v = cmul(al, make_double2(double(cr[j]), double(ci[j])));
+      double2 v = cmul(al, make_double2(cr[j], ci[j]));
       const int64_t at = roffs[qm][j] + coff;
       if (cf32) {
         float2* C = reinterpret_cast<float2*>(bases.p[P.cbuf]);
@@ -601,10 +653,11 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       }
     } else {
       // pieces of the B quarters (mask and conjugation applied first), then of each A quarter
-      bf8 br[2][NS], bi[2][NS];
+      using BV = typename BfV<GS>::T;
+      BV br[2][NS], bi[2][NS];
 #pragma unroll
       for (int q = 0; q < (N2 ? 2 : 1); ++q) {
-        float xr[8], xi[8];
+        float xr[GS], xi[GS];
 #pragma unroll
         for (int h = 0; h < GS; ++h) {
           xr[h] = b[h][q].x * m[h];
@@ -615,13 +668,13 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       }
 #pragma unroll
       for (int q = 0; q < (M2 ? 2 : 1); ++q) {
-        float xr[8], xi[8];
+        float xr[GS], xi[GS];
 #pragma unroll
         for (int h = 0; h < GS; ++h) {
           xr[h] = a[h][q].x;
           xi[h] = a[h][q].y * sA;
         }
-        bf8 ar[NS], ai[NS], an[NS];
+        BV ar[NS], ai[NS], an[NS];
         bf_split<NS>(xr, ar);
         bf_split<NS>(xi, ai);
 #pragma unroll
@@ -635,21 +688,42 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
         }
       }
     }
+    if (F32 && ++since == FLUSH) {
+      flush();
+      since = 0;
+    }
     if (++cp == ngrp) {
       // end of a chunk: store it and start the next from zero
       const int cn0 = n0 + 32 * cc;
-      store(cn0, 0, 0, c00r, c00i);
-      if (N2) store(cn0, 0, 1, c01r, c01i);
-      if (M2) store(cn0, 1, 0, c10r, c10i);
-      if (M2 && N2) store(cn0, 1, 1, c11r, c11i);
-      c00r = A4{0, 0, 0, 0};
-      c00i = c00r;
-      c01r = c00r;
-      c01i = c00r;
-      c10r = c00r;
-      c10i = c00r;
-      c11r = c00r;
-      c11i = c00r;
+      if constexpr (F32) {
+        flush();
+        since = 0;
+        store(cn0, 0, 0, s00r, s00i);
+        if (N2) store(cn0, 0, 1, s01r, s01i);
+        if (M2) store(cn0, 1, 0, s10r, s10i);
+        if (M2 && N2) store(cn0, 1, 1, s11r, s11i);
+        s00r = d4{0, 0, 0, 0};
+        s00i = s00r;
+        s01r = s00r;
+        s01i = s00r;
+        s10r = s00r;
+        s10i = s00r;
+        s11r = s00r;
+        s11i = s00r;
+      } else {
+        store(cn0, 0, 0, c00r, c00i);
+        if (N2) store(cn0, 0, 1, c01r, c01i);
+        if (M2) store(cn0, 1, 0, c10r, c10i);
+        if (M2 && N2) store(cn0, 1, 1, c11r, c11i);
+        c00r = A4{0, 0, 0, 0};
+        c00i = c00r;
+        c01r = c00r;
+        c01i = c00r;
+        c10r = c00r;
+        c10i = c00r;
+        c11r = c00r;
+        c11i = c00r;
+      }
       cp = 0;
       ++cc;
     }
@@ -691,10 +765,11 @@ void launch_wgemm_t(const GemmPlanDev& p, const Bases& b, void* partials, hipStr
 void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, int arith,
                   unsigned f32mask) {
   if (p.ntiles > 0) {
+    const bool k16 = p.kdepth == 16;
     switch (arith) {
       case 1: launch_wgemm_t<1>(p, b, partials, s, tag, f32mask); break;
-      case 2: launch_wgemm_t<2>(p, b, partials, s, tag, f32mask); break;
-      case 3: launch_wgemm_t<3>(p, b, partials, s, tag, f32mask); break;
+      case 2: k16 ? launch_wgemm_t<4>(p, b, partials, s, tag, f32mask) : launch_wgemm_t<2>(p, b, partials, s, tag, f32mask); break;
+      case 3: k16 ? launch_wgemm_t<5>(p, b, partials, s, tag, f32mask) : launch_wgemm_t<3>(p, b, partials, s, tag, f32mask); break;
       default: launch_wgemm_t<0>(p, b, partials, s, tag, f32mask); break;
     }
   }

@@ -21,6 +21,7 @@ struct Range {
   double macs = 0;   // complex multiply-accumulates requested by the launch
   double bytes = 0;  // algorithmic bytes moved (memory-bound launches)
   int shape[4] = {0, 0, 0, 0};   // wave-tile launches: tiles per shape class, in list order
+  int kdepth = 32;               // k values per bfloat16 MFMA in the split-bfloat16 forms
 };
 
 // Workgroup p of a launch runs on XCD p % 8, and each XCD has its own L2.  Tiles that read
@@ -111,9 +112,13 @@ struct GemmStage {
   void xcd_order(int t0) { xcd_order_tiles(tiles, t0, probs); }
   // Closes a launch: turns its problems into tiles; problems with a long outer loop are
   // split so that the launch has about `target` workgroups.
-  bool wave = false;   // tiles for the wave-tile kernel: one 32-column chunk each, more of them
-  void close(int target = 2048) {
-    if (wave) target = 8192;
+  bool wave = false;   // tiles for the wave-tile kernel: 32-column chunks, more of them
+  // wave-tile plan: workgroups a launch aims for, 32-column chunks per tile, XCD order,
+  // bfloat16 k depth (0: per launch)
+  int target = 8192, per = 1, kdepth = 0;
+  bool xcd = true;
+  void close() {
+    const int target = wave ? this->target : 2048;
     Range r;
     r.t0 = int(tiles.size());
     r.r0 = int(reds.size());
@@ -143,7 +148,7 @@ struct GemmStage {
             if (wave) {
               // one full 32-column chunk per wave (a wave can walk several: nn = 2 x chunks),
               // a last 16-column unit on its own
-              const int full = nu / 2, per = 1;
+              const int full = nu / 2;
               for (int j = 0; j < full; j += per)
                 tiles.push_back({id, b, i, 2 * j, 0, p.T, -1, mh, 2 * std::min(per, full - j), 0});
               if (nu % 2) tiles.push_back({id, b, i, 2 * full, 0, p.T, -1, mh, 1, 0});
@@ -173,7 +178,7 @@ struct GemmStage {
         const int c0 = int(tiles.size());
         for (const GemmTile& t : all)
           if ((t.mh == 2) * 2 + (t.nn >= 2) == sh) tiles.push_back(t);
-        xcd_order(c0);
+        if (xcd) xcd_order(c0);
         r.shape[sh] = int(tiles.size()) - c0;
       }
     } else {
@@ -181,6 +186,18 @@ struct GemmStage {
     }
     r.nt = int(tiles.size()) - r.t0;
     r.nr = int(reds.size()) - r.r0;
+    // k depth of the bfloat16 MFMA: a tile walks ceil(K/4) sub-steps per outer index in groups
+    // of 8 (32-deep) or 4 (16-deep), the last group padded; 16-deep where 32 would pad more
+    // than a quarter of the work
+    double sub = 0, pad8 = 0;
+    for (int t = r.t0; t < r.t0 + r.nt; ++t) {
+      const GemmTile& tl = tiles[t];
+      if (tl.prob < 0) continue;
+      const double n = double(tl.t1 - tl.t0) * ((probs[tl.prob].K + 3) / 4);
+      sub += n;
+      pad8 += 8.0 * std::ceil(n / 8.0);
+    }
+    r.kdepth = kdepth ? kdepth : pad8 > 1.25 * sub ? 16 : 32;
     max_slots = std::max(max_slots, slots);
     launches.push_back(r);
     pending.clear();
@@ -265,6 +282,9 @@ struct DevState {
   void* W1 = nullptr;
   void* W2 = nullptr;
   size_t ws_elems = 0;
+  size_t ws_min = 0;        // workspace elements the non-contraction stages need
+  size_t scr_tau = 0;       // tau slabs SCR holds
+  bool ws_exact = false;    // the next plan sizes the workspaces exactly (also shrinks them)
   void* partials = nullptr;
   size_t nslots = 0, partial_cap = 0;
   double* scratch = nullptr;  // mu state (3), eps range (2), internal n_free (1)
@@ -339,6 +359,7 @@ GemmPlanDev plan_of(const GemmStage& g, const Range& r) {
   p.ntiles = r.nt;
   p.nreds = r.nr;
   for (int i = 0; i < 4; ++i) p.shape[i] = r.shape[i];
+  p.kdepth = r.kdepth;
   return p;
 }
 
@@ -371,71 +392,63 @@ i64 U_off(const Ctx& c, bool aux, int k) {
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-// device_init: tables, workspaces and the work lists that do not depend on V.
+// The contraction work lists (eq. P0 / Alg. 3 and eq. sigma / Alg. 4) for the plan in
+// c.tune: tau chunk, and per GEMM stage the workgroup target, tile width, XCD order and
+// bfloat16 k depth.  Replaces the previous lists (their device copies are freed), grows the
+// workspaces to the chunk and drops a captured iteration graph.
 
-int device_init(Ctx& c, void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  DevState* dp = new DevState();
-  c.dev_state = dp;
-  DevState& d = *dp;
-  const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nw = c.nw, nib = c.nibz;
-  d.p0_gemm.wave = d.s_gemmA.wave = d.s_gemmC.wave = true;
-  for (int i = 0; i < nib; ++i) d.gmax = std::max<int>(d.gmax, int(c.bao[i].packed));
+namespace {
+
+void dfree(DevState& d, void*& p) {
+  if (!p) return;
+  hipFree(p);
+  auto it = std::find(d.allocs.begin(), d.allocs.end(), p);
+  if (it != d.allocs.end()) d.allocs.erase(it);
+  p = nullptr;
+}
+
+void reset_gemm(DevState& d, GemmStage& g) {
+  dfree(d, g.d_probs);
+  dfree(d, g.d_tiles);
+  dfree(d, g.d_reds);
+  g = GemmStage{};
+  g.wave = true;
+}
+
+}  // namespace
+
+int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
+  const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nib = c.nibz;
   int st;
-  // U tables
-  {
-    std::vector<cplx> u;
-    u.reserve(size_t(nk) * (no * no + na * na));
-    for (int k = 0; k < nk; ++k) u.insert(u.end(), c.U_ao[k].a.begin(), c.U_ao[k].a.end());
-    for (int k = 0; k < nk; ++k) u.insert(u.end(), c.U_aux[k].a.begin(), c.U_aux[k].a.end());
-    if ((st = upload(c, d, u, &d.U, s))) return st;
+  // the lists and workspaces being replaced may still be read by queued work on any stream
+  if (d.p0_gemm.d_tiles) HIPCHECK(hipDeviceSynchronize());
+  reset_gemm(d, d.p0_gemm);
+  reset_gemm(d, d.s_gemmA);
+  reset_gemm(d, d.s_gemmC);
+  GemmStage* gs[3] = {&d.p0_gemm, &d.s_gemmA, &d.s_gemmC};
+  for (int g = 0; g < 3; ++g) {
+    gs[g]->target = c.tune.wg_target[g];
+    gs[g]->per = c.tune.cols[g] / 32;
+    gs[g]->xcd = c.tune.xcd_order[g] != 0;
+    gs[g]->kdepth = c.tune.kdepth[g];
   }
-  {
-    std::vector<cplx> tr;
-    tr.insert(tr.end(), c.Tf.begin(), c.Tf.end());
-    tr.insert(tr.end(), c.Tb.begin(), c.Tb.end());
-    tr.insert(tr.end(), c.Bf.begin(), c.Bf.end());
-    tr.insert(tr.end(), c.Bb.begin(), c.Bb.end());
-    if ((st = upload(c, d, tr, &d.TR, s))) return st;
-    void* t;
-    if ((st = upload(c, d, c.tau, &t, s))) return st;
-    d.tau = static_cast<double*>(t);
+  for (RowStage* r : {&d.p0_both, &d.s_right}) {
+    dfree(d, r->d);
+    *r = RowStage{};
   }
-  const i64 TF = 0, TB = i64(nw) * nt, BF = 2 * i64(nw) * nt, BB = 3 * i64(nw) * nt;
-  // block tables: count, then (off, size, poff) per block
-  {
-    std::vector<int> bt;
-    for (int i = 0; i < nib; ++i) {
-      d.bt_ao.push_back(int(bt.size()));
-      const Blocks& B = c.bao[i];
-      bt.push_back(int(B.size.size()));
-      for (size_t r = 0; r < B.size.size(); ++r) {
-        bt.push_back(B.off[r]);
-        bt.push_back(B.size[r]);
-        bt.push_back(int(B.poff[r]));
-      }
-    }
-    for (int i = 0; i < nib; ++i) {
-      d.bt_aux.push_back(int(bt.size()));
-      const Blocks& B = c.baux[i];
-      bt.push_back(int(B.size.size()));
-      for (size_t r = 0; r < B.size.size(); ++r) {
-        bt.push_back(B.off[r]);
-        bt.push_back(B.size[r]);
-        bt.push_back(int(B.poff[r]));
-      }
-    }
-    void* t;
-    if ((st = upload(c, d, bt, &t, s))) return st;
-    d.btab = static_cast<int*>(t);
+  for (auto* l : {&d.p0_mirror, &d.s_pack}) {
+    dfree(d, l->d);
+    *l = ListStage<CopySeg>{};
   }
-  // star weights
-  std::vector<int> star(nib, 0);
-  for (int k = 0; k < nk; ++k) star[c.rep[k]]++;
+  if (d.graph_exec) {
+    hipGraphExecDestroy(d.graph_exec);
+    d.graph_exec = nullptr;
+    d.graph_key.clear();
+  }
 
   // tau chunk: contraction workspaces hold J * nk * naux * nao^2 complex numbers each
   const i64 slab = i64(nk) * na * no * no;
-  int J = c.prm.tau_chunk;
+  int J = c.tune.tau_chunk;
   if (J <= 0) {
     const double budget = 2.0e9 / 16.0;  // elements per workspace
     J = int(std::max(1.0, std::min(double(nt), budget / double(slab))));
@@ -443,24 +456,21 @@ int device_init(Ctx& c, void* stream) {
   J = std::min(J, nt);
   if (c.prm.half_tau && nt >= 2) J = std::max(J, 2);   // a tau and its mirror share a chunk
   d.tau_chunk = J;
+  c.tune.tau_chunk = J;
   const int nthalf = c.prm.half_tau ? (nt + 1) / 2 : nt;
-
-  // frequency and readout sizes
-  i64 pw = 0, gw = 0;
-  std::vector<i64> pw_off(nib + 1, 0), gw_off(nib + 1, 0);
-  for (int i = 0; i < nib; ++i) {
-    pw_off[i + 1] = pw_off[i] + i64(nw) * c.baux[i].packed;
-    gw_off[i + 1] = gw_off[i] + i64(nw) * c.bao[i].packed;
+  const size_t ws = std::max(d.ws_min, size_t(J) * size_t(slab));
+  if (ws > d.ws_elems || (d.ws_exact && ws < d.ws_elems)) {
+    dfree(d, d.W1);
+    dfree(d, d.W2);
+    d.ws_elems = ws;
+    if ((st = dalloc(c, d, &d.W1, d.ws_elems * 16))) return st;
+    if ((st = dalloc(c, d, &d.W2, d.ws_elems * 16))) return st;
   }
-  pw = pw_off[nib];
-  gw = gw_off[nib];
-  i64 ws = std::max<i64>(i64(J) * slab, std::max(pw, gw));
-  ws = std::max<i64>(ws, i64(nk) * nt * std::max(no * no, na * na));   // from_block of P over every k
-  ws = std::max<i64>(ws, c.p_off[nib] + c.g_off[nib]);
-  d.ws_elems = size_t(ws);
-  if ((st = dalloc(c, d, &d.W1, d.ws_elems * 16))) return st;
-  if ((st = dalloc(c, d, &d.W2, d.ws_elems * 16))) return st;
-  if ((st = dalloc(c, d, &d.SCR, size_t(J) * no * no * 16))) return st;
+  if (size_t(J) > d.scr_tau || (d.ws_exact && size_t(J) < d.scr_tau)) {
+    dfree(d, d.SCR);
+    d.scr_tau = size_t(J);
+    if ((st = dalloc(c, d, &d.SCR, size_t(J) * no * no * 16))) return st;
+  }
 
   // ---------------- polarization (eq. P0, Alg. 3) ----------------
   Mesh mesh{c.n};
@@ -468,10 +478,6 @@ int device_init(Ctx& c, void* stream) {
   for (int i = 0; i < nib; ++i)
     for (int sz : c.bao[i].size) sumsq_ao[i] += double(sz) * sz;
   const double pscale = -c.prm.spin / nk;
-  if (no > 64) {   // the block multiplies give each orbital column one lane
-    c.err = "orbital basis larger than 64 functions";
-    return GWSYM_ESHAPE;
-  }
   // P0^q(tau_j)[Q, Q'] = -(s/Nk) sum_k sum_(a,b) Vp(Q)_ab conj(W(Q')_ab) with
   // W(Q') = G^k(beta - tau_j)^H Vp(Q') G^(k+q)(tau_j)^H, which equals the trace of eq. P0;
   // W comes from one pass of the both-sided block multiply, then a plain grouped GEMM.
@@ -636,6 +642,95 @@ int device_init(Ctx& c, void* stream) {
     }
   }
 
+  for (GemmStage* g : gs)
+    if ((st = upload_stage(c, d, *g, s))) return st;
+  for (RowStage* r : {&d.p0_both, &d.s_right})
+    if ((st = upload(c, d, r->segs, &r->d, s))) return st;
+  for (auto* l : {&d.p0_mirror, &d.s_pack})
+    if ((st = upload(c, d, l->items, &l->d, s))) return st;
+  HIPCHECK(hipStreamSynchronize(s));
+  return GWSYM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// device_init: tables, workspaces and the work lists that do not depend on V.
+
+int device_init(Ctx& c, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState* dp = new DevState();
+  c.dev_state = dp;
+  DevState& d = *dp;
+  const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nw = c.nw, nib = c.nibz;
+  d.p0_gemm.wave = d.s_gemmA.wave = d.s_gemmC.wave = true;
+  for (int i = 0; i < nib; ++i) d.gmax = std::max<int>(d.gmax, int(c.bao[i].packed));
+  int st;
+  // U tables
+  {
+    std::vector<cplx> u;
+    u.reserve(size_t(nk) * (no * no + na * na));
+    for (int k = 0; k < nk; ++k) u.insert(u.end(), c.U_ao[k].a.begin(), c.U_ao[k].a.end());
+    for (int k = 0; k < nk; ++k) u.insert(u.end(), c.U_aux[k].a.begin(), c.U_aux[k].a.end());
+    if ((st = upload(c, d, u, &d.U, s))) return st;
+  }
+  {
+    std::vector<cplx> tr;
+    tr.insert(tr.end(), c.Tf.begin(), c.Tf.end());
+    tr.insert(tr.end(), c.Tb.begin(), c.Tb.end());
+    tr.insert(tr.end(), c.Bf.begin(), c.Bf.end());
+    tr.insert(tr.end(), c.Bb.begin(), c.Bb.end());
+    if ((st = upload(c, d, tr, &d.TR, s))) return st;
+    void* t;
+    if ((st = upload(c, d, c.tau, &t, s))) return st;
+    d.tau = static_cast<double*>(t);
+  }
+  const i64 TF = 0, TB = i64(nw) * nt, BF = 2 * i64(nw) * nt, BB = 3 * i64(nw) * nt;
+  // block tables: count, then (off, size, poff) per block
+  {
+    std::vector<int> bt;
+    for (int i = 0; i < nib; ++i) {
+      d.bt_ao.push_back(int(bt.size()));
+      const Blocks& B = c.bao[i];
+      bt.push_back(int(B.size.size()));
+      for (size_t r = 0; r < B.size.size(); ++r) {
+        bt.push_back(B.off[r]);
+        bt.push_back(B.size[r]);
+        bt.push_back(int(B.poff[r]));
+      }
+    }
+    for (int i = 0; i < nib; ++i) {
+      d.bt_aux.push_back(int(bt.size()));
+      const Blocks& B = c.baux[i];
+      bt.push_back(int(B.size.size()));
+      for (size_t r = 0; r < B.size.size(); ++r) {
+        bt.push_back(B.off[r]);
+        bt.push_back(B.size[r]);
+        bt.push_back(int(B.poff[r]));
+      }
+    }
+    void* t;
+    if ((st = upload(c, d, bt, &t, s))) return st;
+    d.btab = static_cast<int*>(t);
+  }
+  // star weights
+  std::vector<int> star(nib, 0);
+  for (int k = 0; k < nk; ++k) star[c.rep[k]]++;
+
+  // frequency and readout sizes; the contraction plan adds its tau slabs to the workspaces
+  std::vector<i64> pw_off(nib + 1, 0), gw_off(nib + 1, 0);
+  for (int i = 0; i < nib; ++i) {
+    pw_off[i + 1] = pw_off[i] + i64(nw) * c.baux[i].packed;
+    gw_off[i + 1] = gw_off[i] + i64(nw) * c.bao[i].packed;
+  }
+  i64 ws = std::max(pw_off[nib], gw_off[nib]);
+  ws = std::max<i64>(ws, i64(nk) * nt * std::max(no * no, na * na));   // from_block of P over every k
+  ws = std::max<i64>(ws, c.p_off[nib] + c.g_off[nib]);
+  d.ws_min = size_t(ws);
+  if (no > 64) {   // the block multiplies give each orbital column one lane
+    c.err = "orbital basis larger than 64 functions";
+    return GWSYM_ESHAPE;
+  }
+  if ((st = plan_contractions(c, d, s))) return st;
+
   // ---------------- screened interaction (eq. P02P) ----------------
   for (int i = 0; i < nib; ++i) {
     const Blocks& B = c.baux[i];
@@ -736,14 +831,12 @@ int device_init(Ctx& c, void* stream) {
     d.fb_2[kind].close();
   }
 
-  for (GemmStage* g : {&d.p0_gemm, &d.s_gemmA, &d.s_gemmC, &d.scr_fwd, &d.scr_bwd, &d.dys_fwd, &d.dys_bwd})
+  for (GemmStage* g : {&d.scr_fwd, &d.scr_bwd, &d.dys_fwd, &d.dys_bwd})
     if ((st = upload_stage(c, d, *g, s))) return st;
   for (int kind = 0; kind < 3; ++kind)
     for (GemmStage* g : {&d.tb_1[kind], &d.tb_2[kind], &d.fb_1[kind], &d.fb_2[kind]})
       if ((st = upload_stage(c, d, *g, s))) return st;
-  for (RowStage* r : {&d.p0_both, &d.s_right})
-    if ((st = upload(c, d, r->segs, &r->d, s))) return st;
-  for (auto* l : {&d.p0_mirror, &d.scr_herm, &d.dys_herm, &d.s_pack})
+  for (auto* l : {&d.scr_herm, &d.dys_herm})
     if ((st = upload(c, d, l->items, &l->d, s))) return st;
   for (auto* l : {&d.scr_inv, &d.dys_inv, &d.mu_inv})
     if ((st = upload(c, d, l->items, &l->d, s))) return st;
@@ -1232,6 +1325,134 @@ int device_profile_read(Ctx& c, double* ms, int64_t* launches, double* macs, dou
   p.recs.clear();
   p.used = 0;
   return GWSYM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Contraction plans: rebuild from c.tune, or choose c.tune by timing candidates.
+
+int device_replan(Ctx& c, void* stream) {
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  d.ws_exact = true;
+  const int st = plan_contractions(c, d, static_cast<hipStream_t>(stream));
+  d.ws_exact = false;
+  return st;
+}
+
+namespace {
+
+// device buffers and events that live for one autotune call
+struct TuneScratch {
+  std::vector<void*> bufs;
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~TuneScratch() {
+    for (void* p : bufs) hipFree(p);
+    for (hipEvent_t x : e)
+      if (x) hipEventDestroy(x);
+  }
+};
+
+}  // namespace
+
+int device_autotune(Ctx& c, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nib = c.nibz;
+  int st;
+  TuneScratch ts;
+  // zero G and P inputs: the launch sequence and the operand traffic do not depend on values
+  void* buf[4];
+  const size_t gbytes = size_t(c.g_off[nib]) * 16 + 16, pbytes = size_t(c.p_off[nib]) * 16 + 16;
+  const size_t sizes[4] = {gbytes, pbytes, pbytes, gbytes};   // G, P, P0, Sigma
+  for (int b = 0; b < 4; ++b) {
+    HIPCHECK(hipMalloc(&buf[b], sizes[b]));
+    ts.bufs.push_back(buf[b]);
+    HIPCHECK(hipMemsetAsync(buf[b], 0, sizes[b], s));
+  }
+  HIPCHECK(hipEventCreate(&ts.e[0]));
+  HIPCHECK(hipEventCreate(&ts.e[1]));
+  const bool prof_on = d.prof.on;
+  d.prof.on = false;
+  // which: 1 polarization, 2 self-energy, 3 both; best of two runs after one warm-up run
+  auto time_calls = [&](int which, float& best) -> int {
+    best = 3.4e38f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHECK(hipEventRecord(ts.e[0], s));
+      if ((which & 1) && (st = device_polarization(c, buf[0], buf[2], s))) return st;
+      if ((which & 2) && (st = device_self_energy(c, buf[0], buf[1], buf[3], s))) return st;
+      HIPCHECK(hipEventRecord(ts.e[1], s));
+      HIPCHECK(hipEventSynchronize(ts.e[1]));
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, ts.e[0], ts.e[1]));
+      if (rep > 0) best = std::min(best, ms);
+    }
+    return GWSYM_OK;
+  };
+  gwsym_tuning best = c.tune;
+  float best_ms = 3.4e38f;
+  auto trial = [&](const gwsym_tuning& t, int which) -> int {
+    c.tune = t;
+    float ms;
+    if ((st = plan_contractions(c, d, s)) || (st = time_calls(which, ms))) {
+      d.prof.on = prof_on;
+      return st;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c.tune;   // with the tau chunk the plan actually used
+    }
+    return GWSYM_OK;
+  };
+  // 1. tau chunk: powers of two up to the tau count of one contraction pass, within the
+  //    workspace budget (the current workspaces count as free)
+  size_t freeb = 0, totalb = 0;
+  HIPCHECK(hipMemGetInfo(&freeb, &totalb));
+  const double slab_bytes = 16.0 * nk * na * double(no) * no;
+  const double cap = std::min(16.0e9, 0.25 * (double(freeb) + 32.0 * double(d.ws_elems)));
+  const int nthalf = c.prm.half_tau ? (nt + 1) / 2 : nt;
+  const int J0 = d.tau_chunk, Jmin = c.prm.half_tau ? 2 : 1;
+  std::vector<int> js;
+  for (int J = Jmin; J < nthalf; J *= 2) js.push_back(J);
+  js.push_back(nthalf);
+  js.push_back(J0);
+  std::sort(js.begin(), js.end());
+  js.erase(std::unique(js.begin(), js.end()), js.end());
+  for (int J : js) {
+    if (J != J0 && J > Jmin && J * slab_bytes > cap) continue;
+    gwsym_tuning t = best;
+    t.tau_chunk = J;
+    if ((st = trial(t, 3))) return st;
+  }
+  // 2. per GEMM stage, one knob at a time, timed on the call that contains the stage
+  const bool bf = c.prm.precision == GWSYM_BF16X6 || c.prm.precision == GWSYM_BF16X3;
+  for (int g = 0; g < 3; ++g) {
+    const int which = g == 0 ? 1 : 2;
+    best_ms = 3.4e38f;
+    if ((st = trial(best, which))) return st;
+    for (int v : {2048, 4096, 16384, 32768}) {
+      gwsym_tuning t = best;
+      t.wg_target[g] = v;
+      if ((st = trial(t, which))) return st;
+    }
+    {
+      gwsym_tuning t = best;
+      t.cols[g] = t.cols[g] == 32 ? 64 : 32;
+      if ((st = trial(t, which))) return st;
+    }
+    {
+      gwsym_tuning t = best;
+      t.xcd_order[g] ^= 1;
+      if ((st = trial(t, which))) return st;
+    }
+    if (bf)
+      for (int v : {16, 32}) {
+        gwsym_tuning t = best;
+        t.kdepth[g] = v;
+        if ((st = trial(t, which))) return st;
+      }
+  }
+  d.prof.on = prof_on;
+  c.tune = best;
+  return device_replan(c, stream);
 }
 
 }  // namespace gw

@@ -39,6 +39,23 @@ class Crystal(C.Structure):
                 ("aux_l", C.POINTER(C.c_int))]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("tau_chunk", C.c_int), ("wg_target", C.c_int * 3), ("cols", C.c_int * 3),
+                ("xcd_order", C.c_int * 3), ("kdepth", C.c_int * 3)]
+
+    def to_dict(self):
+        return {"tau_chunk": int(self.tau_chunk), "wg_target": list(self.wg_target), "cols": list(self.cols),
+                "xcd_order": list(self.xcd_order), "kdepth": list(self.kdepth)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        t.tau_chunk = int(d["tau_chunk"])
+        for f in ("wg_target", "cols", "xcd_order", "kdepth"):
+            getattr(t, f)[:] = [int(x) for x in d[f]]
+        return t
+
+
 _vp = C.c_void_p
 lib.gwsym_create.argtypes = [C.POINTER(Params), C.POINTER(_vp)]
 lib.gwsym_destroy.argtypes = [_vp]
@@ -60,6 +77,9 @@ lib.gwsym_self_energy.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.gwsym_find_mu.argtypes = [_vp, _vp, _vp, C.c_double, _vp, _vp]
 lib.gwsym_dyson_G.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 lib.gwsym_iteration.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int, _vp]
+lib.gwsym_autotune.argtypes = [_vp, _vp, C.POINTER(Tuning)]
+lib.gwsym_get_tuning.argtypes = [_vp, C.POINTER(Tuning)]
+lib.gwsym_set_tuning.argtypes = [_vp, C.POINTER(Tuning), _vp]
 lib.gwsym_flop_counts.argtypes = [_vp, C.POINTER(C.c_double)]
 lib.gwsym_profile.argtypes = [_vp, C.c_int]
 lib.gwsym_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -68,8 +88,8 @@ lib.gwsym_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int
 EXPORTED = ["gwsym_create", "gwsym_destroy", "gwsym_last_error", "gwsym_build_symmetry_basis",
             "gwsym_table_size", "gwsym_get", "gwsym_device_init", "gwsym_load_V", "gwsym_to_block",
             "gwsym_from_block", "gwsym_g0", "gwsym_polarization", "gwsym_screened_interaction",
-            "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_flop_counts",
-            "gwsym_profile", "gwsym_profile_read"]
+            "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_autotune",
+            "gwsym_get_tuning", "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read"]
 
 PROFILE_CLASSES = ["p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction", "row_block_multiply",
                    "two_sided_block_multiply", "transforms", "inverses", "other"]
@@ -214,6 +234,57 @@ class Context:
     def iteration(self, F_blk, G_blk, P0_blk, P_blk, S_blk, mu, n_target=0.0, use_graph=False, stream=None):
         self._check(lib.gwsym_iteration(self.h, _ptr(F_blk), _ptr(G_blk), _ptr(P0_blk), _ptr(P_blk), _ptr(S_blk),
                                         _ptr(mu), float(n_target or 0.0), int(bool(use_graph)), _stream(stream)))
+
+    # -- launch plan ----------------------------------------------------------------
+    def plan_key(self):
+        """Hash of what a contraction plan depends on: parameters, sizes and block structure."""
+        import hashlib
+        h = hashlib.sha256()
+        p = self.params
+        h.update(repr((p.beta, p.ntau, p.nw, p.mode, p.precision, p.half_tau)).encode())
+        for name in ("dims", "ibz", "rep", "ao_blocks", "aux_blocks"):
+            h.update(self.table(name).tobytes())
+        return h.hexdigest()
+
+    def autotune(self, stream=None, cache=None):
+        """Time candidate contraction plans and keep the fastest (gwsym_autotune); returns the
+        plan as a dict.  cache: optional JSON file of plans keyed by plan_key() and the device
+        name; a plan found there is applied without timing, a new one is added."""
+        import json
+        key = None
+        if cache is not None:
+            import torch
+            key = self.plan_key() + ":" + torch.cuda.get_device_name(0)
+            try:
+                with open(cache) as f:
+                    known = json.load(f)
+            except (OSError, ValueError):
+                known = {}
+            if key in known:
+                self.set_tuning(known[key], stream)
+                return self.get_tuning()
+        t = Tuning()
+        self._check(lib.gwsym_autotune(self.h, _stream(stream), C.byref(t)))
+        plan = t.to_dict()
+        if cache is not None:
+            try:
+                with open(cache) as f:
+                    known = json.load(f)
+            except (OSError, ValueError):
+                known = {}
+            known[key] = plan
+            with open(cache, "w") as f:
+                json.dump(known, f, indent=1)
+        return plan
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(lib.gwsym_get_tuning(self.h, C.byref(t)))
+        return t.to_dict()
+
+    def set_tuning(self, plan, stream=None):
+        t = Tuning.from_dict(plan)
+        self._check(lib.gwsym_set_tuning(self.h, C.byref(t), _stream(stream)))
 
     def profile(self, enable=True):
         self._check(lib.gwsym_profile(self.h, int(enable)))

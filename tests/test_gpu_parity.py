@@ -97,6 +97,38 @@ def test_degenerate(name, mode, identity_only):
         assert e < TOL
 
 
+FORCED_PLAN = {"tau_chunk": 4, "wg_target": [2048, 32768, 4096], "cols": [64, 64, 64], "xcd_order": [0, 1, 0],
+               "kdepth": [16, 32, 16]}
+
+
+@pytest.mark.parametrize("name,precision,plan", [("small_rocksalt", 0, "auto"), ("wide_diamond", 0, "auto"),
+                                                 ("small_rocksalt", 0, "forced"), ("wide_diamond", 2, "auto"),
+                                                 ("wide_diamond", 2, "forced"), ("wide_diamond", 3, "forced")])
+def test_launch_plans(name, precision, plan):
+    """The results do not depend on the launch plan: the autotuned one and a forced non-default
+    one (small tau chunk, wide tiles, other workgroup targets, XCD order off, fixed bfloat16 k
+    depths) both meet the bar of the precision."""
+    say(f"[plan] {name} precision={precision} {plan}")
+    run = GpuRun(name, MODES["block"], precision=precision)
+    c = run.ctx
+    if plan == "auto":
+        t = c.autotune()
+    else:
+        c.set_tuning(FORCED_PLAN)
+        t = c.get_tuning()
+        assert t == FORCED_PLAN
+    say(f"  {t}")
+    ref = oracle_run(name)
+    r = ref["iters"][0]
+    run.g0()
+    c.iteration(run.F, run.G, run.P0, run.P, run.S, run.mu, ref["n_target"] or 0.0)
+    tol = TOL if precision == 0 else TOL_BY_PRECISION[precision]
+    for kind, buf, key in ((2, run.P0, "P0"), (1, run.S, "Sigma"), (1, run.G, "G")):
+        e = rel(run.full(kind, buf), r[key])
+        say(f"  {key} {e:.2e}")
+        assert e < tol
+
+
 def test_full_tau_without_mirror():
     say("[no half tau] small_rocksalt block")
     run = GpuRun("small_rocksalt", 2, half_tau=False, tau_chunk=5)

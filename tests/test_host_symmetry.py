@@ -192,3 +192,18 @@ def test_error_paths():
     ctx2 = gwsym.Context(10.0, 8, 17)
     with pytest.raises(gwsym.GwsymError, match="EINVAL"):
         ctx2.build_symmetry_basis(lat, pos, rot[::-1], trans[::-1], 2, [(0, 0)], [(0, 0)])  # op 0 not identity
+
+
+def test_tuning_defaults_and_state_errors():
+    """The launch plan is readable before any device work; applying or searching one needs the
+    device state (checked before any HIP call)."""
+    from paper_2405_09494_amd import gwsym
+    ctx = gwsym.Context(10.0, 8, 17, tau_chunk=3)
+    t = ctx.get_tuning()
+    assert t == {"tau_chunk": 3, "wg_target": [8192] * 3, "cols": [32] * 3, "xcd_order": [1] * 3, "kdepth": [0] * 3}
+    with pytest.raises(gwsym.GwsymError, match="ESTATE"):
+        ctx.set_tuning(t, stream=0)
+    with pytest.raises(gwsym.GwsymError, match="ESTATE"):
+        ctx.autotune(stream=0)
+    with pytest.raises(gwsym.GwsymError, match="EINVAL"):
+        gwsym.Context(10.0, 8, 17, precision=4)
