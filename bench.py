@@ -30,16 +30,19 @@ RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop per byte where t
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cfg1.md")
+PLANS_FILE = os.path.join(ROOT, "paper_2405_09494_amd", "plans.json")
 
 
 def source_digest():
-    """sha256 over the kernel and launch-plan sources: measured counters apply only to the
-    code they were taken from."""
+    """sha256 over the kernel and launch-plan sources and the stored launch plans: measured
+    counters apply only to the code and plans they were taken from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "pipeline.hip"):
-        with open(os.path.join(ROOT, "paper_2405_09494_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in ("csrc/kernels.hip", "csrc/pipeline.hip", "plans.json"):
+        path = os.path.join(ROOT, "paper_2405_09494_amd", f)
+        if os.path.exists(path):
+            with open(path, "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()
 
 
@@ -210,7 +213,10 @@ def main():
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the runs of the block path with FP32 and split-bfloat16 contractions")
     ap.add_argument("--autotune", type=int, default=1,
-                    help="1 (default): the block paths time candidate launch plans first and keep the fastest")
+                    help="1 (default): each block path takes its launch plan from --plans, or times candidate "
+                         "plans (gwsym_autotune) when the file has none for this workload and device; 0: default plan")
+    ap.add_argument("--plans", default=PLANS_FILE, help="JSON file of autotuned launch plans")
+    ap.add_argument("--update-plans", action="store_true", help="add newly autotuned plans to --plans")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a plain copy kernel "
                          "of known traffic, to scale hardware byte counters)")
@@ -252,9 +258,9 @@ def main():
     tuning, tune_s = blk.ctx.get_tuning(), 0.0
     if args.autotune:
         t = time.perf_counter()
-        tuning = blk.ctx.autotune()
+        tuning = blk.ctx.autotune(cache=args.plans, update=args.update_plans)
         tune_s = time.perf_counter() - t
-        log(f"[bench] autotuned in {tune_s:.1f} s: {tuning}")
+        log(f"[bench] launch plan, {blk.ctx.plan_source} ({tune_s:.1f} s): {tuning}")
     s_blk = time_steps(blk, args.steps, args.warmup, torch)
     log(f"[bench] block: {s_blk:.4f} s/iteration")
     prof = profile_step(blk, torch)
@@ -297,7 +303,8 @@ def main():
            "contraction_tflops": flops_iter / (contr_ms * 1e-3) / 1e12 if contr_ms > 0 else None,
            "algorithmic_flops_per_iteration": flops_iter,
            "profile_ms": {k: v[0] for k, v in prof.items()},
-           "launch_plan": tuning, "autotune_s": tune_s,
+           "launch_plan": tuning, "launch_plan_source": getattr(blk.ctx, "plan_source", "default"),
+           "launch_plan_s": tune_s,
            "kernels": kernels,
            "roofline": roof}
 
@@ -328,7 +335,8 @@ def main():
                           ("bf16x3_contractions", gwsym.BF16X3)):
             red = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=prec), F_all, V_all,
                        torch, dev, graph=bool(args.graph))
-            red_tuning = red.ctx.autotune() if args.autotune else red.ctx.get_tuning()
+            red_tuning = (red.ctx.autotune(cache=args.plans, update=args.update_plans) if args.autotune
+                          else red.ctx.get_tuning())
             s_red = time_steps(red, args.steps, args.warmup, torch)
             for pth in (blk, red):   # one iteration from the same G0 in both precisions
                 pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)

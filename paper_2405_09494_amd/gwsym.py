@@ -246,15 +246,23 @@ class Context:
             h.update(self.table(name).tobytes())
         return h.hexdigest()
 
-    def autotune(self, stream=None, cache=None):
+    @staticmethod
+    def device_key():
+        """Architecture and compute-unit count of device 0, e.g. gfx950-256cu."""
+        import torch
+        p = torch.cuda.get_device_properties(0)
+        return f"{p.gcnArchName.split(':')[0]}-{p.multi_processor_count}cu"
+
+    def autotune(self, stream=None, cache=None, update=True):
         """Time candidate contraction plans and keep the fastest (gwsym_autotune); returns the
-        plan as a dict.  cache: optional JSON file of plans keyed by plan_key() and the device
-        name; a plan found there is applied without timing, a new one is added."""
+        plan as a dict.  cache: optional JSON file of plans keyed by plan_key() and
+        device_key(); a plan found there is applied without timing, and (update=True) a newly
+        timed one is added to it.  self.plan_source tells which happened."""
         import json
-        key = None
+        key, known = None, {}
+        self.plan_source = "timed"
         if cache is not None:
-            import torch
-            key = self.plan_key() + ":" + torch.cuda.get_device_name(0)
+            key = self.plan_key() + ":" + self.device_key()
             try:
                 with open(cache) as f:
                     known = json.load(f)
@@ -262,19 +270,15 @@ class Context:
                 known = {}
             if key in known:
                 self.set_tuning(known[key], stream)
+                self.plan_source = "stored"
                 return self.get_tuning()
         t = Tuning()
         self._check(lib.gwsym_autotune(self.h, _stream(stream), C.byref(t)))
         plan = t.to_dict()
-        if cache is not None:
-            try:
-                with open(cache) as f:
-                    known = json.load(f)
-            except (OSError, ValueError):
-                known = {}
+        if cache is not None and update:
             known[key] = plan
             with open(cache, "w") as f:
-                json.dump(known, f, indent=1)
+                json.dump(known, f, indent=1, sort_keys=True)
         return plan
 
     def get_tuning(self):
