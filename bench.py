@@ -27,10 +27,13 @@ METRIC = "s/GW iteration + contraction TFLOP/s, block-grouped vs full FP64, at â
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop per byte where the two bounds meet
+VALU_CLASSES = ("row_block_multiply", "two_sided_block_multiply")
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cfg1.md")
 PLANS_FILE = os.path.join(ROOT, "paper_2405_09494_amd", "plans.json")
+CRYSTAL_NAMES = {"sc": "simple cubic Pm-3m", "rocksalt": "rocksalt Fm-3m (two atoms)",
+                 "diamond": "diamond Fd-3m (two atoms, non-symmorphic)"}
 
 
 def source_digest():
@@ -87,12 +90,15 @@ def make_ctx(wl, mode, half_tau=True, tau_chunk=0, precision=0):
 class Path:
     """Device state of one mode: F, G, P0, P, Sigma, mu, and the iteration."""
 
-    def __init__(self, ctx, F_all, V_all, torch, dev, graph=False):
+    def __init__(self, ctx, F_all, V_src, torch, dev, graph=False):
+        """V_src: V over every pair [Nk, Nk, ...], or a function of the irreducible indices
+        that returns V for those rows."""
         self.ctx, self.torch = ctx, torch
         self.graph = torch.cuda.Stream() if graph else None
         ctx.device_init()
         ibz = torch.as_tensor(ctx.table("ibz"), device=dev)
-        ctx.load_V(V_all[ibz].contiguous())
+        ctx.load_V(V_src(ibz) if callable(V_src) else V_src[ibz].contiguous())
+        torch.cuda.synchronize()
         z = lambda n: torch.zeros(n, dtype=torch.complex128, device=dev)
         self.F, self.G, self.P0, self.P, self.S = z(ctx.f_size), z(ctx.g_size), z(ctx.p_size), z(ctx.p_size), z(ctx.g_size)
         ctx.to_block(0, F_all[ibz].contiguous(), self.F)
@@ -145,7 +151,7 @@ def profile_step(path, torch):
     return prof
 
 
-def cpu_baseline(wl, F_all, V_all, ibz_rep_q, torch):
+def cpu_baseline(wl, F_all, vpairs, ibz_rep_q, torch):
     """The FP64 oracle (full matrices, no symmetry) on the host, timed on a bounded sample of
     one iteration at the workload's shapes: 32 P0 outputs (one q, 32 tau, every k), 32 Sigma
     outputs (one k, 32 tau, every q), the screened interaction for 4 of the Nk transfer
@@ -167,20 +173,23 @@ def cpu_baseline(wl, F_all, V_all, ibz_rep_q, torch):
     tau = oracle.tau_grid(wl.beta, nt)
     G = oracle.g0_closed_form(F, 0.0, wl.beta, tau)
     q = ibz_rep_q
-    Vq = V_all[torch.arange(nk), torch.as_tensor(add[:, q])].cpu().numpy()
+    Vq = vpairs([(kk, int(add[kk, q])) for kk in range(nk)]).cpu().numpy()
     k = ibz_rep_q
-    Vk = V_all[k, torch.as_tensor(sub[k])].cpu().numpy()
+    Vk = vpairs([(k, int(sub[k, qq])) for qq in range(nk)]).cpu().numpy()
     rng = np.random.default_rng(0)
     Ph = rng.standard_normal((nk, wl.naux, wl.naux)) * 1e-3
     Ph = Ph + Ph.transpose(0, 2, 1)
-    t = time.perf_counter()
-    for j in range(ns):
-        oracle.polarization_unit(G, Vq, add, q, j, wl.spin)
-    t_p0 = (time.perf_counter() - t) / ns
-    t = time.perf_counter()
-    for j in range(ns):
-        oracle.self_energy_unit(G, Vk, Ph, sub, k, j)
-    t_s = (time.perf_counter() - t) / ns
+    # at most ns outputs of each contraction, fewer where they take over 10 s in all
+    t, n_p0 = time.perf_counter(), 0
+    while n_p0 < ns and (n_p0 == 0 or time.perf_counter() - t < 10.0):
+        oracle.polarization_unit(G, Vq, add, q, n_p0, wl.spin)
+        n_p0 += 1
+    t_p0 = (time.perf_counter() - t) / n_p0
+    t, n_s = time.perf_counter(), 0
+    while n_s < ns and (n_s == 0 or time.perf_counter() - t < 10.0):
+        oracle.self_energy_unit(G, Vk, Ph, sub, k, n_s)
+        n_s += 1
+    t_s = (time.perf_counter() - t) / n_s
     nq = min(4, nk)
     X = rng.standard_normal((nq, nt, wl.naux, wl.naux)) * 1e-3
     X = X + X.transpose(0, 1, 3, 2)
@@ -192,7 +201,7 @@ def cpu_baseline(wl, F_all, V_all, ibz_rep_q, torch):
     oracle.dyson(F, S0, 0.0, wl.beta, wl.nw)
     t_dys = time.perf_counter() - t
     total = (t_p0 + t_s) * nk * nt + t_scr * nk + 65 * t_dys
-    sample = (f"measured: {ns} P0 outputs (q={q}, all {nk} k) at {t_p0:.3f} s each, {ns} Sigma outputs (k={k}, "
+    sample = (f"measured: {n_p0} P0 outputs (q={q}, all {nk} k) at {t_p0:.3f} s each, {n_s} Sigma outputs (k={k}, "
               f"all {nk} q) at {t_s:.3f} s each, screened interaction for {nq} momenta at {t_scr:.2f} s each, one "
               f"Dyson solve over all k {t_dys:.3f} s; scaled to {nk * nt} outputs of each contraction, {nk} "
               f"momenta and 65 Dyson solves")
@@ -237,7 +246,24 @@ def main():
     t = time.perf_counter()
     inp = Inputs(wl, device=dev)
     F_all = inp.fock()
-    V_all = inp.three_index_full()
+    if wl.pairwise:
+        # 6^3 meshes: only the irreducible rows of V are drawn (V over every pair would not fit)
+        V_all, rows = None, {}
+
+        def V_src(ibz):
+            key = tuple(ibz.tolist())
+            if key not in rows:
+                rows.clear()
+                V = torch.empty((len(key), wl.nk, wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=dev)
+                for i, k0 in enumerate(key):
+                    V[i] = inp.three_index([(k0, kp) for kp in range(wl.nk)])
+                    log(f"[bench] V row {i + 1} of {len(key)}")
+                rows[key] = V
+                torch.cuda.empty_cache()
+            return rows[key]
+    else:
+        V_all = inp.three_index_full()
+        V_src = V_all
     torch.cuda.synchronize()
     log(f"[bench] inputs generated in {time.perf_counter() - t:.1f} s")
 
@@ -252,13 +278,13 @@ def main():
 
     # ---- block-grouped, irreducible wedge, FP64 ----
     t = time.perf_counter()
-    blk = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk), F_all, V_all, torch, dev,
+    blk = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk), F_all, V_src, torch, dev,
                graph=bool(args.graph))
     log(f"[bench] block path set up in {time.perf_counter() - t:.1f} s; N_target={blk.n_target:.6f}")
     tuning, tune_s = blk.ctx.get_tuning(), 0.0
     if args.autotune:
         t = time.perf_counter()
-        tuning = blk.ctx.autotune(cache=args.plans, update=args.update_plans)
+        tuning = blk.ctx.autotune(cache=args.plans, update=args.update_plans, time_missing=not wl.pairwise)
         tune_s = time.perf_counter() - t
         log(f"[bench] launch plan, {blk.ctx.plan_source} ({tune_s:.1f} s): {tuning}")
     s_blk = time_steps(blk, args.steps, args.warmup, torch)
@@ -282,8 +308,11 @@ def main():
             achieved = nbytes / nl / avg_s / 1e9
             entry.update({"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"})
         else:
+            # the GEMM stages run on the FP64 MFMA, the block multiplies on the FP64 vector ALU
+            # (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s, the same figure)
             achieved = flops / nl / avg_s / 1e12
-            entry.update({"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"})
+            entry.update({"bound": "alu" if name in VALU_CLASSES else "mfma", "achieved": achieved,
+                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"})
         entry["frac"] = entry["achieved"] / entry["peak"]
         entry["traffic"] = measured_traffic(name)
         return entry
@@ -296,7 +325,7 @@ def main():
     out = {"metric": METRIC, "value": s_blk, "unit": "s/iteration", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * s_blk, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"{wl.name}: simple cubic Pm-3m, Gamma-centred {wl.n}^3 k mesh "
+           "config": {"workload": f"{wl.name}: {CRYSTAL_NAMES[wl.crystal]}, Gamma-centred {wl.n}^3 k mesh "
                                   f"(Nk={wl.nk}, {blk.ctx.nibz} irreducible), nao={wl.nao}, naux={wl.naux}, "
                                   f"ntau={wl.ntau}, nw={wl.nw}, beta={wl.beta}",
                       "mode": "irreducible wedge + isotypic blocks, grouped contractions", "precision": "fp64"},
@@ -309,7 +338,13 @@ def main():
            "roofline": roof}
 
     # ---- full-matrix FP64 (no symmetry) on the same GPU ----
-    if not args.no_full:
+    if wl.pairwise and not args.no_full:
+        need = 16.0 * wl.nk * wl.nk * wl.naux * wl.nao * wl.nao
+        out["full_fp64_s_per_iteration"] = None
+        out["full_fp64_note"] = (f"not run: V over every pair of the mesh alone is {need / 1e9:.0f} GB "
+                                 f"(and the form keeps two transformed copies), beyond one GPU's 288 GB")
+        log(f"[bench] full: {out['full_fp64_note']}")
+    elif not args.no_full:
         full = Path(make_ctx(wl, gwsym.MODE_FULL, tau_chunk=args.tau_chunk), F_all, V_all, torch, dev)
         # compare one iteration from the same G0 against the block path
         blk2 = blk
@@ -330,14 +365,33 @@ def main():
 
     # ---- the same block path with reduced-precision contractions (FP64 transforms, inverses
     # and mu): FP32 operands on the FP32 MFMA, and split-bfloat16 products on the bfloat16 MFMA
+    if wl.pairwise:
+        # the 6^3 workloads hold one path at a time (their errors against the oracle are checked
+        # by the sampled full-size parity tests)
+        ibz_blk = blk.ctx.table("ibz")
+        del blk
+        torch.cuda.empty_cache()
+        blk = None
     if not args.no_fp32:
-        for key, prec in (("fp32_contractions", gwsym.FP32), ("bf16x6_contractions", gwsym.BF16X6),
-                          ("bf16x3_contractions", gwsym.BF16X3)):
-            red = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=prec), F_all, V_all,
+        modes = (("fp32_contractions", gwsym.FP32), ("bf16x6_contractions", gwsym.BF16X6),
+                 ("bf16x3_contractions", gwsym.BF16X3))
+        if wl.pairwise:
+            modes = modes[1:2]
+        for key, prec in modes:
+            red = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=prec), F_all, V_src,
                        torch, dev, graph=bool(args.graph))
-            red_tuning = (red.ctx.autotune(cache=args.plans, update=args.update_plans) if args.autotune
-                          else red.ctx.get_tuning())
+            red_tuning = (red.ctx.autotune(cache=args.plans, update=args.update_plans, time_missing=not wl.pairwise)
+                          if args.autotune else red.ctx.get_tuning())
             s_red = time_steps(red, args.steps, args.warmup, torch)
+            if blk is None:
+                prof_red = profile_step(red, torch)
+                out[key] = {"s_per_iteration": s_red, "speedup_vs_fp64_block": s_blk / s_red,
+                            "launch_plan": red_tuning, "profile_ms": {k: v[0] for k, v in prof_red.items()}}
+                log(f"[bench] {key}: {s_red:.4f} s/iteration")
+                log(f"[bench] {key} profile: " + ", ".join(f"{k} {v[0]:.1f} ms" for k, v in prof_red.items()))
+                del red
+                torch.cuda.empty_cache()
+                continue
             for pth in (blk, red):   # one iteration from the same G0 in both precisions
                 pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)
                 pth.step()
@@ -361,8 +415,9 @@ def main():
             del red
 
     if not args.no_cpu:
-        ibz = blk.ctx.table("ibz")
-        out["cpu_baseline"] = cpu_baseline(wl, F_all, V_all, int(ibz[1]), torch)
+        ibz = blk.ctx.table("ibz") if blk is not None else ibz_blk
+        vpairs = (lambda pr: inp.three_index(pr)) if wl.pairwise else (lambda pr: V_all[tuple(zip(*pr))])
+        out["cpu_baseline"] = cpu_baseline(wl, F_all, vpairs, int(ibz[1]), torch)
         log(f"[bench] cpu oracle (extrapolated): {out['cpu_baseline']['value']:.1f} s/iteration")
     print(json.dumps(out), flush=True)
 

@@ -167,6 +167,7 @@ class Workload:
     beta: float
     seed: int
     mu_fixed: bool = False          # True: mu stays 0; False: N_e held fixed
+    pairwise: bool = False          # raw V drawn per (k1, k2) pair (large meshes)
     iterations: int = 1
     spin: float = 2.0
     extra: dict = field(default_factory=dict)
@@ -210,11 +211,11 @@ def workload(name: str) -> Workload:
     if name == "cfg2":
         return Workload(name, "rocksalt", 6, shells_on_atoms(_AO26, 2),
                         shells_on_atoms(_AUX25 * 5, 2), 100, 200.0, BASE_SEED + 2,
-                        iterations=10)
+                        iterations=10, pairwise=True)
     if name == "cfg4":
         return Workload(name, "diamond", 6, shells_on_atoms(_AO26, 2),
                         shells_on_atoms(_AUX25 * 6, 2), 128, 400.0, BASE_SEED + 4,
-                        iterations=10)
+                        iterations=10, pairwise=True)
     # reduced workloads for parity tests
     if name == "small_sc2":        # cfg0 crystal, more aux functions: several tiles + tail
         return Workload(name, "sc", 2, shells_on_atoms([S, P, D], 1),
@@ -241,4 +242,7 @@ def workload(name: str) -> Workload:
     if name == "wide_diamond":     # cfg4 orbital basis, non-symmorphic
         return Workload(name, "diamond", 2, shells_on_atoms(_AO26, 2),
                         shells_on_atoms([S, P, D, F_], 2), 16, 30.0, BASE_SEED + 16)
+    if name == "pair_diamond":     # small_diamond with the pair-keyed V draws of the 6^3 meshes
+        return Workload(name, "diamond", 2, shells_on_atoms([S, P, D], 2),
+                        shells_on_atoms([S, P, D, F_], 2), 16, 30.0, BASE_SEED + 18, pairwise=True)
     raise ValueError(f"unknown workload {name!r}")

@@ -7,6 +7,10 @@ Recipe (one reading of the workload specification, stated once here):
 * raw V^{k1,k2}_{ij}(Q) = (x + i y)/sqrt(2) / (1 + Q/8), Q counted from 0;
 * every raw draw comes from a Philox counter-based generator keyed by
   (seed, tensor id, first momentum index), so any row can be regenerated alone;
+  workloads marked ``pairwise`` (the 6^3 meshes, whose Nk^2 raw pairs would take
+  hundreds of GB) key the raw V by (seed, tensor id, k1, k2) instead, drawn with
+  torch's Philox generator on the generating device (so their values depend on the
+  device type), and only the pairs an output needs are drawn;
 * the raw tensors are projected onto the subspace fixed by three commuting
   projections: space-group averaging (with the orbital representation of
   ``rep.BasisRep``; for V the auxiliary index rotates with the auxiliary
@@ -33,6 +37,18 @@ TENSOR_F, TENSOR_V, TENSOR_AUXMAT = 1, 2, 3
 def _philox(seed: int, tensor: int, a: int, b: int = 0) -> np.random.Generator:
     key = (seed << 64) | (tensor << 48) | (a << 24) | b
     return np.random.Generator(np.random.Philox(key=key))
+
+
+def _pair_seed(seed: int, tensor: int, a: int, b: int) -> int:
+    """63-bit generator seed of one (tensor, k1, k2) stream: the SplitMix64 finaliser of the
+    packed key."""
+    m = (1 << 64) - 1
+    x = ((seed & 0xFFFFFFFF) << 32 | (tensor & 0xFF) << 24 | (a & 0xFFF) << 12 | (b & 0xFFF)) & m
+    x = (x + 0x9E3779B97F4A7C15) & m
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & m
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & m
+    x ^= x >> 31
+    return x & ((1 << 63) - 1)
 
 
 def _cnormal(rng, shape):
@@ -121,11 +137,36 @@ class Inputs:
         del raw
         return W * 0.25
 
+    def _raw_pairs(self, p1, p2) -> torch.Tensor:
+        """Raw V^{p1,p2}(Q) of pairwise workloads, each pair from its own seeded stream."""
+        wl = self.wl
+        out = torch.empty((len(p1), wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=self.device)
+        g = torch.Generator(device=self.device)
+        for i in range(len(p1)):
+            g.manual_seed(_pair_seed(wl.seed, TENSOR_V, int(p1[i]), int(p2[i])))
+            z = torch.randn((wl.naux, wl.nao, wl.nao, 2), generator=g, dtype=torch.float64, device=self.device)
+            out[i] = torch.view_as_complex(z)
+        scale = torch.as_tensor(1.0 / (1.0 + np.arange(wl.naux) / 8.0) / np.sqrt(2.0), device=self.device)
+        out *= scale[None, :, None, None]
+        return out
+
+    def _paired_pairs(self, p1, p2) -> torch.Tensor:
+        """Hermitian pairing and time reversal of the raw pairs (p1, p2), as _paired_V does for
+        the whole mesh: (V^{k1,k2} + V^{k2,k1 H} + V^{-k1,-k2 *} + V^{-k2,-k1 T}) / 4."""
+        m1, m2 = self.mk[p1], self.mk[p2]
+        W = self._raw_pairs(p1, p2)
+        W += self._raw_pairs(p2, p1).conj().transpose(-1, -2)
+        W += self._raw_pairs(m1, m2).conj()
+        W += self._raw_pairs(m2, m1).transpose(-1, -2)
+        return W * 0.25
+
     def three_index(self, pairs, chunk: int = 256) -> torch.Tensor:
         """Symmetric V^{k1,k2} for the given list of (k1, k2): [len(pairs), naux, nao, nao]."""
         pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
-        W = self._paired_V()
         wl = self.wl
+        if wl.pairwise:
+            return self._three_index_pairwise(pairs, max(1, min(chunk, 64)))
+        W = self._paired_V()
         out = torch.zeros((len(pairs), wl.naux, wl.nao, wl.nao), dtype=torch.complex128,
                           device=self.device)
         for a in range(self.h):
@@ -144,6 +185,27 @@ class Inputs:
                 T = (X @ T.reshape(len(pc), wl.naux, wl.nao * wl.nao)).reshape(T.shape)
                 out[c0:c0 + chunk] += T
         del W
+        return out / self.h
+
+    def _three_index_pairwise(self, pairs, chunk: int) -> torch.Tensor:
+        wl = self.wl
+        dev = self.device
+        out = torch.zeros((len(pairs), wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=dev)
+        for a in range(self.h):
+            Oao = self._t(np.stack([self.ao.matrix(a, k) for k in range(self.nk)]))
+            Oaux = self._t(np.stack([self.aux.matrix(a, q) for q in range(self.nk)]))
+            for c0 in range(0, len(pairs), chunk):
+                pc = pairs[c0:c0 + chunk]
+                p1 = self.inv_kmap[a, pc[:, 0]]
+                p2 = self.inv_kmap[a, pc[:, 1]]
+                q0 = self.sub[p1, p2]
+                Wsel = self._paired_pairs(p1, p2)
+                L = Oao[torch.as_tensor(p1, device=dev)]
+                R = Oao[torch.as_tensor(p2, device=dev)].conj().transpose(-1, -2).contiguous()
+                T = L[:, None] @ Wsel @ R[:, None]
+                X = Oaux[torch.as_tensor(q0, device=dev)]
+                T = (X @ T.reshape(len(pc), wl.naux, wl.nao * wl.nao)).reshape(T.shape)
+                out[c0:c0 + chunk] += T
         return out / self.h
 
     def three_index_full(self) -> torch.Tensor:

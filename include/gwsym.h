@@ -170,7 +170,9 @@ int gwsym_device_init(gwsym_ctx* ctx, void* stream);
  * [nibz][nk][naux][nao][nao]) and builds the two block-transformed copies the
  * contractions read: one indexed by (k0, k') for the self-energy and one indexed by
  * (q0, k) with q0 irreducible, rotated with O^k(alpha) and O_aux^q(alpha), for the
- * polarization.  The input is only read; it may be freed once `stream` is done. */
+ * polarization.  The input is only read; it may be freed once `stream` is done.  Device
+ * memory: two copies of the input's size in GWSYM_FP64; in the reduced-precision modes the
+ * FP64 copies are replaced by FP32 ones (half the size each) before this call returns. */
 int gwsym_load_V(gwsym_ctx* ctx, const void* V_ibz, void* stream);
 
 /* eq. mat_blk: full matrices at the irreducible points (device, layout by kind with
@@ -231,7 +233,9 @@ typedef struct {
   int wg_target[3];   /* workgroups a launch aims for: outer sums are split (and the parts
                          summed in a fixed order) until the tile list reaches this size */
   int cols[3];        /* output columns per wave tile: 32 or 64 */
-  int xcd_order[3];   /* 1: tiles sharing operand rows queued on one XCD in sequence; 0: plain */
+  int xcd_order[3];   /* 1: tiles sharing operand rows queued on one XCD in sequence; 2: all
+                         tiles of a problem on one XCD, the row tiles of a column chunk
+                         together; 0: plain order */
   int kdepth[3];      /* split-bfloat16 modes: k values per bfloat16 MFMA, 16 or 32; 0 picks
                          per launch (16 where 32 would pad more than a quarter of the sums) */
 } gwsym_tuning;

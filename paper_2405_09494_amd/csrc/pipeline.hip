@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <tuple>
 
 #include "kernel_api.hpp"
 
@@ -29,10 +30,17 @@ struct Range {
 // are gathered into one group, each group is given to the least loaded XCD, and the list is
 // interleaved so that a group's tiles run on that XCD one after another.  Short queues are
 // padded with empty tiles (prob = -1).
-inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vector<GemmProblem>& probs) {
+// mode 2: every problem (with its batch and outer range) is one group, its tiles ordered by
+// column chunk and then row tile, so the row tiles that read the same B columns run together.
+inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vector<GemmProblem>& probs,
+                            int mode = 1) {
   constexpr int NX = 8;
   const int n = int(tiles.size()) - t0;
   if (n <= NX) return;
+  if (mode == 2)
+    std::stable_sort(tiles.begin() + t0, tiles.end(), [](const GemmTile& a, const GemmTile& b) {
+      return std::make_tuple(a.prob, a.batch, a.t0, a.tn, a.tm) < std::make_tuple(b.prob, b.batch, b.t0, b.tn, b.tm);
+    });
   using Key = std::array<i64, 5>;
   auto keyA = [&](const GemmTile& t) {
     const GemmProblem& p = probs[t.prob];
@@ -56,7 +64,8 @@ inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vec
   };
   for (int i = t0; i < int(tiles.size()); ++i) {
     const Key ka = keyA(tiles[i]), kb = keyB(tiles[i]);
-    const Key k = small(tiles[i]) ? Key{tiles[i].prob, tiles[i].batch, 0, 0, 2} : (ca[ka] >= cb[kb] ? ka : kb);
+    const Key k = mode == 2 || small(tiles[i]) ? Key{tiles[i].prob, tiles[i].batch, mode == 2 ? tiles[i].t0 : 0, 0, 2}
+                                               : (ca[ka] >= cb[kb] ? ka : kb);
     auto it = gid.find(k);
     if (it == gid.end()) {
       it = gid.emplace(k, int(groups.size())).first;
@@ -109,14 +118,14 @@ struct GemmStage {
     pending_bytes += 16.0 * p.batch * (double(p.K) * p.T * (double(p.M) + p.N) + double(p.M) * p.N);
   }
   double pending_macs = 0, pending_bytes = 0;
-  void xcd_order(int t0) { xcd_order_tiles(tiles, t0, probs); }
+  void xcd_order(int t0, int mode = 1) { xcd_order_tiles(tiles, t0, probs, mode); }
   // Closes a launch: turns its problems into tiles; problems with a long outer loop are
   // split so that the launch has about `target` workgroups.
   bool wave = false;   // tiles for the wave-tile kernel: 32-column chunks, more of them
   // wave-tile plan: workgroups a launch aims for, 32-column chunks per tile, XCD order,
   // bfloat16 k depth (0: per launch)
   int target = 8192, per = 1, kdepth = 0;
-  bool xcd = true;
+  int xcd = 1;   // 0 plain order, 1 grouped by shared operand rows, 2 grouped by problem
   void close() {
     const int target = wave ? this->target : 2048;
     Range r;
@@ -178,7 +187,7 @@ struct GemmStage {
         const int c0 = int(tiles.size());
         for (const GemmTile& t : all)
           if ((t.mh == 2) * 2 + (t.nn >= 2) == sh) tiles.push_back(t);
-        if (xcd) xcd_order(c0);
+        if (xcd) xcd_order(c0, xcd);
         r.shape[sh] = int(tiles.size()) - c0;
       }
     } else {
@@ -429,7 +438,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   for (int g = 0; g < 3; ++g) {
     gs[g]->target = c.tune.wg_target[g];
     gs[g]->per = c.tune.cols[g] / 32;
-    gs[g]->xcd = c.tune.xcd_order[g] != 0;
+    gs[g]->xcd = c.tune.xcd_order[g];
     gs[g]->kdepth = c.tune.kdepth[g];
   }
   for (RowStage* r : {&d.p0_both, &d.s_right}) {
@@ -450,7 +459,9 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   const i64 slab = i64(nk) * na * no * no;
   int J = c.tune.tau_chunk;
   if (J <= 0) {
-    const double budget = 2.0e9 / 16.0;  // elements per workspace
+    // 2 GB per workspace, or as many tau slabs as the workspaces hold anyway for the other
+    // stages (the readout of P over every k)
+    const double budget = std::max(2.0e9 / 16.0, double(d.ws_min));  // elements per workspace
     J = int(std::max(1.0, std::min(double(nt), budget / double(slab))));
   }
   J = std::min(J, nt);
@@ -1071,6 +1082,10 @@ int device_load_V(Ctx& c, const void* Vin, void* stream) {
   }
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipStreamSynchronize(s));
+  if (c.prm.precision != GWSYM_FP64) {   // the contractions read only the FP32 copies
+    dfree(d, d.VP);
+    dfree(d, d.VS);
+  }
   c.vloaded = true;
   return GWSYM_OK;
 }
@@ -1438,9 +1453,10 @@ int device_autotune(Ctx& c, void* stream) {
       t.cols[g] = t.cols[g] == 32 ? 64 : 32;
       if ((st = trial(t, which))) return st;
     }
-    {
+    for (int v : {0, 1, 2}) {
       gwsym_tuning t = best;
-      t.xcd_order[g] ^= 1;
+      if (v == t.xcd_order[g]) continue;
+      t.xcd_order[g] = v;
       if ((st = trial(t, which))) return st;
     }
     if (bf)

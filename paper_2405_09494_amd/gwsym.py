@@ -253,11 +253,12 @@ class Context:
         p = torch.cuda.get_device_properties(0)
         return f"{p.gcnArchName.split(':')[0]}-{p.multi_processor_count}cu"
 
-    def autotune(self, stream=None, cache=None, update=True):
+    def autotune(self, stream=None, cache=None, update=True, time_missing=True):
         """Time candidate contraction plans and keep the fastest (gwsym_autotune); returns the
         plan as a dict.  cache: optional JSON file of plans keyed by plan_key() and
         device_key(); a plan found there is applied without timing, and (update=True) a newly
-        timed one is added to it.  self.plan_source tells which happened."""
+        timed one is added to it.  time_missing=False keeps the current plan when the cache has
+        none.  self.plan_source tells which happened ("stored", "timed" or "default")."""
         import json
         key, known = None, {}
         self.plan_source = "timed"
@@ -272,6 +273,9 @@ class Context:
                 self.set_tuning(known[key], stream)
                 self.plan_source = "stored"
                 return self.get_tuning()
+        if not time_missing:
+            self.plan_source = "default"
+            return self.get_tuning()
         t = Tuning()
         self._check(lib.gwsym_autotune(self.h, _stream(stream), C.byref(t)))
         plan = t.to_dict()

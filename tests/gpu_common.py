@@ -3,6 +3,7 @@ read every quantity back as full matrices over the full Brillouin zone, and run 
 oracle on the same seeded inputs."""
 import functools
 import sys
+import time
 
 import numpy as np
 import torch
@@ -12,8 +13,11 @@ from gwinputs import Inputs, workload, add_k
 from tests.helpers import make_context, sub_table
 
 
+_T0 = time.perf_counter()
+
+
 def say(*a):
-    print(*a, flush=True)
+    print(f"[{time.perf_counter() - _T0:7.1f} s]", *a, flush=True)
     sys.stdout.flush()
 
 

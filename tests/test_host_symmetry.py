@@ -207,3 +207,27 @@ def test_tuning_defaults_and_state_errors():
         ctx.autotune(stream=0)
     with pytest.raises(gwsym.GwsymError, match="EINVAL"):
         gwsym.Context(10.0, 8, 17, precision=4)
+
+
+def test_pairwise_inputs_are_symmetric():
+    """The pair-keyed draws of the 6^3 workloads (checked on a 2^3 diamond mesh) give the same
+    symmetries as the row-keyed ones: Hermitian pairing, time reversal, and invariance under
+    every space-group operation with its non-symmorphic phases,
+    V^{alpha k1, alpha k2} = Obar^q(alpha) [O^{k1}(alpha) V^{k1,k2} O^{k2}(alpha)^H]."""
+    wl = workload("pair_diamond")
+    inp = Inputs(wl)
+    V = inp.three_index_full().numpy()
+    nk, mk = wl.nk, inp.mk
+    scale = np.abs(V).max()
+    for a in range(nk):
+        for b in range(nk):
+            assert np.abs(V[b, a] - V[a, b].conj().transpose(0, 2, 1)).max() < 1e-14 * scale
+            assert np.abs(V[mk[a], mk[b]] - V[a, b].conj()).max() < 1e-14 * scale
+    for op in range(len(inp.cr.ops)):
+        for k1 in range(nk):
+            for k2 in range(0, nk, 3):
+                q = inp.sub[k1, k2]
+                L, R = inp.ao.matrix(op, k1), inp.ao.matrix(op, k2)
+                X = inp.aux.matrix(op, q)
+                rot = np.einsum("QP,Pij->Qij", X, L[None] @ V[k1, k2] @ R.conj().T[None])
+                assert np.abs(V[inp.kmap[op, k1], inp.kmap[op, k2]] - rot).max() < 1e-12 * scale
