@@ -238,13 +238,15 @@ typedef struct {
                          together; 0: plain order */
   int kdepth[3];      /* split-bfloat16 modes: k values per bfloat16 MFMA, 16 or 32; 0 picks
                          per launch (16 where 32 would pad more than a quarter of the sums) */
+  int prefetch[3];    /* FP64 / FP32 modes: K steps of 4 fetched ahead per wave, 2 or 4 */
 } gwsym_tuning;
 
 /* Autotuner: times candidate launch plans of the polarization and self-energy on this GPU
  * with the loaded V and keeps the fastest: first the tau chunk (powers of two up to the
  * half-tau count, within a workspace budget of a quarter of free device memory and 16 GB
  * per workspace), then per GEMM stage the workgroup target, tile width, XCD order and (in
- * the split-bfloat16 modes) the k depth, one at a time.  Must follow gwsym_load_V.
+ * the split-bfloat16 modes) the k depth, else the prefetch depth, one at a time.  Must follow
+ * gwsym_load_V.
  * Allocates and frees temporary device buffers (zero G and P inputs) and may grow the
  * workspaces; synchronises `stream`.  *out (host, may be NULL) receives the chosen plan. */
 int gwsym_autotune(gwsym_ctx* ctx, void* stream, gwsym_tuning* out);

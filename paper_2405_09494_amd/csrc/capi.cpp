@@ -112,6 +112,7 @@ int gwsym_create(const gwsym_params* params, gwsym_ctx** out) {
     t.cols[g] = 32;
     t.xcd_order[g] = 1;
     t.kdepth[g] = 0;
+    t.prefetch[g] = 2;
   }
   *out = ctx;
   return GWSYM_OK;
@@ -293,6 +294,7 @@ int gwsym_set_tuning(gwsym_ctx* ctx, const gwsym_tuning* t, void* stream) {
     NEED(t->cols[g] == 32 || t->cols[g] == 64, GWSYM_EINVAL, "cols must be 32 or 64");
     NEED(t->xcd_order[g] >= 0 && t->xcd_order[g] <= 2, GWSYM_EINVAL, "xcd_order must be 0, 1 or 2");
     NEED(t->kdepth[g] == 0 || t->kdepth[g] == 16 || t->kdepth[g] == 32, GWSYM_EINVAL, "kdepth must be 0, 16 or 32");
+    NEED(t->prefetch[g] == 2 || t->prefetch[g] == 4, GWSYM_EINVAL, "prefetch must be 2 or 4");
   }
   ctx->c.tune = *t;
   return device_replan(ctx->c, stream);

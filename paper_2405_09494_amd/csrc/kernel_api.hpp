@@ -22,6 +22,7 @@ struct GemmPlanDev {
   int ntiles = 0, nreds = 0, nslots = 0;
   int shape[4] = {0, 0, 0, 0};   // wave-tile lists: tiles per shape (16x16, 16x32, 32x16, 32x32), in order
   int kdepth = 32;               // split-bfloat16 forms: k values per MFMA (32, or 16 for short sums)
+  int prefetch = 2;              // FP64 / FP32 forms: K sub-steps per group (2 or 4)
 };
 
 // rows [0, nrows) of a row-major slab (right multiply), or the slab width (left multiply)

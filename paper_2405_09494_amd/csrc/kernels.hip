@@ -408,6 +408,9 @@ template <> struct WArith<2> { using R = float; static constexpr int GS = 8, NS 
 template <> struct WArith<3> { using R = float; static constexpr int GS = 8, NS = 2; };
 template <> struct WArith<4> { using R = float; static constexpr int GS = 4, NS = 3; };
 template <> struct WArith<5> { using R = float; static constexpr int GS = 4, NS = 2; };
+// FP64 and FP32 with four sub-steps per group: twice the operand bytes in flight per wave
+template <> struct WArith<6> { using R = double; static constexpr int GS = 4, NS = 0; };
+template <> struct WArith<7> { using R = float; static constexpr int GS = 4, NS = 0; };
 template <int GS> struct BfV;
 template <> struct BfV<8> { using T = bf8; };
 template <> struct BfV<4> { using T = bf4; };
@@ -765,12 +768,12 @@ void launch_wgemm_t(const GemmPlanDev& p, const Bases& b, void* partials, hipStr
 void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, int arith,
                   unsigned f32mask) {
   if (p.ntiles > 0) {
-    const bool k16 = p.kdepth == 16;
+    const bool k16 = p.kdepth == 16, deep = p.prefetch == 4;
     switch (arith) {
-      case 1: launch_wgemm_t<1>(p, b, partials, s, tag, f32mask); break;
+      case 1: deep ? launch_wgemm_t<7>(p, b, partials, s, tag, f32mask) : launch_wgemm_t<1>(p, b, partials, s, tag, f32mask); break;
       case 2: k16 ? launch_wgemm_t<4>(p, b, partials, s, tag, f32mask) : launch_wgemm_t<2>(p, b, partials, s, tag, f32mask); break;
       case 3: k16 ? launch_wgemm_t<5>(p, b, partials, s, tag, f32mask) : launch_wgemm_t<3>(p, b, partials, s, tag, f32mask); break;
-      default: launch_wgemm_t<0>(p, b, partials, s, tag, f32mask); break;
+      default: deep ? launch_wgemm_t<6>(p, b, partials, s, tag, f32mask) : launch_wgemm_t<0>(p, b, partials, s, tag, f32mask); break;
     }
   }
   launch_reduce_tag(p, b, partials, s, tag, f32mask);

@@ -23,6 +23,7 @@ struct Range {
   double bytes = 0;  // algorithmic bytes moved (memory-bound launches)
   int shape[4] = {0, 0, 0, 0};   // wave-tile launches: tiles per shape class, in list order
   int kdepth = 32;               // k values per bfloat16 MFMA in the split-bfloat16 forms
+  int prefetch = 2;              // FP64 / FP32: K sub-steps per group of the wave-tile GEMM
 };
 
 // Workgroup p of a launch runs on XCD p % 8, and each XCD has its own L2.  Tiles that read
@@ -124,7 +125,7 @@ struct GemmStage {
   bool wave = false;   // tiles for the wave-tile kernel: 32-column chunks, more of them
   // wave-tile plan: workgroups a launch aims for, 32-column chunks per tile, XCD order,
   // bfloat16 k depth (0: per launch)
-  int target = 8192, per = 1, kdepth = 0;
+  int target = 8192, per = 1, kdepth = 0, prefetch = 2;
   int xcd = 1;   // 0 plain order, 1 grouped by shared operand rows, 2 grouped by problem
   void close() {
     const int target = wave ? this->target : 2048;
@@ -207,6 +208,7 @@ struct GemmStage {
       pad8 += 8.0 * std::ceil(n / 8.0);
     }
     r.kdepth = kdepth ? kdepth : pad8 > 1.25 * sub ? 16 : 32;
+    r.prefetch = prefetch;
     max_slots = std::max(max_slots, slots);
     launches.push_back(r);
     pending.clear();
@@ -369,6 +371,7 @@ GemmPlanDev plan_of(const GemmStage& g, const Range& r) {
   p.nreds = r.nr;
   for (int i = 0; i < 4; ++i) p.shape[i] = r.shape[i];
   p.kdepth = r.kdepth;
+  p.prefetch = r.prefetch;
   return p;
 }
 
@@ -440,6 +443,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
     gs[g]->per = c.tune.cols[g] / 32;
     gs[g]->xcd = c.tune.xcd_order[g];
     gs[g]->kdepth = c.tune.kdepth[g];
+    gs[g]->prefetch = c.tune.prefetch[g];
   }
   for (RowStage* r : {&d.p0_both, &d.s_right}) {
     dfree(d, r->d);
@@ -1465,6 +1469,11 @@ int device_autotune(Ctx& c, void* stream) {
         t.kdepth[g] = v;
         if ((st = trial(t, which))) return st;
       }
+    else {
+      gwsym_tuning t = best;
+      t.prefetch[g] = t.prefetch[g] == 2 ? 4 : 2;
+      if ((st = trial(t, which))) return st;
+    }
   }
   d.prof.on = prof_on;
   c.tune = best;

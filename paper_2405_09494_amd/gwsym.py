@@ -41,18 +41,21 @@ class Crystal(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("tau_chunk", C.c_int), ("wg_target", C.c_int * 3), ("cols", C.c_int * 3),
-                ("xcd_order", C.c_int * 3), ("kdepth", C.c_int * 3)]
+                ("xcd_order", C.c_int * 3), ("kdepth", C.c_int * 3), ("prefetch", C.c_int * 3)]
+    _LISTS = ("wg_target", "cols", "xcd_order", "kdepth", "prefetch")
+    _DEFAULTS = {"prefetch": [2, 2, 2]}   # fields a plan stored before they existed
 
     def to_dict(self):
-        return {"tau_chunk": int(self.tau_chunk), "wg_target": list(self.wg_target), "cols": list(self.cols),
-                "xcd_order": list(self.xcd_order), "kdepth": list(self.kdepth)}
+        d = {"tau_chunk": int(self.tau_chunk)}
+        d.update({f: list(getattr(self, f)) for f in self._LISTS})
+        return d
 
     @classmethod
     def from_dict(cls, d):
         t = cls()
         t.tau_chunk = int(d["tau_chunk"])
-        for f in ("wg_target", "cols", "xcd_order", "kdepth"):
-            getattr(t, f)[:] = [int(x) for x in d[f]]
+        for f in cls._LISTS:
+            getattr(t, f)[:] = [int(x) for x in d.get(f, cls._DEFAULTS.get(f))]
         return t
 
 

@@ -97,8 +97,8 @@ def test_degenerate(name, mode, identity_only):
         assert e < TOL
 
 
-FORCED_PLAN = {"tau_chunk": 4, "wg_target": [2048, 32768, 4096], "cols": [64, 64, 64], "xcd_order": [0, 1, 0],
-               "kdepth": [16, 32, 16]}
+FORCED_PLAN = {"tau_chunk": 4, "wg_target": [2048, 32768, 4096], "cols": [64, 64, 64], "xcd_order": [0, 1, 2],
+               "kdepth": [16, 32, 16], "prefetch": [4, 2, 4]}
 
 
 @pytest.mark.parametrize("name,precision,plan", [("small_rocksalt", 0, "auto"), ("wide_diamond", 0, "auto"),
