@@ -11,3 +11,6 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+    # progress lines of long GPU tests go straight to the terminal, past output capture
+    from tests import progress
+    progress.CAPTURE = config.pluginmanager.getplugin("capturemanager")

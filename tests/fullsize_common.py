@@ -46,6 +46,7 @@ def setup(name):
     inp = Inputs(wl, device=dev)
     F = inp.fock()
     ctx = make_context(wl)
+    say(f"[{name}] symmetry basis built")
     ibz = ctx.table("ibz")
     nk, nib = wl.nk, len(ibz)
     add, sub = add_k(wl.n), sub_table(wl.n)
@@ -58,13 +59,16 @@ def setup(name):
     for i in range(nib):
         Vibz[i] = inp.three_index([(int(ibz[i]), kp) for kp in range(nk)])
         say(f"[{name}] V row {i + 1} of {nib}")
+    say(f"[{name}] stand-in P")
     X = inp.aux_matrices(1)[:, 0]    # [nk, naux, naux], symmetric Hermitian stand-in for P(tau_js)
     torch.cuda.empty_cache()
     Fh = F.cpu().numpy()
     tau = oracle.tau_grid(wl.beta, wl.ntau)
-    say(f"[{name}] oracle outputs")
+    say(f"[{name}] oracle G0")
     G0 = oracle.g0_closed_form(Fh, 0.0, wl.beta, tau)
+    say(f"[{name}] oracle P0 output")
     ref_p0 = oracle.polarization_unit(G0, Vq, add, q, j, wl.spin)
+    say(f"[{name}] oracle Sigma output")
     ref_s = oracle.self_energy_unit(G0, Vk, X.cpu().numpy(), sub, k, js)
     del G0, Vq, Vk
     Ux = ctx.table("U_aux").reshape(nk, wl.naux, wl.naux)[q]
@@ -78,9 +82,11 @@ def run(d, precision):
     wl, dev = d["wl"], d["dev"]
     say(f"[{wl.name}] library, precision {precision}")
     ctx = make_context(wl, precision=precision)
+    say(f"[{wl.name}] device tables and plans")
     ctx.device_init()
     ctx.load_V(d["Vibz"])
     torch.cuda.synchronize()
+    say(f"[{wl.name}] V loaded")
     z = lambda n: torch.zeros(n, dtype=torch.complex128, device=dev)
     Fb, G, P0, Pb, S = z(ctx.f_size), z(ctx.g_size), z(ctx.p_size), z(ctx.p_size), z(ctx.g_size)
     ibz_t = torch.as_tensor(d["ibz"], device=dev)

@@ -13,12 +13,7 @@ from gwinputs import Inputs, workload, add_k
 from tests.helpers import make_context, sub_table
 
 
-_T0 = time.perf_counter()
-
-
-def say(*a):
-    print(f"[{time.perf_counter() - _T0:7.1f} s]", *a, flush=True)
-    sys.stdout.flush()
+from tests.progress import say  # noqa: F401  (re-exported for the test modules)
 
 
 @functools.lru_cache(maxsize=None)
