@@ -131,6 +131,29 @@ class Path:
         return out
 
 
+def iteration_errors(ref, red, n, torch):
+    """[P0 rel, Sigma rel, occupation abs] after each of n iterations run by both paths from the
+    same G0 (mu from the electron count in both)."""
+    nk_, nt_, no_ = ref.ctx.nk, ref.ctx.ntau, ref.ctx.nao
+    occ = lambda g: -torch.diagonal(g.view(nk_, nt_, no_, no_)[:, -1], dim1=-2, dim2=-1).real
+    for pth in (ref, red):
+        pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)
+    hist = []
+    for _ in range(n):
+        for pth in (ref, red):
+            pth.step(eager=True)
+        torch.cuda.synchronize()
+        a, b = red.full(2, red.P0), ref.full(2, ref.P0)
+        e0 = float((a - b).abs().max() / b.abs().max())
+        del a, b
+        a, b = red.full(1, red.S), ref.full(1, ref.S)
+        es = float((a - b).abs().max() / b.abs().max())
+        a, b = red.full(1, red.G), ref.full(1, ref.G)
+        eo = float((occ(a) - occ(b)).abs().max())
+        hist.append((e0, es, eo))
+    return hist
+
+
 def time_steps(path, steps, warmup, torch):
     for _ in range(warmup):
         path.step()
@@ -225,6 +248,8 @@ def main():
                     help="1 (default): each block path takes its launch plan from --plans, or times candidate "
                          "plans (gwsym_autotune) when the file has none for this workload and device; 0: default plan")
     ap.add_argument("--plans", default=PLANS_FILE, help="JSON file of autotuned launch plans")
+    ap.add_argument("--error-iterations", type=int, default=10,
+                    help="iterations over which the reduced-precision paths are compared with the FP64 one")
     ap.add_argument("--update-plans", action="store_true", help="add newly autotuned plans to --plans")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a plain copy kernel "
@@ -383,6 +408,12 @@ def main():
             red_tuning = (red.ctx.autotune(cache=args.plans, update=args.update_plans, time_missing=not wl.pairwise)
                           if args.autotune else red.ctx.get_tuning())
             s_red = time_steps(red, args.steps, args.warmup, torch)
+            if blk is not None and args.error_iterations > 0:
+                # errors against the FP64 block path over several iterations from the same G0
+                # (the FP64 path is held to the oracle at 1e-10 per iteration by the parity tests)
+                hist = iteration_errors(blk, red, args.error_iterations, torch)
+                log(f"[bench] {key}: over {args.error_iterations} iterations max P0 {max(h[0] for h in hist):.2e}, "
+                    f"Sigma {max(h[1] for h in hist):.2e}, occupations {max(h[2] for h in hist):.2e}")
             if blk is None:
                 prof_red = profile_step(red, torch)
                 out[key] = {"s_per_iteration": s_red, "speedup_vs_fp64_block": s_blk / s_red,
@@ -409,6 +440,12 @@ def main():
                         "p0_rel_err_vs_fp64": err_p0, "sigma_rel_err_vs_fp64": err_s,
                         "occupation_max_abs_err_vs_fp64": occ_err, "launch_plan": red_tuning,
                         "profile_ms": {k: v[0] for k, v in prof_red.items()}}
+            if args.error_iterations > 0:
+                out[key]["errors_over_iterations"] = {
+                    "iterations": args.error_iterations, "reference": "FP64 block path, same G0",
+                    "p0_rel_max": max(h[0] for h in hist), "sigma_rel_max": max(h[1] for h in hist),
+                    "occupation_abs_max": max(h[2] for h in hist),
+                    "per_iteration": [[float(f"{x:.3e}") for x in h] for h in hist]}
             log(f"[bench] {key}: {s_red:.4f} s/iteration, P0 vs fp64 {err_p0:.2e}, Sigma {err_s:.2e}, "
                 f"occupations {occ_err:.2e}")
             log(f"[bench] {key} profile: " + ", ".join(f"{k} {v[0]:.1f} ms" for k, v in prof_red.items()))
