@@ -8,9 +8,11 @@ Recipe (one reading of the workload specification, stated once here):
 * every raw draw comes from a Philox counter-based generator keyed by
   (seed, tensor id, first momentum index), so any row can be regenerated alone;
   workloads marked ``pairwise`` (the 6^3 meshes, whose Nk^2 raw pairs would take
-  hundreds of GB) key the raw V by (seed, tensor id, k1, k2) instead, drawn with
-  torch's Philox generator on the generating device (so their values depend on the
-  device type), and only the pairs an output needs are drawn;
+  hundreds of GB) key the raw V by (seed, tensor id, k1, k2) instead and draw it from a
+  counter-based generator evaluated in bulk on the generating device: the uniform
+  numbers are the SplitMix64 finaliser of key + counter x 0x9E3779B97F4A7C15, turned into
+  normal pairs by the Box-Muller transform (the same numbers on any device, up to the
+  last bits of log, cos and sin), and only the pairs an output needs are drawn;
 * the raw tensors are projected onto the subspace fixed by three commuting
   projections: space-group averaging (with the orbital representation of
   ``rep.BasisRep``; for V the auxiliary index rotates with the auxiliary
@@ -49,6 +51,40 @@ def _pair_seed(seed: int, tensor: int, a: int, b: int) -> int:
     x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & m
     x ^= x >> 31
     return x & ((1 << 63) - 1)
+
+
+def _signed64(x: int) -> int:
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+_GOLDEN = _signed64(0x9E3779B97F4A7C15)
+_MIX1 = _signed64(0xBF58476D1CE4E5B9)
+_MIX2 = _signed64(0x94D049BB133111EB)
+
+
+def _srl(x: torch.Tensor, s: int) -> torch.Tensor:
+    """logical right shift of int64 (torch shifts arithmetically)"""
+    return (x >> s) & ((1 << (64 - s)) - 1)
+
+
+def _mix64(x: torch.Tensor) -> torch.Tensor:
+    """SplitMix64 finaliser on int64 tensors (wrapping arithmetic)."""
+    x = x ^ _srl(x, 30)
+    x = x * _MIX1
+    x = x ^ _srl(x, 27)
+    x = x * _MIX2
+    return x ^ _srl(x, 31)
+
+
+def _counter_normals(keys: torch.Tensor, n: int) -> torch.Tensor:
+    """Standard normal pairs [len(keys), n, 2]: element e of stream `key` takes the uniforms of
+    counters 2e + 1 and 2e + 2, u = (top 53 bits + 1) / 2^53 in (0, 1], through Box-Muller."""
+    c = torch.arange(1, 2 * n + 1, dtype=torch.int64, device=keys.device)
+    x = _mix64(keys[:, None] + c[None, :] * _GOLDEN)
+    u = ((_srl(x, 11) + 1).to(torch.float64) * (2.0 ** -53)).view(len(keys), n, 2)
+    r = torch.sqrt(-2.0 * torch.log(u[..., 0]))
+    t = (2.0 * np.pi) * u[..., 1]
+    return torch.stack((r * torch.cos(t), r * torch.sin(t)), dim=-1)
 
 
 def _cnormal(rng, shape):
@@ -138,14 +174,15 @@ class Inputs:
         return W * 0.25
 
     def _raw_pairs(self, p1, p2) -> torch.Tensor:
-        """Raw V^{p1,p2}(Q) of pairwise workloads, each pair from its own seeded stream."""
+        """Raw V^{p1,p2}(Q) of pairwise workloads, each pair from its own keyed counter stream."""
         wl = self.wl
+        n = wl.naux * wl.nao * wl.nao
+        keys = torch.as_tensor([_signed64(_pair_seed(wl.seed, TENSOR_V, int(a), int(b))) for a, b in zip(p1, p2)],
+                               dtype=torch.int64, device=self.device)
         out = torch.empty((len(p1), wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=self.device)
-        g = torch.Generator(device=self.device)
-        for i in range(len(p1)):
-            g.manual_seed(_pair_seed(wl.seed, TENSOR_V, int(p1[i]), int(p2[i])))
-            z = torch.randn((wl.naux, wl.nao, wl.nao, 2), generator=g, dtype=torch.float64, device=self.device)
-            out[i] = torch.view_as_complex(z)
+        for c0 in range(0, len(p1), 32):     # bounded temporaries
+            z = _counter_normals(keys[c0:c0 + 32], n)       # [pairs, n, 2]
+            out[c0:c0 + 32] = torch.view_as_complex(z).view(-1, wl.naux, wl.nao, wl.nao)
         scale = torch.as_tensor(1.0 / (1.0 + np.arange(wl.naux) / 8.0) / np.sqrt(2.0), device=self.device)
         out *= scale[None, :, None, None]
         return out
@@ -165,6 +202,8 @@ class Inputs:
         pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
         wl = self.wl
         if wl.pairwise:
+            if len(pairs) > 1 and (pairs[:, 0] == pairs[0, 0]).all():
+                return self._three_index_row(int(pairs[0, 0]), pairs[:, 1])
             return self._three_index_pairwise(pairs, max(1, min(chunk, 64)))
         W = self._paired_V()
         out = torch.zeros((len(pairs), wl.naux, wl.nao, wl.nao), dtype=torch.complex128,
@@ -187,13 +226,17 @@ class Inputs:
         del W
         return out / self.h
 
+    def _omats(self, rep: BasisRep, a: int) -> torch.Tensor:
+        """O^k(alpha_a) for every k of the mesh, [Nk, size, size], formed on the device."""
+        return self._t(rep.template(a))[None] * self._t(rep.column_phases(a))[:, None, :]
+
     def _three_index_pairwise(self, pairs, chunk: int) -> torch.Tensor:
         wl = self.wl
         dev = self.device
         out = torch.zeros((len(pairs), wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=dev)
         for a in range(self.h):
-            Oao = self._t(np.stack([self.ao.matrix(a, k) for k in range(self.nk)]))
-            Oaux = self._t(np.stack([self.aux.matrix(a, q) for q in range(self.nk)]))
+            Oao = self._omats(self.ao, a)
+            Oaux = self._omats(self.aux, a)
             for c0 in range(0, len(pairs), chunk):
                 pc = pairs[c0:c0 + chunk]
                 p1 = self.inv_kmap[a, pc[:, 0]]
@@ -206,6 +249,32 @@ class Inputs:
                 X = Oaux[torch.as_tensor(q0, device=dev)]
                 T = (X @ T.reshape(len(pc), wl.naux, wl.nao * wl.nao)).reshape(T.shape)
                 out[c0:c0 + chunk] += T
+        return out / self.h
+
+    def _three_index_row(self, k1: int, k2s) -> torch.Tensor:
+        """The same projection for pairs (k1, k2) with one k1: every operation alpha reads the raw
+        row p1 = alpha^{-1} k1, so each distinct p1 (the star of k1) is paired once and reused."""
+        wl = self.wl
+        dev = self.device
+        k2s = np.asarray(k2s, dtype=np.int64)
+        out = torch.zeros((len(k2s), wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=dev)
+        by_p1 = {}
+        for a in range(self.h):
+            by_p1.setdefault(int(self.inv_kmap[a, k1]), []).append(a)
+        all_k = np.arange(self.nk)
+        for p1, alphas in by_p1.items():
+            W = self._paired_pairs(np.full(self.nk, p1), all_k)      # W[p2] = paired V^{p1,p2}
+            for a in alphas:
+                p2 = self.inv_kmap[a, k2s]
+                q0 = self.sub[p1, p2]
+                Oao = self._omats(self.ao, a)
+                L = Oao[p1]
+                R = Oao[torch.as_tensor(p2, device=dev)].conj().transpose(-1, -2).contiguous()
+                X = self._omats(self.aux, a)[torch.as_tensor(q0, device=dev)]
+                T = L[None, None] @ W[torch.as_tensor(p2, device=dev)] @ R[:, None]
+                T = (X @ T.reshape(len(k2s), wl.naux, wl.nao * wl.nao)).reshape(T.shape)
+                out += T
+            del W
         return out / self.h
 
     def three_index_full(self) -> torch.Tensor:

@@ -105,6 +105,26 @@ class BasisRep:
                     raise ValueError("operation does not map the crystal onto itself")
         return perm, shift
 
+    def template(self, a: int) -> np.ndarray:
+        """O^k(alpha_a) without its k-dependent phases: the Wigner blocks at the permuted
+        shell positions."""
+        O = np.zeros((self.size, self.size), dtype=complex)
+        for s, (x, l) in enumerate(self.shells):
+            sp = self.lookup[(self.perm[a, x], self.local[s])]
+            o, op = self.offsets[s], self.offsets[sp]
+            O[op:op + 2 * l + 1, o:o + 2 * l + 1] = self.D[a][l]
+        return O
+
+    def column_phases(self, a: int) -> np.ndarray:
+        """[Nk, size]: the phase every column of O^k(alpha_a) carries (that of its shell), so
+        that O^k(alpha_a) = template(a) * column_phases(a)[k][None, :]."""
+        W = self.cr.ops[a][0]
+        kt = (self.pts @ np.rint(np.linalg.inv(W)).astype(np.int64)) % self.n     # rows: W^{-T} k
+        shell_of_col = np.repeat(np.arange(len(self.shells)), [2 * l + 1 for _, l in self.shells])
+        sh = self.shift[a][[x for x, _ in self.shells]]                            # [shells, 3]
+        ph = np.exp(-2j * np.pi * (kt @ sh.T) / self.n)                           # [Nk, shells]
+        return ph[:, shell_of_col]
+
     def matrix(self, a: int, k: int) -> np.ndarray:
         """O^k(alpha_a): columns are the images of the Bloch orbitals at k,
         expanded in the Bloch orbitals at alpha k (reduced to the mesh)."""
