@@ -41,7 +41,7 @@ def oracle_run(name, iterations=1):
     return out
 
 
-class GpuRun:
+class DeviceRun:
     """Device buffers and calls of one workload in one mode."""
 
     def __init__(self, name, mode, half_tau=True, tau_chunk=0, precision=0, identity_only=False):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from tests.gpu_common import GpuRun, inputs, oracle_run, say
+from tests.gpu_common import DeviceRun, inputs, oracle_run, say
 from tests.helpers import rel
 
 pytestmark = pytest.mark.gpu
@@ -24,7 +24,7 @@ def _gpu():
 @pytest.mark.parametrize("name,mode", [("cfg0", "full"), ("cfg0", "block"), ("small_diamond", "block")])
 def test_block_round_trip(name, mode):
     say(f"[round trip] {name} {mode}")
-    run = GpuRun(name, MODES[mode])
+    run = DeviceRun(name, MODES[mode])
     wl, inp, F, V = inputs(name)
     Ff = run.full(0, run.F)
     assert rel(Ff, F) < TOL
@@ -34,7 +34,7 @@ def test_block_round_trip(name, mode):
                                        ("small_diamond", "block"), ("small_diamond", "rotate")])
 def test_g0(name, mode):
     say(f"[g0] {name} {mode}")
-    run = GpuRun(name, MODES[mode])
+    run = DeviceRun(name, MODES[mode])
     run.g0()
     ref = oracle_run(name)
     assert rel(run.full(1, run.G), ref["G0"]) < TOL
@@ -52,7 +52,7 @@ CASES = [("cfg0", "full"), ("cfg0", "block"), ("small_sc2", "block"), ("small_ro
 @pytest.mark.parametrize("name,mode", CASES)
 def test_iteration(name, mode):
     say(f"[iteration] {name} {mode}")
-    run = GpuRun(name, MODES[mode], tau_chunk=3)
+    run = DeviceRun(name, MODES[mode], tau_chunk=3)
     ref = oracle_run(name)
     r = ref["iters"][0]
     run.g0()
@@ -85,7 +85,7 @@ def test_iteration(name, mode):
 def test_degenerate(name, mode, identity_only):
     """A single k point, and the trivial group (one block per matrix, every point irreducible)."""
     say(f"[degenerate] {name} {mode} identity_only={identity_only}")
-    run = GpuRun(name, MODES[mode], identity_only=identity_only)
+    run = DeviceRun(name, MODES[mode], identity_only=identity_only)
     ref = oracle_run(name)
     r = ref["iters"][0]
     run.g0()
@@ -109,7 +109,7 @@ def test_launch_plans(name, precision, plan):
     one (small tau chunk, wide tiles, other workgroup targets, XCD order off, fixed bfloat16 k
     depths) both meet the bar of the precision."""
     say(f"[plan] {name} precision={precision} {plan}")
-    run = GpuRun(name, MODES["block"], precision=precision)
+    run = DeviceRun(name, MODES["block"], precision=precision)
     c = run.ctx
     if plan == "auto":
         t = c.autotune()
@@ -131,7 +131,7 @@ def test_launch_plans(name, precision, plan):
 
 def test_full_tau_without_mirror():
     say("[no half tau] small_rocksalt block")
-    run = GpuRun("small_rocksalt", 2, half_tau=False, tau_chunk=5)
+    run = DeviceRun("small_rocksalt", 2, half_tau=False, tau_chunk=5)
     r = oracle_run("small_rocksalt")["iters"][0]
     run.g0()
     run.ctx.polarization(run.G, run.P0)
@@ -140,7 +140,7 @@ def test_full_tau_without_mirror():
 
 def test_deterministic_rerun():
     say("[determinism] small_diamond block")
-    run = GpuRun("small_diamond", 2)
+    run = DeviceRun("small_diamond", 2)
     run.g0()
     run.ctx.polarization(run.G, run.P0)
     run.ctx.screened_interaction(run.P0, run.P)
@@ -165,7 +165,7 @@ PRECISION_NAME = {1: "fp32", 2: "bf16x6", 3: "bf16x3"}
 @pytest.mark.parametrize("name", ["cfg0", "small_sc4", "small_diamond", "wide_diamond"])
 def test_reduced_precision_contractions(name, precision):
     say(f"[{PRECISION_NAME[precision]}] {name}")
-    run = GpuRun(name, MODES["block"], precision=precision)
+    run = DeviceRun(name, MODES["block"], precision=precision)
     ref = oracle_run(name)
     r = ref["iters"][0]
     run.g0()
@@ -193,7 +193,7 @@ def test_graph_iteration(name):
     say(f"[graph] {name}")
     ref = oracle_run(name)
     nt = ref["n_target"] or 0.0
-    eager, graph = GpuRun(name, MODES["block"]), GpuRun(name, MODES["block"])
+    eager, graph = DeviceRun(name, MODES["block"]), DeviceRun(name, MODES["block"])
     eager.g0()
     graph.g0()
     side = torch.cuda.Stream()
