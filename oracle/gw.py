@@ -199,6 +199,20 @@ def self_energy_unit(G: np.ndarray, Vk: np.ndarray, P: np.ndarray, sub: np.ndarr
     return -(1.0 / nk) * acc
 
 
+def exchange(G: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """Exchange part of the static self-energy (eq. sigma_hf, K term) with the density matrix
+    gamma^k = G^k(0^-) = -G^k(beta):
+    K^k = -(1/Nk) sum_{k'} sum_Q V^{k,k'}(Q) gamma^{k'} V^{k',k}(Q).  Spin-diagonal: no spin
+    factor."""
+    nk = G.shape[0]
+    gamma = -G[:, -1]
+    K = np.zeros((nk,) + G.shape[2:], dtype=complex)
+    for k in range(nk):
+        for kp in range(nk):
+            K[k] += np.einsum("Qia,ab,Qbj->ij", V[k, kp], gamma[kp], V[kp, k], optimize=True)
+    return -K / nk
+
+
 # ----------------------------------------------------------------------------
 # screened interaction (eq. P02P) and Dyson equation (eq. dyson)
 

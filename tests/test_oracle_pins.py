@@ -373,3 +373,54 @@ def test_single_output_units_match_full_contractions():
     for k, j in [(0, 1), (7, 3)]:
         Vk = np.stack([V[k, sub[k, q]] for q in range(nk)])
         assert np.abs(oracle.self_energy_unit(G, Vk, P[:, j], sub, k, j) - S[k, j]).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------- exchange (eq. sigma_hf, K)
+
+def test_bruteforce_exchange():
+    """K^k_ij = -(1/Nk) sum_{k'} sum_{ab} sum_Q V^{kk'}_{ia}(Q) gamma^{k'}_{ab} V^{k'k}_{bj}(Q),
+    gamma = G(0^-) = -G(beta), written out index by index on a tiny mesh."""
+    V, G, _ = _tiny_inputs(seed=7)
+    nk, nt, nao, _ = G.shape
+    naux = V.shape[2]
+    ref = np.zeros((nk, nao, nao), complex)
+    for k in range(nk):
+        for i in range(nao):
+            for j in range(nao):
+                acc = 0j
+                for kp in range(nk):
+                    for a in range(nao):
+                        for b in range(nao):
+                            for Q in range(naux):
+                                acc += V[k, kp, Q, i, a] * (-G[kp, nt - 1, a, b]) * V[kp, k, Q, b, j]
+                ref[k, i, j] = -acc / nk
+    got = oracle.exchange(G, V)
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_exchange_one_orbital_pair_closed_form():
+    """One k point, one auxiliary function, V = [[0, v], [v*, 0]], F = diag(e1, e2): gamma is
+    diag(f1, f2) with f = 1/(1 + exp(beta e)), so K = -V gamma V = -diag(|v|^2 f2, |v|^2 f1)."""
+    e1, e2, v, beta = -0.4, 0.7, 0.3 - 0.2j, 10.0
+    F = np.diag([e1, e2]).astype(complex)[None]
+    V = np.zeros((1, 1, 1, 2, 2), complex)
+    V[0, 0, 0, 0, 1] = v
+    V[0, 0, 0, 1, 0] = np.conj(v)
+    G = oracle.g0_closed_form(F, 0.0, beta, oracle.tau_grid(beta, 8))
+    f1, f2 = 1 / (1 + np.exp(beta * e1)), 1 / (1 + np.exp(beta * e2))
+    K = oracle.exchange(G, V)[0]
+    assert np.abs(K - np.diag([-abs(v) ** 2 * f2, -abs(v) ** 2 * f1])).max() < 1e-15
+
+
+def test_exchange_hermitian_negative_semidefinite_and_symmetric(diamond_run):
+    """With Hermitian pairing of V and 0 <= gamma <= 1, K = -sum (V gamma^1/2)(V gamma^1/2)^H is
+    Hermitian and negative semidefinite; it obeys the group relation like Sigma."""
+    inp, V = diamond_run["inp"], diamond_run["V"]
+    K = oracle.exchange(diamond_run["G0"], V)
+    scale = np.abs(K).max()
+    assert np.abs(K - np.conj(np.swapaxes(K, -1, -2))).max() < 1e-14 * scale
+    assert np.linalg.eigvalsh(K).max() < 1e-13 * scale
+    for a in range(inp.h):
+        for k in range(inp.nk):
+            O = inp.ao.matrix(a, k)
+            assert np.abs(O @ K[k] @ O.conj().T - K[inp.kmap[a, k]]).max() < 1e-12 * scale
