@@ -213,6 +213,15 @@ int gwsym_find_mu(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, doub
 int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, const double* mu,
                   void* G_blk, void* stream);
 
+/* eq. sigma_hf, exchange term: K^k = -(1/Nk) sum_{k'} sum_Q V^{k,k'}(Q) gamma^{k'} V^{k',k}(Q)
+ * with the density matrix gamma^k = G^k(0^-) = -G^k(beta), taken from the last tau point of
+ * G_blk (device, G layout).  Writes K_blk (device) in the F layout: block-packed, one matrix
+ * per irreducible point ("f_off").  Spin-diagonal, so no spin factor.  The Hartree term J and
+ * the update of F are not computed (F stays as given).  GWSYM_FP64 only (GWSYM_EINVAL in the
+ * reduced-precision modes, which keep only FP32 copies of V).  Uses the contraction
+ * workspaces: not concurrent with the other calls of this context. */
+int gwsym_exchange(gwsym_ctx* ctx, const void* G_blk, void* K_blk, void* stream);
+
 /* One GW iteration in the order of Alg. 2: polarization(G) -> screened interaction ->
  * self-energy(G, P) -> (find_mu when n_target > 0, else mu is read as given) -> dyson_G,
  * which overwrites G_blk.  All buffers are device memory of the layouts above; mu is one

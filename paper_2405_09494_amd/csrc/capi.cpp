@@ -270,6 +270,13 @@ int gwsym_profile_read(gwsym_ctx* ctx, double* ms, int64_t* launches, double* ma
   return device_profile_read(ctx->c, ms, launches, macs, bytes);
 }
 
+int gwsym_exchange(gwsym_ctx* ctx, const void* G_blk, void* K_blk, void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");
+  NEED(G_blk && K_blk, GWSYM_EINVAL, "NULL buffer");
+  return device_exchange(ctx->c, G_blk, K_blk, stream);
+}
+
 int gwsym_autotune(gwsym_ctx* ctx, void* stream, gwsym_tuning* out) {
   if (!ctx) return GWSYM_EINVAL;
   NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");

@@ -309,6 +309,10 @@ struct DevState {
   GemmStage p0_gemm, s_gemmA, s_gemmC, scr_fwd, scr_bwd, dys_fwd, dys_bwd, tb_1[3], tb_2[3], fb_1[3], fb_2[3];
   GemmStage lv1, lv2, lv3;
   RowStage p0_both, s_right;
+  // exchange part of the static self-energy (eq. sigma_hf, K term), one launch set per k0
+  GemmStage hx_gemm;
+  RowStage hx_right;
+  ListStage<CopySeg> hx_pack;
   ListStage<CopySeg> p0_mirror, scr_herm, dys_herm, s_pack;
   void* SCR = nullptr;      // full nao x nao self-energy products of one tau chunk
   ListStage<InvItem> scr_inv, dys_inv, mu_inv;
@@ -745,6 +749,57 @@ int device_init(Ctx& c, void* stream) {
     return GWSYM_ESHAPE;
   }
   if ((st = plan_contractions(c, d, s))) return st;
+
+  // ---------------- exchange (eq. sigma_hf, K term) ----------------
+  // K^{k0} = -(1/Nk) sum_{k', Q} V^{k0,k'}(Q) gamma^{k'} V^{k0,k'}(Q)^H with gamma = -G(beta):
+  // Z(k') = V_S[k0][k'] G^{k'}(beta) (block multiply), then +(1/Nk) sum_{(k',s)} Z V_S^H on the
+  // diagonal squares of the same orbital bins as the self-energy, gathered into the F layout.
+  d.hx_gemm.wave = true;
+  {
+    const i64 slab1 = i64(nk) * na * no * no;
+    for (int i = 0; i < nib; ++i) {
+      const Blocks& BO = c.bao[i];
+      for (int kp = 0; kp < nk; ++kp) {
+        const int ik = c.rep[kp];
+        RowSeg r{};
+        r.inbuf = B_VS; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
+        r.in_off = (i64(i) * nk + kp) * na * no * no;
+        r.out_off = i64(kp) * na * no * no;
+        r.g_off = c.g_off[ik] + i64(nt - 1) * c.bao[ik].packed;
+        r.out_off2 = -1;
+        r.nrows = na * no;
+        double sq = 0;
+        for (int sz : c.bao[ik].size) sq += double(sz) * sz;
+        d.hx_right.add(r, double(na) * no * sq, double(na) * no * no);
+      }
+      int r0 = 0, nb = 0;
+      std::vector<std::pair<int, int>> bins;
+      for (size_t rb = 0; rb < BO.size.size(); ++rb) {
+        if (nb > 0 && nb + BO.size[rb] > 16) {
+          bins.push_back({r0, nb});
+          r0 += nb;
+          nb = 0;
+        }
+        nb += BO.size[rb];
+      }
+      if (nb > 0) bins.push_back({r0, nb});
+      for (const auto& bn : bins) {
+        GemmProblem p = gp(bn.second, bn.second, no, nk * na, 1, B_W2, i64(bn.first) * no, no, i64(no) * no, 0, OP_N,
+                           B_VS, i64(i) * slab1 + i64(bn.first) * no, no, i64(no) * no, 0, OP_H, B_SCR,
+                           i64(bn.first) * no + bn.first, no, 0, 1.0 / nk);
+        d.hx_gemm.add(p);
+      }
+      for (size_t rb = 0; rb < BO.size.size(); ++rb)
+        d.hx_pack.items.push_back({B_SCR, B_OUT, BO.size[rb], 0, i64(BO.off[rb]) * no + BO.off[rb],
+                                   c.f_off[i] + BO.poff[rb], no});
+      d.hx_right.close();
+      d.hx_gemm.close();
+      d.hx_pack.close();
+    }
+    if ((st = upload_stage(c, d, d.hx_gemm, s))) return st;
+    if ((st = upload(c, d, d.hx_right.segs, &d.hx_right.d, s))) return st;
+    if ((st = upload(c, d, d.hx_pack.items, &d.hx_pack.d, s))) return st;
+  }
 
   // ---------------- screened interaction (eq. P02P) ----------------
   for (int i = 0; i < nib; ++i) {
@@ -1205,6 +1260,31 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
   }
   HIPCHECK(hipGetLastError());
   c.last_macs[1] = d.s_gemmA.macs + d.s_gemmC.macs;
+  return GWSYM_OK;
+}
+
+int device_exchange(Ctx& c, const void* G, void* K, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  if (c.prm.precision != GWSYM_FP64) {
+    c.err = "the exchange term is computed in FP64 only (the reduced modes keep FP32 copies of V)";
+    return GWSYM_EINVAL;
+  }
+  int st;
+  if ((st = need_partials(c, d))) return st;
+  Bases b = bases_of(d);
+  b.p[B_G] = const_cast<void*>(G);
+  b.p[B_OUT] = K;
+  for (size_t l = 0; l < d.hx_gemm.launches.size(); ++l) {
+    const Range& rr = d.hx_right.launches[l];
+    RowSegList R{static_cast<RowSeg*>(d.hx_right.d) + rr.t0, rr.nt, rr.r0};
+    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, d.gmax, s, false); }, rr.bytes);
+    const Range& rc = d.hx_gemm.launches[l];
+    timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.hx_gemm, rc), b, d.partials, s, 3, 0, 0u); }, rc.bytes);
+    const Range& rp = d.hx_pack.launches[l];
+    timed(d, s, PC_OTHER, 0, [&] { launch_pack(static_cast<CopySeg*>(d.hx_pack.d) + rp.t0, rp.nt, b, s); });
+  }
+  HIPCHECK(hipGetLastError());
   return GWSYM_OK;
 }
 

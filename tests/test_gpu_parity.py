@@ -210,3 +210,45 @@ def test_graph_iteration(name):
         assert torch.equal(eager.S, graph.S) and torch.equal(eager.mu, graph.mu)
         if it == 0:
             assert rel(Gg, ref["iters"][0]["G"]) < TOL
+
+
+@pytest.mark.parametrize("name,mode", [("cfg0", "full"), ("cfg0", "block"), ("small_rocksalt", "block"),
+                                       ("small_rocksalt", "rotate"), ("small_diamond", "block"),
+                                       ("wide_diamond", "block"), ("gamma_sc", "block")])
+def test_exchange(name, mode):
+    """Exchange part of the static self-energy (eq. sigma_hf) from the free G0, against the
+    oracle, after from_block at every k."""
+    import oracle
+    say(f"[exchange] {name} {mode}")
+    run = DeviceRun(name, MODES[mode])
+    run.g0()
+    K = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    run.ctx.exchange(run.G, K)
+    wl, inp, F, V = inputs(name)
+    e = rel(run.full(0, K), oracle.exchange(oracle_run(name)["G0"], V))
+    say(f"  K {e:.2e}")
+    assert e < TOL
+
+
+def test_exchange_after_iteration():
+    """The same from the Green's function one iteration later (interacting density matrix)."""
+    import oracle
+    say("[exchange after iteration] small_diamond block")
+    run = DeviceRun("small_diamond", MODES["block"])
+    ref = oracle_run("small_diamond")
+    run.g0()
+    run.iteration(ref["n_target"])
+    K = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    run.ctx.exchange(run.G, K)
+    wl, inp, F, V = inputs("small_diamond")
+    e = rel(run.full(0, K), oracle.exchange(ref["iters"][0]["G"], V))
+    say(f"  K {e:.2e}")
+    assert e < TOL
+
+
+def test_exchange_fp64_only():
+    from paper_2405_09494_amd import gwsym
+    run = DeviceRun("small_rocksalt", MODES["block"], precision=1)
+    K = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    with pytest.raises(gwsym.GwsymError, match="EINVAL"):
+        run.ctx.exchange(run.G, K)
