@@ -248,6 +248,7 @@ def main():
                     help="1 (default): each block path takes its launch plan from --plans, or times candidate "
                          "plans (gwsym_autotune) when the file has none for this workload and device; 0: default plan")
     ap.add_argument("--plans", default=PLANS_FILE, help="JSON file of autotuned launch plans")
+    ap.add_argument("--no-exchange", action="store_true", help="skip timing the exchange term (profiling runs)")
     ap.add_argument("--error-iterations", type=int, default=10,
                     help="iterations over which the reduced-precision paths are compared with the FP64 one")
     ap.add_argument("--update-plans", action="store_true", help="add newly autotuned plans to --plans")
@@ -322,16 +323,18 @@ def main():
     log("[bench] profile: " + ", ".join(f"{k} {v[0]:.1f} ms/{v[1]}" for k, v in prof.items()))
 
     # exchange part of the static self-energy (eq. sigma_hf) from the current G, once
-    Kx = torch.zeros(blk.ctx.f_size, dtype=torch.complex128, device=dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    blk.ctx.exchange(blk.G, Kx)
-    ev0.record()
-    blk.ctx.exchange(blk.G, Kx)
-    ev1.record()
-    torch.cuda.synchronize()
-    exchange_ms = ev0.elapsed_time(ev1)
-    log(f"[bench] exchange (Sigma_HF, K term): {exchange_ms:.2f} ms")
-    del Kx
+    exchange_ms = None
+    if not args.no_exchange:
+        Kx = torch.zeros(blk.ctx.f_size, dtype=torch.complex128, device=dev)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        blk.ctx.exchange(blk.G, Kx)
+        ev0.record()
+        blk.ctx.exchange(blk.G, Kx)
+        ev1.record()
+        torch.cuda.synchronize()
+        exchange_ms = ev0.elapsed_time(ev1)
+        log(f"[bench] exchange (Sigma_HF, K term): {exchange_ms:.2f} ms")
+        del Kx
 
     # dominant kernel class by time; its bound follows from the algorithmic intensity
     def roofline(name):
