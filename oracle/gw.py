@@ -213,6 +213,23 @@ def exchange(G: np.ndarray, V: np.ndarray) -> np.ndarray:
     return -K / nk
 
 
+def hartree(G: np.ndarray, V: np.ndarray, spin: float) -> np.ndarray:
+    """Hartree part of the static self-energy (eq. sigma_hf, J term) with the density matrix
+    gamma^k = G^k(0^-) = -G^k(beta): the density on the auxiliary functions,
+    rho(Q) = sum_{k'} sum_{ab} gamma^{k'}_{ab} V^{k'k'}_{ba}(Q), then
+    J^k_ij = (s/Nk) sum_Q V^{kk}_ij(Q) rho(Q).  The sum over the spin index sigma_1 of the
+    equation gives the spin factor s (gamma is the density matrix of one spin)."""
+    nk = G.shape[0]
+    gamma = -G[:, -1]
+    rho = np.zeros(V.shape[2], dtype=complex)
+    for kp in range(nk):
+        rho += np.einsum("ab,Qba->Q", gamma[kp], V[kp, kp])
+    J = np.zeros((nk,) + G.shape[2:], dtype=complex)
+    for k in range(nk):
+        J[k] = np.einsum("Q,Qij->ij", rho, V[k, k])
+    return (spin / nk) * J
+
+
 # ----------------------------------------------------------------------------
 # screened interaction (eq. P02P) and Dyson equation (eq. dyson)
 

@@ -424,3 +424,63 @@ def test_exchange_hermitian_negative_semidefinite_and_symmetric(diamond_run):
         for k in range(inp.nk):
             O = inp.ao.matrix(a, k)
             assert np.abs(O @ K[k] @ O.conj().T - K[inp.kmap[a, k]]).max() < 1e-12 * scale
+
+
+
+# ----------------------------------------------------------------------------- Hartree (eq. sigma_hf, J)
+
+def test_bruteforce_hartree():
+    """J^k_ij = (s/Nk) sum_{k'} sum_{ab} sum_Q V^{kk}_{ij}(Q) gamma^{k'}_{ab} V^{k'k'}_{ba}(Q),
+    gamma = -G(beta), written out index by index on a tiny mesh."""
+    V, G, _ = _tiny_inputs(seed=11)
+    s = 2.0
+    nk, nt, nao, _ = G.shape
+    naux = V.shape[2]
+    ref = np.zeros((nk, nao, nao), complex)
+    for k in range(nk):
+        for i in range(nao):
+            for j in range(nao):
+                acc = 0j
+                for kp in range(nk):
+                    for a in range(nao):
+                        for b in range(nao):
+                            for Q in range(naux):
+                                acc += V[k, k, Q, i, j] * (-G[kp, nt - 1, a, b]) * V[kp, kp, Q, b, a]
+                ref[k, i, j] = s * acc / nk
+    got = oracle.hartree(G, V, s)
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_hartree_one_orbital_pair_closed_form():
+    """One k point, one auxiliary function, V = [[v1, w], [w*, v2]], F = diag(e1, e2): gamma is
+    diag(f1, f2), the density on the auxiliary function is v1 f1 + v2 f2 (the off-diagonal w
+    does not contribute), and J = s (v1 f1 + v2 f2) V."""
+    e1, e2, v1, v2, w, beta, s = -0.4, 0.7, 0.9, 0.35, 0.3 - 0.2j, 10.0, 2.0
+    F = np.diag([e1, e2]).astype(complex)[None]
+    V = np.zeros((1, 1, 1, 2, 2), complex)
+    V[0, 0, 0] = [[v1, w], [np.conj(w), v2]]
+    G = oracle.g0_closed_form(F, 0.0, beta, oracle.tau_grid(beta, 8))
+    f1, f2 = 1 / (1 + np.exp(beta * e1)), 1 / (1 + np.exp(beta * e2))
+    J = oracle.hartree(G, V, s)[0]
+    assert np.abs(J - s * (v1 * f1 + v2 * f2) * V[0, 0, 0]).max() < 1e-15
+
+
+def test_hartree_hermitian_positive_energy_and_symmetric(diamond_run):
+    """With Hermitian V^{kk}(Q) and gamma, the density on each auxiliary function is real, J is
+    Hermitian and the Hartree energy sum_k Tr[gamma^k J^k] = (s/Nk) sum_Q rho(Q)^2 is real and
+    positive; J obeys the group relation like Sigma.  A Gamma-only reading of the sum over k'
+    (dropping the other momenta) changes J."""
+    inp, V, G0, wl = diamond_run["inp"], diamond_run["V"], diamond_run["G0"], diamond_run["wl"]
+    J = oracle.hartree(G0, V, wl.spin)
+    scale = np.abs(J).max()
+    assert scale > 0
+    assert np.abs(J - np.conj(np.swapaxes(J, -1, -2))).max() < 1e-14 * scale
+    E = sum(np.trace(-G0[k, -1] @ J[k]) for k in range(inp.nk))
+    assert abs(E.imag) < 1e-13 * abs(E) and E.real > 0
+    for a in range(inp.h):
+        for k in range(inp.nk):
+            O = inp.ao.matrix(a, k)
+            assert np.abs(O @ J[k] @ O.conj().T - J[inp.kmap[a, k]]).max() < 1e-12 * scale
+    G1 = np.zeros_like(G0)
+    G1[0] = G0[0] * inp.nk
+    assert np.abs(oracle.hartree(G1, V, wl.spin) - J).max() > 1e-6 * scale
