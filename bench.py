@@ -322,18 +322,25 @@ def main():
                                          "row_block_multiply", "two_sided_block_multiply"))
     log("[bench] profile: " + ", ".join(f"{k} {v[0]:.1f} ms/{v[1]}" for k, v in prof.items()))
 
-    # exchange part of the static self-energy (eq. sigma_hf) from the current G, once
-    exchange_ms = None
+    # static self-energy (eq. sigma_hf) from the current G, once each: K, J and F = H0 + J + K
+    exchange_ms = hartree_ms = fock_ms = None
     if not args.no_exchange:
         Kx = torch.zeros(blk.ctx.f_size, dtype=torch.complex128, device=dev)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        blk.ctx.exchange(blk.G, Kx)
-        ev0.record()
-        blk.ctx.exchange(blk.G, Kx)
-        ev1.record()
-        torch.cuda.synchronize()
-        exchange_ms = ev0.elapsed_time(ev1)
-        log(f"[bench] exchange (Sigma_HF, K term): {exchange_ms:.2f} ms")
+
+        def once(call):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            call()
+            ev0.record()
+            call()
+            ev1.record()
+            torch.cuda.synchronize()
+            return ev0.elapsed_time(ev1)
+
+        exchange_ms = once(lambda: blk.ctx.exchange(blk.G, Kx))
+        hartree_ms = once(lambda: blk.ctx.hartree(blk.G, Kx))
+        fock_ms = once(lambda: blk.ctx.fock(blk.F, blk.G, Kx))
+        log(f"[bench] Sigma_HF: exchange {exchange_ms:.2f} ms, Hartree {hartree_ms:.3f} ms, "
+            f"F = H0 + J + K {fock_ms:.2f} ms")
         del Kx
 
     # dominant kernel class by time; its bound follows from the algorithmic intensity
@@ -372,7 +379,7 @@ def main():
            "contraction_tflops": flops_iter / (contr_ms * 1e-3) / 1e12 if contr_ms > 0 else None,
            "algorithmic_flops_per_iteration": flops_iter,
            "profile_ms": {k: v[0] for k, v in prof.items()},
-           "exchange_ms": exchange_ms,
+           "exchange_ms": exchange_ms, "hartree_ms": hartree_ms, "fock_ms": fock_ms,
            "launch_plan": tuning, "launch_plan_source": getattr(blk.ctx, "plan_source", "default"),
            "launch_plan_s": tune_s,
            "kernels": kernels,

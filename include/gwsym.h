@@ -216,11 +216,27 @@ int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, cons
 /* eq. sigma_hf, exchange term: K^k = -(1/Nk) sum_{k'} sum_Q V^{k,k'}(Q) gamma^{k'} V^{k',k}(Q)
  * with the density matrix gamma^k = G^k(0^-) = -G^k(beta), taken from the last tau point of
  * G_blk (device, G layout).  Writes K_blk (device) in the F layout: block-packed, one matrix
- * per irreducible point ("f_off").  Spin-diagonal, so no spin factor.  The Hartree term J and
- * the update of F are not computed (F stays as given).  GWSYM_FP64 only (GWSYM_EINVAL in the
+ * per irreducible point ("f_off").  Spin-diagonal, so no spin factor.  F is not updated by
+ * this call: the caller forms F = H0 + J + K.  GWSYM_FP64 only (GWSYM_EINVAL in the
  * reduced-precision modes, which keep only FP32 copies of V).  Uses the contraction
  * workspaces: not concurrent with the other calls of this context. */
 int gwsym_exchange(gwsym_ctx* ctx, const void* G_blk, void* K_blk, void* stream);
+
+/* eq. sigma_hf, Hartree term: J^k = (s/Nk) sum_Q V^{k,k}(Q) rho(Q) with the density on the
+ * auxiliary functions rho(Q) = sum_{k'} Tr[gamma^{k'} V^{k',k'}(Q)] over the whole zone,
+ * gamma^k = -G^k(beta) from the last tau point of G_blk (device, G layout), s the spin factor
+ * of the parameters (the equation's spin sum).  Needs V^{k,k}(Q) Hermitian in the orbital
+ * indices (as the pairing V^{k',k} = V^{k,k'}^H of gwsym_load_V implies).  Writes J_blk
+ * (device, F layout).  GWSYM_FP64 only (GWSYM_EINVAL otherwise).  Uses two small buffers of
+ * the context: not concurrent with other calls of this context. */
+int gwsym_hartree(gwsym_ctx* ctx, const void* G_blk, void* J_blk, void* stream);
+
+/* The one-body matrix of the self-consistent loop (eq. sigma_hf with eq. dyson):
+ * F = H0 + J + K, J and K as gwsym_hartree and gwsym_exchange compute them from the density
+ * matrix of G_blk.  H0_blk (the non-interacting one-body matrix), G_blk and F_blk are device
+ * buffers (F layout, G layout, F layout); F_blk must not alias H0_blk or G_blk (GWSYM_EINVAL).
+ * Pass F_blk to the next gwsym_iteration / gwsym_dyson_G.  GWSYM_FP64 only. */
+int gwsym_fock(gwsym_ctx* ctx, const void* H0_blk, const void* G_blk, void* F_blk, void* stream);
 
 /* One GW iteration in the order of Alg. 2: polarization(G) -> screened interaction ->
  * self-energy(G, P) -> (find_mu when n_target > 0, else mu is read as given) -> dyson_G,

@@ -277,6 +277,21 @@ int gwsym_exchange(gwsym_ctx* ctx, const void* G_blk, void* K_blk, void* stream)
   return device_exchange(ctx->c, G_blk, K_blk, stream);
 }
 
+int gwsym_hartree(gwsym_ctx* ctx, const void* G_blk, void* J_blk, void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");
+  NEED(G_blk && J_blk, GWSYM_EINVAL, "NULL buffer");
+  return device_hartree(ctx->c, G_blk, J_blk, nullptr, 0, stream);
+}
+
+int gwsym_fock(gwsym_ctx* ctx, const void* H0_blk, const void* G_blk, void* F_blk, void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");
+  NEED(H0_blk && G_blk && F_blk, GWSYM_EINVAL, "NULL buffer");
+  NEED(F_blk != H0_blk && F_blk != G_blk, GWSYM_EINVAL, "F_blk must not alias H0_blk or G_blk");
+  return device_fock(ctx->c, H0_blk, G_blk, F_blk, stream);
+}
+
 int gwsym_autotune(gwsym_ctx* ctx, void* stream, gwsym_tuning* out) {
   if (!ctx) return GWSYM_EINVAL;
   NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");

@@ -167,6 +167,8 @@ int device_g0(Ctx& c, const void* F, double mu, void* G, double* nfree, void* st
 int device_polarization(Ctx& c, const void* G, void* P0, void* stream);
 int device_screened(Ctx& c, const void* P0, void* P, void* stream);
 int device_exchange(Ctx& c, const void* G, void* K, void* stream);
+int device_hartree(Ctx& c, const void* G, void* J, const void* add, int accumulate, void* stream);
+int device_fock(Ctx& c, const void* H0, const void* G, void* F, void* stream);
 int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stream);
 int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double* mu, void* stream);
 int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream);

@@ -58,6 +58,14 @@ struct CopySeg {
 
 enum { INV_P = 0, INV_G = 1, INV_TRACE = 2 };
 
+// One diagonal orbital block of one irreducible point for the Hartree term: the block's
+// first function and size in the block basis, the block of G(beta) it pairs with, the
+// diagonal pair V_S^{k0,k0} it reads and where the block of J goes in the F layout.
+struct HartreeItem {
+  int off, n;
+  int64_t g_off, v_off, f_off;
+};
+
 struct InvItem {
   int n, xbuf, fbuf, outbuf;
   int64_t x_off, f_off, out_off;
@@ -93,6 +101,9 @@ void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStrea
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s);
+void launch_hartree(const void* items, const int* first, int nib, int nitems, const double* w, const void* proj,
+                    int naux, int nao, void* rpart, void* rho, const void* add, int accumulate, const Bases& b,
+                    hipStream_t s);
 // nmax: largest matrix among the items
 void launch_inverse(const void* items, int nitems, int nmax, const Bases& b, int mode, const double* mu,
                     double* trace, int* status, hipStream_t s);

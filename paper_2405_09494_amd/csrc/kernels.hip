@@ -1360,6 +1360,104 @@ void launch_inverse(const void* items, int nitems, int nmax, const Bases& b, int
 }
 
 // ----------------------------------------------------------------------------
+// Hartree term of the static self-energy (eq. sigma_hf, J).  Three small launches over the
+// diagonal pairs V_S^{k0,k0}(s) (block basis, q = 0):
+//   R[i][s]  = sum over the diagonal blocks of G^{k0}(beta)_ab conj(V_S^{k0,k0}(s)_ab)
+//   rho[s]   = sum_s' Pi[s][s'] sum_i w_i R[i][s']   (Pi: projector onto the invariant
+//              auxiliary functions; w_i folds -1 from gamma = -G(beta), s/Nk and |star|)
+//   J^{k0}   = sum_s V_S^{k0,k0}(s) rho[s] on the diagonal blocks, into the F layout.
+// All reductions run in a fixed order (no atomics).
+
+__device__ inline double2 block_sum256(double2 v, double2* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// grid (naux, nib): one workgroup per (s, irreducible point)
+__global__ __launch_bounds__(256) void k_hartree_rho(const HartreeItem* __restrict__ items,
+                                                     const int* __restrict__ first, Bases bases, int naux, int nao,
+                                                     double2* __restrict__ R) {
+  __shared__ double2 red[256];
+  const int sx = blockIdx.x, i = blockIdx.y;
+  const double2* VS = reinterpret_cast<const double2*>(bases.p[B_VS]);
+  const double2* G = reinterpret_cast<const double2*>(bases.p[B_G]);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int t = first[i]; t < first[i + 1]; ++t) {
+    const HartreeItem it = items[t];
+    const double2* v = VS + it.v_off + int64_t(sx) * nao * nao;
+    const double2* g = G + it.g_off;
+    for (int e = threadIdx.x; e < it.n * it.n; e += 256) {
+      const int a = it.off + e / it.n, b = it.off + e % it.n;
+      acc = cadd(acc, cmul(g[e], cconj(v[a * nao + b])));
+    }
+  }
+  const double2 r = block_sum256(acc, red);
+  if (threadIdx.x == 0) R[int64_t(i) * naux + sx] = r;
+}
+
+// grid ceil(naux / 4): one wave per auxiliary function s
+__global__ __launch_bounds__(256) void k_hartree_mix(const double2* __restrict__ R, const double* __restrict__ w,
+                                                     int nib, const double2* __restrict__ proj, int naux,
+                                                     double2* __restrict__ rho) {
+  const int lane = threadIdx.x & 63;
+  const int sx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (sx >= naux) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int t = lane; t < naux; t += 64) {
+    double2 m = make_double2(0.0, 0.0);
+    for (int i = 0; i < nib; ++i) {
+      const double2 r = R[int64_t(i) * naux + t];
+      m.x += w[i] * r.x;
+      m.y += w[i] * r.y;
+    }
+    acc = cadd(acc, cmul(proj[int64_t(sx) * naux + t], m));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o, 64);
+    acc.y += __shfl_xor(acc.y, o, 64);
+  }
+  if (lane == 0) rho[sx] = acc;
+}
+
+// grid (nitems): one workgroup per diagonal block.  With add != null the output is
+// J + add (+ the output's previous value when accumulate != 0), for F = H0 + J + K.
+__global__ __launch_bounds__(256) void k_hartree_j(const HartreeItem* __restrict__ items, Bases bases, int naux,
+                                                   int nao, const double2* __restrict__ rho,
+                                                   const double2* __restrict__ add, int accumulate) {
+  const HartreeItem it = items[blockIdx.x];
+  const double2* VS = reinterpret_cast<const double2*>(bases.p[B_VS]) + it.v_off;
+  double2* J = reinterpret_cast<double2*>(bases.p[B_OUT]) + it.f_off;
+  const int64_t slab = int64_t(nao) * nao;
+  for (int e = threadIdx.x; e < it.n * it.n; e += 256) {
+    const int a = it.off + e / it.n, b = it.off + e % it.n;
+    const double2* v = VS + a * nao + b;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int sx = 0; sx < naux; ++sx) acc = cadd(acc, cmul(v[sx * slab], rho[sx]));
+    if (add) acc = cadd(acc, add[it.f_off + e]);
+    if (accumulate) acc = cadd(acc, J[e]);
+    J[e] = acc;
+  }
+}
+
+void launch_hartree(const void* items, const int* first, int nib, int nitems, const double* w, const void* proj,
+                    int naux, int nao, void* rpart, void* rho, const void* add, int accumulate, const Bases& b,
+                    hipStream_t s) {
+  if (nib == 0 || nitems == 0 || naux == 0) return;
+  const HartreeItem* it = static_cast<const HartreeItem*>(items);
+  hipLaunchKernelGGL(k_hartree_rho, dim3(naux, nib), dim3(256), 0, s, it, first, b, naux, nao,
+                     static_cast<double2*>(rpart));
+  hipLaunchKernelGGL(k_hartree_mix, dim3((naux + 3) / 4), dim3(256), 0, s, static_cast<const double2*>(rpart), w,
+                     nib, static_cast<const double2*>(proj), naux, static_cast<double2*>(rho));
+  hipLaunchKernelGGL(k_hartree_j, dim3(nitems), dim3(256), 0, s, it, b, naux, nao, static_cast<const double2*>(rho),
+                     static_cast<const double2*>(add), accumulate);
+}
+
+// ----------------------------------------------------------------------------
 // Chemical potential bisection (one workgroup): N(mu) from the traces of G(i w_n) at the
 // current mu, then the bracket update.  state = [lo, hi, mu].
 

@@ -313,6 +313,15 @@ struct DevState {
   GemmStage hx_gemm;
   RowStage hx_right;
   ListStage<CopySeg> hx_pack;
+  // Hartree part (eq. sigma_hf, J term): diagonal blocks, per-point item ranges, weights,
+  // the invariant-subspace projector of the auxiliary basis at q = 0 and two small buffers
+  void* hj_items = nullptr;
+  int* hj_first = nullptr;
+  double* hj_w = nullptr;
+  void* hj_proj = nullptr;
+  void* hj_r = nullptr;
+  void* hj_rho = nullptr;
+  int hj_nitems = 0;
   ListStage<CopySeg> p0_mirror, scr_herm, dys_herm, s_pack;
   void* SCR = nullptr;      // full nao x nao self-energy products of one tau chunk
   ListStage<InvItem> scr_inv, dys_inv, mu_inv;
@@ -801,6 +810,54 @@ int device_init(Ctx& c, void* stream) {
     if ((st = upload(c, d, d.hx_pack.items, &d.hx_pack.d, s))) return st;
   }
 
+  // ---------------- Hartree (eq. sigma_hf, J term) ----------------
+  // rho = sum over the whole zone of Tr[gamma^{k'} V^{k'k'}(Q)].  Only the irreducible points
+  // hold V^{k'k'}: a star's points add the rotated copies of the representative's density,
+  // whose sum is |star| times its projection onto the invariant auxiliary functions.
+  {
+    Mesh mesh{c.n};
+    std::vector<HartreeItem> items;
+    std::vector<int> first(size_t(nib) + 1, 0);
+    std::vector<double> w(size_t(nib), 0.0);
+    for (int k = 0; k < nk; ++k) w[size_t(c.rep[k])] += 1.0;
+    for (int i = 0; i < nib; ++i) {
+      w[size_t(i)] *= -c.prm.spin / nk;   // gamma = -G(beta); s/Nk; star size
+      const Blocks& BO = c.bao[i];
+      first[size_t(i)] = int(items.size());
+      for (size_t rb = 0; rb < BO.size.size(); ++rb)
+        items.push_back({BO.off[rb], BO.size[rb], c.g_off[i] + i64(nt - 1) * BO.packed + BO.poff[rb],
+                         (i64(i) * nk + c.ibz[i]) * na * no * no, c.f_off[i] + BO.poff[rb]});
+    }
+    first[size_t(nib)] = int(items.size());
+    d.hj_nitems = int(items.size());
+    // V_S(s) = sum_Q U_{Qs} V(Q), so a density vector maps as rho_s = (U^H rho)_s and the
+    // projector (1/|G|) sum_g Obar(g) becomes U^H Pi U
+    const int kg = mesh.sub(c.ibz[0], c.ibz[0]);
+    CMat Pi(na, na);
+    for (int a = 0; a < c.nop; ++a) {
+      const CMat O = orbital_rep(c, true, a, kg);
+      for (size_t e = 0; e < Pi.a.size(); ++e) Pi.a[e] += O.a[e] / double(c.nop);
+    }
+    const CMat P2 = matmul(Pi, Pi);
+    double dev2 = 0;
+    for (size_t e = 0; e < Pi.a.size(); ++e) dev2 = std::max(dev2, std::abs(P2.a[e] - Pi.a[e]));
+    if (dev2 > 1e-10) {
+      c.err = "the auxiliary representation at q = 0 does not average to a projector";
+      return GWSYM_EINVAL;
+    }
+    const CMat Ps = matmul(adjoint(c.U_aux[kg]), matmul(Pi, c.U_aux[kg]));
+    if ((st = upload(c, d, items, &d.hj_items, s))) return st;
+    void* fp = nullptr;
+    if ((st = upload(c, d, first, &fp, s))) return st;
+    d.hj_first = static_cast<int*>(fp);
+    void* wp = nullptr;
+    if ((st = upload(c, d, w, &wp, s))) return st;
+    d.hj_w = static_cast<double*>(wp);
+    if ((st = upload(c, d, Ps.a, &d.hj_proj, s))) return st;
+    if ((st = dalloc(c, d, &d.hj_r, size_t(nib) * na * 16))) return st;
+    if ((st = dalloc(c, d, &d.hj_rho, size_t(na) * 16))) return st;
+  }
+
   // ---------------- screened interaction (eq. P02P) ----------------
   for (int i = 0; i < nib; ++i) {
     const Blocks& B = c.baux[i];
@@ -1286,6 +1343,31 @@ int device_exchange(Ctx& c, const void* G, void* K, void* stream) {
   }
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
+}
+
+int device_hartree(Ctx& c, const void* G, void* J, const void* add, int accumulate, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  if (c.prm.precision != GWSYM_FP64) {
+    c.err = "the Hartree term is computed in FP64 only (the reduced modes keep FP32 copies of V)";
+    return GWSYM_EINVAL;
+  }
+  Bases b = bases_of(d);
+  b.p[B_G] = const_cast<void*>(G);
+  b.p[B_OUT] = J;
+  timed(d, s, PC_OTHER, 0, [&] {
+    launch_hartree(d.hj_items, d.hj_first, c.nibz, d.hj_nitems, d.hj_w, d.hj_proj, c.naux, c.nao, d.hj_r, d.hj_rho,
+                   add, accumulate, b, s);
+  });
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+// F = H0 + J + K (eq. sigma_hf): the exchange term written into F, then J and H0 added
+int device_fock(Ctx& c, const void* H0, const void* G, void* F, void* stream) {
+  int st;
+  if ((st = device_exchange(c, G, F, stream))) return st;
+  return device_hartree(c, G, F, H0, 1, stream);
 }
 
 int device_screened(Ctx& c, const void* P0, void* P, void* stream) {

@@ -81,6 +81,8 @@ lib.gwsym_find_mu.argtypes = [_vp, _vp, _vp, C.c_double, _vp, _vp]
 lib.gwsym_dyson_G.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 lib.gwsym_iteration.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int, _vp]
 lib.gwsym_exchange.argtypes = [_vp, _vp, _vp, _vp]
+lib.gwsym_hartree.argtypes = [_vp, _vp, _vp, _vp]
+lib.gwsym_fock.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.gwsym_autotune.argtypes = [_vp, _vp, C.POINTER(Tuning)]
 lib.gwsym_get_tuning.argtypes = [_vp, C.POINTER(Tuning)]
 lib.gwsym_set_tuning.argtypes = [_vp, C.POINTER(Tuning), _vp]
@@ -92,7 +94,7 @@ lib.gwsym_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int
 EXPORTED = ["gwsym_create", "gwsym_destroy", "gwsym_last_error", "gwsym_build_symmetry_basis",
             "gwsym_table_size", "gwsym_get", "gwsym_device_init", "gwsym_load_V", "gwsym_to_block",
             "gwsym_from_block", "gwsym_g0", "gwsym_polarization", "gwsym_screened_interaction",
-            "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_exchange",
+            "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_exchange", "gwsym_hartree", "gwsym_fock",
             "gwsym_autotune",
             "gwsym_get_tuning", "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read"]
 
@@ -238,6 +240,12 @@ class Context:
 
     def exchange(self, G_blk, K_blk, stream=None):
         self._check(lib.gwsym_exchange(self.h, _ptr(G_blk), _ptr(K_blk), _stream(stream)))
+
+    def hartree(self, G_blk, J_blk, stream=None):
+        self._check(lib.gwsym_hartree(self.h, _ptr(G_blk), _ptr(J_blk), _stream(stream)))
+
+    def fock(self, H0_blk, G_blk, F_blk, stream=None):
+        self._check(lib.gwsym_fock(self.h, _ptr(H0_blk), _ptr(G_blk), _ptr(F_blk), _stream(stream)))
 
     def iteration(self, F_blk, G_blk, P0_blk, P_blk, S_blk, mu, n_target=0.0, use_graph=False, stream=None):
         self._check(lib.gwsym_iteration(self.h, _ptr(F_blk), _ptr(G_blk), _ptr(P0_blk), _ptr(P_blk), _ptr(S_blk),

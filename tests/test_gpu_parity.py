@@ -7,7 +7,8 @@ import pytest
 import torch
 
 from tests.gpu_common import DeviceRun, inputs, oracle_run, say
-from tests.helpers import rel
+from gwinputs import add_k
+from tests.helpers import rel, sub_table
 
 pytestmark = pytest.mark.gpu
 
@@ -244,6 +245,102 @@ def test_exchange_after_iteration():
     e = rel(run.full(0, K), oracle.exchange(ref["iters"][0]["G"], V))
     say(f"  K {e:.2e}")
     assert e < TOL
+
+
+@pytest.mark.parametrize("name,mode", [("cfg0", "full"), ("cfg0", "block"), ("small_rocksalt", "block"),
+                                       ("small_rocksalt", "rotate"), ("small_diamond", "block"),
+                                       ("wide_diamond", "block"), ("gamma_sc", "block")])
+def test_hartree(name, mode):
+    """Hartree part of the static self-energy (eq. sigma_hf) from the free G0, against the
+    oracle's sum over the whole zone, after from_block at every k."""
+    import oracle
+    say(f"[hartree] {name} {mode}")
+    run = DeviceRun(name, MODES[mode])
+    run.g0()
+    J = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    run.ctx.hartree(run.G, J)
+    wl, inp, F, V = inputs(name)
+    e = rel(run.full(0, J), oracle.hartree(oracle_run(name)["G0"], V, wl.spin))
+    say(f"  J {e:.2e}")
+    assert e < TOL
+
+
+def test_hartree_after_iteration():
+    """The same from the Green's function one iteration later (interacting density matrix)."""
+    import oracle
+    say("[hartree after iteration] small_diamond block")
+    run = DeviceRun("small_diamond", MODES["block"])
+    ref = oracle_run("small_diamond")
+    run.g0()
+    run.iteration(ref["n_target"])
+    J = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    run.ctx.hartree(run.G, J)
+    wl, inp, F, V = inputs("small_diamond")
+    e = rel(run.full(0, J), oracle.hartree(ref["iters"][0]["G"], V, wl.spin))
+    say(f"  J {e:.2e}")
+    assert e < TOL
+
+
+def test_hartree_fp64_only():
+    from paper_2405_09494_amd import gwsym
+    run = DeviceRun("small_rocksalt", MODES["block"], precision=1)
+    J = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    with pytest.raises(gwsym.GwsymError, match="EINVAL"):
+        run.ctx.hartree(run.G, J)
+
+
+@pytest.mark.parametrize("name,mode", [("cfg0", "block"), ("small_rocksalt", "rotate"), ("small_diamond", "block"),
+                                       ("gamma_sc", "block")])
+def test_fock(name, mode):
+    """F = H0 + J + K from the free G0 against the oracle's three terms."""
+    import oracle
+    say(f"[fock] {name} {mode}")
+    run = DeviceRun(name, MODES[mode])
+    run.g0()
+    F1 = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    run.ctx.fock(run.F, run.G, F1)
+    wl, inp, F, V = inputs(name)
+    G0 = oracle_run(name)["G0"]
+    e = rel(run.full(0, F1), F + oracle.hartree(G0, V, wl.spin) + oracle.exchange(G0, V))
+    say(f"  F {e:.2e}")
+    assert e < TOL
+
+
+@pytest.mark.parametrize("name", ["small_diamond", "gamma_sc"])
+def test_self_consistent_step_with_fock_update(name):
+    """Two iterations of the self-consistent loop: G1 from F = H0, then F1 = H0 + J[G1] + K[G1]
+    and a second iteration with F1, against the oracle doing the same."""
+    import oracle
+    say(f"[scgw with F update] {name} block")
+    wl, inp, F, V = inputs(name)
+    ref = oracle_run(name)
+    r1 = ref["iters"][0]
+    G1, mu1, nt = r1["G"], r1["mu"], ref["n_target"]
+    F1_ref = F + oracle.hartree(G1, V, wl.spin) + oracle.exchange(G1, V)
+    r2 = oracle.gw_iteration(F1_ref, V, G1, mu1, wl.beta, wl.nw, wl.spin, add_k(wl.n), sub_table(wl.n),
+                             n_target=nt)
+    run = DeviceRun(name, MODES["block"])
+    run.g0()
+    run.iteration(nt)
+    F1 = torch.zeros(run.ctx.f_size, dtype=torch.complex128, device=run.dev)
+    run.ctx.fock(run.F, run.G, F1)
+    eF = rel(run.full(0, F1), F1_ref)
+    # the bracket of the chemical-potential search comes from the spectrum of the last g0 call
+    scratch = torch.zeros(run.ctx.g_size, dtype=torch.complex128, device=run.dev)
+    run.ctx.g0(F1, 0.0, scratch, run.nfree)
+    run.F = F1
+    run.iteration(nt)
+    eG = rel(run.full(1, run.G), r2["G"])
+    emu = abs(run.mu.item() - r2["mu"])
+    say(f"  F1 {eF:.2e}  G2 {eG:.2e}  mu2 {emu:.2e}")
+    assert eF < TOL and eG < TOL and emu < 1e-10
+
+
+def test_fock_rejects_aliasing():
+    from paper_2405_09494_amd import gwsym
+    run = DeviceRun("small_rocksalt", MODES["block"])
+    with pytest.raises(gwsym.GwsymError, match="EINVAL"):
+        run.ctx.fock(run.F, run.G, run.F)
 
 
 def test_exchange_fp64_only():
