@@ -91,7 +91,7 @@ void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s);
 // gmax: largest packed block-diagonal factor (sum of squared block sizes)
 void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, int gmax, hipStream_t s,
                            bool fp32 = false);
-void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, int gmax, hipStream_t s,
+void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s,
                           bool fp32);
 // Wave-tile complex GEMM over the same problem and tile lists (tiles of at most 32 x 32).
 // arith: 0 FP64 operands and MFMA; on float2 operands 1 FP32 MFMA, 2 three-piece and

@@ -901,10 +901,12 @@ __global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict
 // second factor with both Green's function blocks applied in one pass over the slab).  The
 // tile is at most 64 columns wide: lane = column, wave w = rows w, w + 4, ...; each Green's
 // function element is read once per lane and used for all of its rows, and the intermediate
-// stays in LDS.
-template <typename V2, bool GLDS, int RPW>
-__global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict__ segs, Bases bases,
-                                                       const int* __restrict__ btab, int n, int gmax) {
+// stays in LDS.  The Green's function blocks are read through the caches, not staged in LDS:
+// the smaller LDS footprint admits more workgroups per CU, which measured faster at nao 26
+// (7 waves per SIMD for the 8-row form, 17.9 ms against 21.0 ms per iteration with staging).
+template <typename V2, int RPW>
+__global__ __launch_bounds__(256, RPW <= 8 ? 7 : 1) void k_rowblock_both(const RowSeg* __restrict__ segs, Bases bases,
+                                                                      const int* __restrict__ btab, int n) {
   extern __shared__ double2 lds_rb[];
   const RowSeg sg = segs[blockIdx.y];
   const int nq = rbb_nq(n), w = nq * n;
@@ -915,22 +917,12 @@ __global__ __launch_bounds__(256) void k_rowblock_both(const RowSeg* __restrict_
   const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
   V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
   const V2* Gl = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
-  const V2* Gr = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off2;   // global or, below, LDS
+  const V2* Gr = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off2;
   const int* btl = btab + sg.blk;
   const int* btr = btab + sg.blk2;
-  V2* tile = reinterpret_cast<V2*>(lds_rb);   // n x w, then (GLDS) the packed blocks of Gl and Gr
+  V2* tile = reinterpret_cast<V2*>(lds_rb);   // n x w
   const int nbl = btl[0], nbr = btr[0];
-  int* info = reinterpret_cast<int*>(tile + n * w + (GLDS ? 2 * gmax : 0));   // per index: (off, size, poff) of its block
-  if (GLDS) {
-    V2* gl = tile + n * w;
-    V2* gr = gl + gmax;
-    const int szl = btl[3 * nbl] + btl[3 * nbl - 1] * btl[3 * nbl - 1];
-    const int szr = btr[3 * nbr] + btr[3 * nbr - 1] * btr[3 * nbr - 1];
-    for (int e = threadIdx.x; e < szl; e += 256) gl[e] = Gl[e];
-    for (int e = threadIdx.x; e < szr; e += 256) gr[e] = Gr[e];
-    Gl = gl;
-    Gr = gr;
-  }
+  int* info = reinterpret_cast<int*>(tile + n * w);   // per index: (off, size, poff) of its block
   for (int c = threadIdx.x; c < n; c += 256) {
     int bl = 0, br = 0;
     while (bl + 1 < nbl && c >= btl[1 + 3 * (bl + 1)]) ++bl;
@@ -1022,30 +1014,25 @@ void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab,
 }
 
 template <typename V2, int RPW>
-void launch_both_r(dim3 g, int n, int w, int gmax, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
+void launch_both_r(dim3 g, int n, int w, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
   const size_t ex = 6 * n * sizeof(int) + 16;
-  const size_t with = (size_t(n) * w + 2 * size_t(gmax)) * sizeof(V2) + ex;
-  if (with <= LDS_CAP)
-    hipLaunchKernelGGL((k_rowblock_both<V2, true, RPW>), g, dim3(256), with, s, sg, b, btab, n, gmax);
-  else
-    hipLaunchKernelGGL((k_rowblock_both<V2, false, RPW>), g, dim3(256), size_t(n) * w * sizeof(V2) + ex, s, sg, b,
-                       btab, n, gmax);
+  hipLaunchKernelGGL((k_rowblock_both<V2, RPW>), g, dim3(256), size_t(n) * w * sizeof(V2) + ex, s, sg, b, btab, n);
 }
 
 template <typename V2>
-void launch_both_t(dim3 g, int n, int w, int gmax, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
-  if (n <= 32) launch_both_r<V2, 8>(g, n, w, gmax, s, sg, b, btab);
-  else launch_both_r<V2, 16>(g, n, w, gmax, s, sg, b, btab);
+void launch_both_t(dim3 g, int n, int w, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
+  if (n <= 32) launch_both_r<V2, 8>(g, n, w, s, sg, b, btab);
+  else launch_both_r<V2, 16>(g, n, w, s, sg, b, btab);
 }
 
-void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, int gmax, hipStream_t s,
+void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s,
                           bool fp32) {
   if (l.nseg == 0) return;
   const int w = rbb_nq(n) * n;
   const dim3 g((l.maxrows + w - 1) / w, l.nseg);
   const RowSeg* sg = (const RowSeg*)l.segs;
-  if (fp32) launch_both_t<float2>(g, n, w, gmax, s, sg, b, btab);
-  else launch_both_t<double2>(g, n, w, gmax, s, sg, b, btab);
+  if (fp32) launch_both_t<float2>(g, n, w, s, sg, b, btab);
+  else launch_both_t<double2>(g, n, w, s, sg, b, btab);
 }
 
 // ----------------------------------------------------------------------------

@@ -1273,7 +1273,7 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
   for (size_t l = 0; l < d.p0_gemm.launches.size(); ++l) {
     const Range& rb = d.p0_both.launches[l];
     RowSegList L{static_cast<RowSeg*>(d.p0_both.d) + rb.t0, rb.nt, rb.r0};
-    timed(d, s, PC_LEFT, rb.macs, [&] { launch_rowblock_both(L, b, d.btab, c.nao, d.gmax, s, f32); }, rb.bytes);
+    timed(d, s, PC_LEFT, rb.macs, [&] { launch_rowblock_both(L, b, d.btab, c.nao, s, f32); }, rb.bytes);
     const Range& rg = d.p0_gemm.launches[l];
     timed(d, s, PC_P0, rg.macs, [&] { launch_wgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, arith, mask); }, rg.bytes);
   }
