@@ -6,4 +6,5 @@ benchmark's CPU-baseline leg, never by the library or its Python binding.
 from .gw import (tau_grid, matsubara, transform_matrices, to_freq, to_tau, fermi_factor_parts,
                  polarization_unit, self_energy_unit,
                  g0_closed_form, free_count, polarization, self_energy, screened, dyson,
-                 particle_number, find_mu, gw_iteration, exchange, hartree)
+                 particle_number, find_mu, gw_iteration, exchange, hartree,
+                 exchange_unit, hartree_unit)

@@ -230,6 +230,27 @@ def hartree(G: np.ndarray, V: np.ndarray, spin: float) -> np.ndarray:
     return (spin / nk) * J
 
 
+def exchange_unit(G: np.ndarray, Vrow: np.ndarray, Vcol: np.ndarray) -> np.ndarray:
+    """K^k of eq. sigma_hf at one k, from Vrow[k'] = V^{k,k'} and Vcol[k'] = V^{k',k} for every
+    k' (the full-size check cannot hold V over all pairs)."""
+    nk = G.shape[0]
+    gamma = -G[:, -1]
+    acc = np.zeros(G.shape[2:], dtype=complex)
+    for kp in range(nk):
+        acc += np.einsum("Qia,ab,Qbj->ij", Vrow[kp], gamma[kp], Vcol[kp], optimize=True)
+    return -acc / nk
+
+
+def hartree_unit(G: np.ndarray, Vdiag: np.ndarray, k: int, spin: float) -> np.ndarray:
+    """J^k of eq. sigma_hf at one k, from the diagonal pairs Vdiag[k'] = V^{k',k'}."""
+    nk = G.shape[0]
+    gamma = -G[:, -1]
+    rho = np.zeros(Vdiag.shape[1], dtype=complex)
+    for kp in range(nk):
+        rho += np.einsum("ab,Qba->Q", gamma[kp], Vdiag[kp])
+    return (spin / nk) * np.einsum("Q,Qij->ij", rho, Vdiag[k])
+
+
 # ----------------------------------------------------------------------------
 # screened interaction (eq. P02P) and Dyson equation (eq. dyson)
 

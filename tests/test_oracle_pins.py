@@ -484,3 +484,16 @@ def test_hartree_hermitian_positive_energy_and_symmetric(diamond_run):
     G1 = np.zeros_like(G0)
     G1[0] = G0[0] * inp.nk
     assert np.abs(oracle.hartree(G1, V, wl.spin) - J).max() > 1e-6 * scale
+
+
+def test_static_units_match_whole_zone(diamond_run):
+    """The one-k forms of K and J used by the full-size check equal the whole-zone forms."""
+    inp, V, G0, wl = diamond_run["inp"], diamond_run["V"], diamond_run["G0"], diamond_run["wl"]
+    K, J = oracle.exchange(G0, V), oracle.hartree(G0, V, wl.spin)
+    nk = inp.nk
+    Vdiag = np.stack([V[kp, kp] for kp in range(nk)])
+    for k in (0, 3, nk - 1):
+        Kk = oracle.exchange_unit(G0, V[k], V[:, k])
+        Jk = oracle.hartree_unit(G0, Vdiag, k, wl.spin)
+        assert np.abs(Kk - K[k]).max() < 1e-14 * np.abs(K).max()
+        assert np.abs(Jk - J[k]).max() < 1e-14 * np.abs(J).max()
