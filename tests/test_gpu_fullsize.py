@@ -37,10 +37,14 @@ def cfg1():
     pairs = [(int(ibz[i]), kp) for i in range(nib) for kp in range(nk)]
     pairs += [(kk, int(add[kk, q])) for kk in range(nk)]
     pairs += [(k, int(sub[k, qq])) for qq in range(nk)]
+    pairs += [(kp, k) for kp in range(nk)] + [(kp, kp) for kp in range(nk)]
     V = inp.three_index(pairs)
     Vibz = V[: nib * nk].reshape(nib, nk, *V.shape[1:]).contiguous()
     Vq = V[nib * nk: nib * nk + nk].cpu().numpy()
-    Vk = V[nib * nk + nk:].cpu().numpy()
+    Vk = V[nib * nk + nk: nib * nk + 2 * nk].cpu().numpy()
+    Vcol = V[nib * nk + 2 * nk: nib * nk + 3 * nk].cpu().numpy()     # V^{k',k}
+    Vdiag = V[nib * nk + 3 * nk:].cpu().numpy()                      # V^{k',k'}
+    Vrow = Vibz[2].cpu().numpy()                                     # V^{k,k'}, k = ibz[2]
     del V
     X = inp.aux_matrices(1)[:, 0]    # [nk, naux, naux], symmetric Hermitian stand-in for P(tau_js)
     tau = oracle.tau_grid(wl.beta, wl.ntau)
@@ -48,7 +52,11 @@ def cfg1():
     say("[full size] oracle outputs")
     ref_p0 = oracle.polarization_unit(G0, Vq, add, q, j, wl.spin)
     ref_s = oracle.self_energy_unit(G0, Vk, X.cpu().numpy(), sub, k, js)
-    return dict(wl=wl, dev=dev, F=F, Vibz=Vibz, X=X, ibz=ibz, q=q, j=j, k=k, js=js, ref_p0=ref_p0, ref_s=ref_s)
+    # F = H0 + J + K of eq. sigma_hf at k from the free G0
+    ref_f = (F[k].cpu().numpy() + oracle.hartree_unit(G0, Vdiag, k, wl.spin)
+             + oracle.exchange_unit(G0, Vrow, Vcol))
+    return dict(wl=wl, dev=dev, F=F, Vibz=Vibz, X=X, ibz=ibz, q=q, j=j, k=k, js=js, ref_p0=ref_p0, ref_s=ref_s,
+                ref_f=ref_f)
 
 
 def run(d, precision):
@@ -105,3 +113,26 @@ def test_cfg1_sampled_bf16x6(cfg1):
     e0, es = rel(p0, cfg1["ref_p0"]), rel(s, cfg1["ref_s"])
     say(f"  P0 {e0:.2e} Sigma {es:.2e}")
     assert e0 < 1e-6 and es < 1e-6
+
+
+def test_cfg1_static_self_energy_fp64(cfg1):
+    """F = H0 + J + K (eq. sigma_hf) at one irreducible k from the free G0, at full size."""
+    say("[full size] F = H0 + J + K")
+    d = cfg1
+    wl, dev = d["wl"], d["dev"]
+    ctx = make_context(wl)
+    ctx.device_init()
+    ctx.load_V(d["Vibz"])
+    z = lambda n: torch.zeros(n, dtype=torch.complex128, device=dev)
+    Fb, G, F1 = z(ctx.f_size), z(ctx.g_size), z(ctx.f_size)
+    ctx.to_block(0, d["F"][torch.as_tensor(d["ibz"], device=dev)].contiguous(), Fb)
+    ctx.g0(Fb, 0.0, G)
+    ctx.fock(Fb, G, F1)
+    no = wl.nao
+    full = torch.zeros(wl.nk * no * no, dtype=torch.complex128, device=dev)
+    ctx.from_block(0, F1, full)
+    torch.cuda.synchronize()
+    f = full.view(wl.nk, no, no)[d["k"]].cpu().numpy()
+    e = rel(f, d["ref_f"])
+    say(f"  F {e:.2e}")
+    assert e < 1e-10
