@@ -248,6 +248,17 @@ int gwsym_fock(gwsym_ctx* ctx, const void* H0_blk, const void* G_blk, void* F_bl
 int gwsym_iteration(gwsym_ctx* ctx, const void* F_blk, void* G_blk, void* P0_blk, void* P_blk, void* Sigma_blk,
                     double* mu, double n_target, int use_graph, void* stream);
 
+/* One iteration of the self-consistent loop (eq. dyson with eq. sigma_hf): first
+ * F_blk = H0_blk + J + K from the density matrix of G_blk (as gwsym_fock), then the steps of
+ * gwsym_iteration with that F, all from the same G.  H0_blk is the non-interacting one-body
+ * matrix (device, F layout); F_blk is written (device, F layout, must not alias H0_blk or
+ * G_blk).  The chemical-potential search brackets the root by the lowest and highest
+ * eigenvalue of the new F -/+ 20 Ha (the eigenvalues as gwsym_g0 computes them; that bracket
+ * then stays for later gwsym_find_mu calls).  use_graph as for gwsym_iteration (the F update is captured with the
+ * rest).  GWSYM_FP64 only (GWSYM_EINVAL otherwise). */
+int gwsym_scf_iteration(gwsym_ctx* ctx, const void* H0_blk, void* F_blk, void* G_blk, void* P0_blk, void* P_blk,
+                        void* Sigma_blk, double* mu, double n_target, int use_graph, void* stream);
+
 /* Launch plan of the contractions (eq. P0 and eq. sigma work lists).  Index 0 is the
  * polarization GEMM, 1 the self-energy auxiliary GEMM (P^T V), 2 the self-energy orbital
  * GEMM (on the diagonal blocks).  Every choice leaves the results unchanged up to rounding

@@ -254,7 +254,18 @@ int gwsym_iteration(gwsym_ctx* ctx, const void* F_blk, void* G_blk, void* P0_blk
   NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");
   NEED(F_blk && G_blk && P0_blk && P_blk && Sigma_blk && mu, GWSYM_EINVAL, "NULL buffer");
   NEED(!(use_graph && stream == nullptr), GWSYM_EINVAL, "graph capture needs a created stream");
-  return device_iteration(ctx->c, F_blk, G_blk, P0_blk, P_blk, Sigma_blk, mu, n_target, use_graph, stream);
+  return device_iteration(ctx->c, nullptr, F_blk, G_blk, P0_blk, P_blk, Sigma_blk, mu, n_target, use_graph, stream);
+}
+
+int gwsym_scf_iteration(gwsym_ctx* ctx, const void* H0_blk, void* F_blk, void* G_blk, void* P0_blk, void* P_blk,
+                        void* Sigma_blk, double* mu, double n_target, int use_graph, void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.vloaded, GWSYM_ESTATE, "gwsym_load_V must come first");
+  NEED(H0_blk && F_blk && G_blk && P0_blk && P_blk && Sigma_blk && mu, GWSYM_EINVAL, "NULL buffer");
+  NEED(F_blk != H0_blk && F_blk != G_blk, GWSYM_EINVAL, "F_blk must not alias H0_blk or G_blk");
+  NEED(ctx->c.prm.precision == GWSYM_FP64, GWSYM_EINVAL, "the F update is computed in FP64 only");
+  NEED(!(use_graph && stream == nullptr), GWSYM_EINVAL, "graph capture needs a created stream");
+  return device_iteration(ctx->c, H0_blk, F_blk, G_blk, P0_blk, P_blk, Sigma_blk, mu, n_target, use_graph, stream);
 }
 
 int gwsym_profile(gwsym_ctx* ctx, int enable) {

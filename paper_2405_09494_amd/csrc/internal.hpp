@@ -172,8 +172,8 @@ int device_fock(Ctx& c, const void* H0, const void* G, void* F, void* stream);
 int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stream);
 int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double* mu, void* stream);
 int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream);
-int device_iteration(Ctx& c, const void* F, void* G, void* P0, void* P, void* S, double* mu, double ntarget,
-                     int use_graph, void* stream);
+int device_iteration(Ctx& c, const void* H0, const void* F, void* G, void* P0, void* P, void* S, double* mu,
+                     double ntarget, int use_graph, void* stream);
 int device_profile(Ctx& c, int enable);
 int device_replan(Ctx& c, void* stream);
 int device_autotune(Ctx& c, void* stream);

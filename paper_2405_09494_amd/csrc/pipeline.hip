@@ -1436,12 +1436,23 @@ int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double*
   return GWSYM_OK;
 }
 
-int device_iteration(Ctx& c, const void* F, void* G, void* P0, void* P, void* S, double* mu, double ntarget,
-                     int use_graph, void* stream) {
+int device_iteration(Ctx& c, const void* H0, const void* F, void* G, void* P0, void* P, void* S, double* mu,
+                     double ntarget, int use_graph, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevState& d = *static_cast<DevState*>(c.dev_state);
+  if (H0 && d.ws_elems < size_t(c.g_off[c.nibz])) {
+    c.err = "workspace smaller than one Green's function";
+    return GWSYM_ESHAPE;
+  }
   auto body = [&]() -> int {
     int st;
+    // self-consistent form: F = H0 + J + K from the same G as the polarization and Sigma; the
+    // bracket of the mu search then comes from the spectrum of the new F (the block eigen-solver
+    // of g0, its free G written into the workspace, which the stages below overwrite)
+    if (H0) {
+      if ((st = device_fock(c, H0, G, const_cast<void*>(F), stream))) return st;
+      if ((st = device_g0(c, F, 0.0, d.W1, nullptr, stream))) return st;
+    }
     if ((st = device_polarization(c, G, P0, stream))) return st;
     if ((st = device_screened(c, P0, P, stream))) return st;
     if ((st = device_self_energy(c, G, P, S, stream))) return st;
@@ -1451,7 +1462,7 @@ int device_iteration(Ctx& c, const void* F, void* G, void* P0, void* P, void* S,
   if (!use_graph) return body();
   int st;
   if ((st = need_partials(c, d))) return st;   // no allocation may happen inside the capture
-  const std::vector<const void*> key{F, G, P0, P, S, mu, stream};
+  const std::vector<const void*> key{H0, F, G, P0, P, S, mu, stream};
   if (!d.graph_exec || key != d.graph_key || ntarget != d.graph_ntarget) {
     if (d.graph_exec) {
       hipGraphExecDestroy(d.graph_exec);

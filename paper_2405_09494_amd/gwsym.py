@@ -83,6 +83,7 @@ lib.gwsym_iteration.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C
 lib.gwsym_exchange.argtypes = [_vp, _vp, _vp, _vp]
 lib.gwsym_hartree.argtypes = [_vp, _vp, _vp, _vp]
 lib.gwsym_fock.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.gwsym_scf_iteration.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int, _vp]
 lib.gwsym_autotune.argtypes = [_vp, _vp, C.POINTER(Tuning)]
 lib.gwsym_get_tuning.argtypes = [_vp, C.POINTER(Tuning)]
 lib.gwsym_set_tuning.argtypes = [_vp, C.POINTER(Tuning), _vp]
@@ -94,9 +95,9 @@ lib.gwsym_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int
 EXPORTED = ["gwsym_create", "gwsym_destroy", "gwsym_last_error", "gwsym_build_symmetry_basis",
             "gwsym_table_size", "gwsym_get", "gwsym_device_init", "gwsym_load_V", "gwsym_to_block",
             "gwsym_from_block", "gwsym_g0", "gwsym_polarization", "gwsym_screened_interaction",
-            "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_exchange", "gwsym_hartree", "gwsym_fock",
-            "gwsym_autotune",
-            "gwsym_get_tuning", "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read"]
+            "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_exchange",
+            "gwsym_hartree", "gwsym_fock", "gwsym_scf_iteration", "gwsym_autotune", "gwsym_get_tuning",
+            "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read"]
 
 PROFILE_CLASSES = ["p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction", "row_block_multiply",
                    "two_sided_block_multiply", "transforms", "inverses", "other"]
@@ -246,6 +247,12 @@ class Context:
 
     def fock(self, H0_blk, G_blk, F_blk, stream=None):
         self._check(lib.gwsym_fock(self.h, _ptr(H0_blk), _ptr(G_blk), _ptr(F_blk), _stream(stream)))
+
+    def scf_iteration(self, H0_blk, F_blk, G_blk, P0_blk, P_blk, S_blk, mu, n_target=0.0, use_graph=False,
+                      stream=None):
+        self._check(lib.gwsym_scf_iteration(self.h, _ptr(H0_blk), _ptr(F_blk), _ptr(G_blk), _ptr(P0_blk),
+                                            _ptr(P_blk), _ptr(S_blk), _ptr(mu), float(n_target or 0.0),
+                                            int(bool(use_graph)), _stream(stream)))
 
     def iteration(self, F_blk, G_blk, P0_blk, P_blk, S_blk, mu, n_target=0.0, use_graph=False, stream=None):
         self._check(lib.gwsym_iteration(self.h, _ptr(F_blk), _ptr(G_blk), _ptr(P0_blk), _ptr(P_blk), _ptr(S_blk),
