@@ -9,7 +9,9 @@
  *   polarization          P0^q(tau)  (eq. P0, Alg. 3)
  *   screened_interaction  P^q = [I - P0^q]^{-1} P0^q at bosonic frequencies (eq. P02P)
  *   self_energy           Sigma~^k(tau)  (eq. sigma, Alg. 4)
- *   find_mu, dyson_G      G^k(i w_n) = [(i w_n + mu) S - H0 - Sigma(i w_n)]^{-1} (eq. dyson), N_e fixed
+ *   find_mu, dyson_G      G^k(i w_n) = [(i w_n + mu) S - F - Sigma(i w_n)]^{-1} (eq. dyson), N_e fixed
+ *   exchange, hartree     K^k and J^k of the static self-energy (eq. sigma_hf)
+ *   fock, scf_iteration   F = H0 + J + K, alone or as the first step of each iteration
  *
  * Conventions
  *   - Complex numbers are interleaved (re, im) IEEE doubles (C99 double _Complex layout).
