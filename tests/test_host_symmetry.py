@@ -210,6 +210,20 @@ def test_tuning_defaults_and_state_errors():
         gwsym.Context(10.0, 8, 17, precision=4)
 
 
+def test_static_self_energy_state_errors():
+    """The Hartree-Fock calls and the self-consistent iteration need V on the device: before
+    load_V they fail with ESTATE, before any HIP call (dummy host addresses are never read)."""
+    from paper_2405_09494_amd import gwsym
+    ctx = gwsym.Context(10.0, 8, 17)
+    a, b, c, d, e, f, mu = 0x1000, 0x2000, 0x3000, 0x4000, 0x5000, 0x6000, 0x7000
+    calls = [lambda: ctx.exchange(a, b, stream=0), lambda: ctx.hartree(a, b, stream=0),
+             lambda: ctx.fock(a, b, c, stream=0),
+             lambda: ctx.scf_iteration(a, b, c, d, e, f, mu, stream=0)]
+    for call in calls:
+        with pytest.raises(gwsym.GwsymError, match="ESTATE"):
+            call()
+
+
 def test_pairwise_inputs_are_symmetric():
     """The pair-keyed draws of the 6^3 workloads (checked on a 2^3 diamond mesh) give the same
     symmetries as the row-keyed ones: Hermitian pairing, time reversal, and invariance under
