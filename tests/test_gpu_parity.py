@@ -215,7 +215,7 @@ def test_graph_iteration(name):
 
 @pytest.mark.parametrize("name,mode", [("cfg0", "full"), ("cfg0", "block"), ("small_rocksalt", "block"),
                                        ("small_rocksalt", "rotate"), ("small_diamond", "block"),
-                                       ("wide_diamond", "block"), ("gamma_sc", "block")])
+                                       ("wide_diamond", "block"), ("wide_rocksalt", "block"), ("gamma_sc", "block")])
 def test_exchange(name, mode):
     """Exchange part of the static self-energy (eq. sigma_hf) from the free G0, against the
     oracle, after from_block at every k."""
@@ -249,7 +249,7 @@ def test_exchange_after_iteration():
 
 @pytest.mark.parametrize("name,mode", [("cfg0", "full"), ("cfg0", "block"), ("small_rocksalt", "block"),
                                        ("small_rocksalt", "rotate"), ("small_diamond", "block"),
-                                       ("wide_diamond", "block"), ("gamma_sc", "block")])
+                                       ("wide_diamond", "block"), ("wide_rocksalt", "block"), ("gamma_sc", "block")])
 def test_hartree(name, mode):
     """Hartree part of the static self-energy (eq. sigma_hf) from the free G0, against the
     oracle's sum over the whole zone, after from_block at every k."""
@@ -336,7 +336,7 @@ def test_self_consistent_step_with_fock_update(name):
     assert eF < TOL and eG < TOL and emu < 1e-10
 
 
-@pytest.mark.parametrize("name", ["small_diamond", "gamma_sc"])
+@pytest.mark.parametrize("name", ["small_diamond", "gamma_sc", "wide_rocksalt"])
 def test_scf_iteration(name):
     """Two iterations of gwsym_scf_iteration (F = H0 + J + K, then P0 -> P -> Sigma -> mu ->
     Dyson, all from the same G) against the oracle doing the same steps."""
