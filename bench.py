@@ -4,11 +4,16 @@
 A step is one GW iteration of the hot path: P0 contraction, screened interaction
 (tau -> i Omega, per-block Dyson, back), Sigma contraction, chemical-potential bisection
 and the Dyson equation for G, in the irreducible wedge and isotypic blocks (FP64).  The
-same iteration is also timed without any symmetry (every k point, full matrices, same
-kernels) for comparison.  Inputs are seeded synthetic tensors of the workload's shapes,
-resident in HBM before the timed region.
+default workload is the largest single-GPU one: diamond Fd-3m on a 6x6x6 mesh, nao 52,
+naux 300, ntau 128 ("cfg4").  Inputs are seeded synthetic tensors of the workload's shapes,
+resident in HBM before the timed region; each timed iteration is one replay of a HIP graph.
 
-    python bench.py [--steps K] [--warmup W] [--workload cfg1] [--no-full] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload cfg4] [--legs fp32,bf16x6,full,unbatched]
+                    [--no-cpu]
+
+--legs adds comparison runs that are not part of the headline: the same block path with
+reduced-precision contractions, the full-matrix form without symmetry (all-pair V, so cfg0 and
+cfg1 only), and the unbatched per-block schedule.
 """
 from __future__ import annotations
 
@@ -27,10 +32,8 @@ METRIC = "s/GW iteration + contraction TFLOP/s, block-grouped vs full FP64, at â
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop per byte where the two bounds meet
-VALU_CLASSES = ("row_block_multiply", "two_sided_block_multiply")
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cfg1.md")
 PLANS_FILE = os.path.join(ROOT, "paper_2405_09494_amd", "plans.json")
 CRYSTAL_NAMES = {"sc": "simple cubic Pm-3m", "rocksalt": "rocksalt Fm-3m (two atoms)",
                  "diamond": "diamond Fd-3m (two atoms, non-symmorphic)"}
@@ -41,7 +44,7 @@ def source_digest():
     counters apply only to the code and plans they were taken from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("csrc/kernels.hip", "csrc/pipeline.hip", "plans.json"):
+    for f in ("csrc/kernels.hip", "csrc/bdiag.hip", "csrc/pipeline.hip", "plans.json"):
         path = os.path.join(ROOT, "paper_2405_09494_amd", f)
         if os.path.exists(path):
             with open(path, "rb") as fh:
@@ -49,11 +52,12 @@ def source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(cls):
+def measured_traffic(workload, cls):
     """HBM bytes per launch of a kernel class from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when that summary was taken from other kernel sources."""
+    WRITE_SIZE summary of the workload, or None when there is none or it was taken from other
+    kernel sources."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")).read()
     except OSError:
         return None
     digest = None
@@ -72,17 +76,21 @@ def measured_traffic(cls):
     return None
 
 
+CONTRACTIONS = {"polarization (eq. P0)": ("p0_contraction", "two_sided_block_multiply"),
+                "self-energy (eq. sigma)": ("sigma_aux_contraction", "row_block_multiply", "sigma_orb_contraction")}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_ctx(wl, mode, half_tau=True, tau_chunk=0, precision=0):
+def make_ctx(wl, mode, half_tau=True, tau_chunk=0, precision=0, sched=0):
     from gwinputs import crystal
     from paper_2405_09494_amd import gwsym
     cr = crystal(wl.crystal)
     rot = np.array([W for W, _ in cr.ops])
     trans = np.array([w for _, w in cr.ops])
-    ctx = gwsym.Context(wl.beta, wl.ntau, wl.nw, wl.spin, mode, precision, half_tau, tau_chunk)
+    ctx = gwsym.Context(wl.beta, wl.ntau, wl.nw, wl.spin, mode, precision, half_tau, tau_chunk, sched)
     ctx.build_symmetry_basis(cr.lattice, cr.positions, rot, trans, wl.n, wl.ao, wl.aux)
     return ctx
 
@@ -174,19 +182,28 @@ def profile_step(path, torch):
     return prof
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(wl, F_all, vpairs, ibz_rep_q, torch):
     """The FP64 oracle (full matrices, no symmetry) on the host, timed on a bounded sample of
-    one iteration at the workload's shapes: 32 P0 outputs (one q, 32 tau, every k), 32 Sigma
-    outputs (one k, 32 tau, every q), the screened interaction for 4 of the Nk transfer
-    momenta and one Dyson solve over every k; scaled to a full iteration (Nk x ntau outputs of
-    each contraction, Nk momenta, 65 Dyson solves for the bisection)."""
+    one iteration at the workload's shapes and scaled to a full iteration (Nk x ntau outputs of
+    each contraction, Nk screened-interaction momenta, 65 Dyson solves for the bisection):
+    with every BLAS thread, up to 32 P0 outputs (one q, every k) and 32 Sigma outputs (one k,
+    every q) within about 6 s each, the screened interaction of 4 momenta and one Dyson solve
+    over every k; and with one BLAS thread, one output of each contraction."""
     import oracle
     from gwinputs import add_k, minus_k
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     nk, nt = wl.nk, wl.ntau
     ns = min(32, nt)
     add = add_k(wl.n)
@@ -195,24 +212,26 @@ def cpu_baseline(wl, F_all, vpairs, ibz_rep_q, torch):
     F = F_all.cpu().numpy()
     tau = oracle.tau_grid(wl.beta, nt)
     G = oracle.g0_closed_form(F, 0.0, wl.beta, tau)
-    q = ibz_rep_q
+    q = k = ibz_rep_q
     Vq = vpairs([(kk, int(add[kk, q])) for kk in range(nk)]).cpu().numpy()
-    k = ibz_rep_q
     Vk = vpairs([(k, int(sub[k, qq])) for qq in range(nk)]).cpu().numpy()
     rng = np.random.default_rng(0)
     Ph = rng.standard_normal((nk, wl.naux, wl.naux)) * 1e-3
     Ph = Ph + Ph.transpose(0, 2, 1)
-    # at most ns outputs of each contraction, fewer where they take over 10 s in all
-    t, n_p0 = time.perf_counter(), 0
-    while n_p0 < ns and (n_p0 == 0 or time.perf_counter() - t < 10.0):
-        oracle.polarization_unit(G, Vq, add, q, n_p0, wl.spin)
-        n_p0 += 1
-    t_p0 = (time.perf_counter() - t) / n_p0
-    t, n_s = time.perf_counter(), 0
-    while n_s < ns and (n_s == 0 or time.perf_counter() - t < 10.0):
-        oracle.self_energy_unit(G, Vk, Ph, sub, k, n_s)
-        n_s += 1
-    t_s = (time.perf_counter() - t) / n_s
+
+    def contractions(nmax, limit):
+        t, n_p0 = time.perf_counter(), 0
+        while n_p0 < nmax and (n_p0 == 0 or time.perf_counter() - t < limit):
+            oracle.polarization_unit(G, Vq, add, q, n_p0, wl.spin)
+            n_p0 += 1
+        t_p0 = (time.perf_counter() - t) / n_p0
+        t, n_s = time.perf_counter(), 0
+        while n_s < nmax and (n_s == 0 or time.perf_counter() - t < limit):
+            oracle.self_energy_unit(G, Vk, Ph, sub, k, n_s)
+            n_s += 1
+        return t_p0, n_p0, (time.perf_counter() - t) / n_s, n_s
+
+    t_p0, n_p0, t_s, n_s = contractions(ns, 6.0)
     nq = min(4, nk)
     X = rng.standard_normal((nq, nt, wl.naux, wl.naux)) * 1e-3
     X = X + X.transpose(0, 1, 3, 2)
@@ -228,8 +247,15 @@ def cpu_baseline(wl, F_all, vpairs, ibz_rep_q, torch):
               f"all {nk} q) at {t_s:.3f} s each, screened interaction for {nq} momenta at {t_scr:.2f} s each, one "
               f"Dyson solve over all k {t_dys:.3f} s; scaled to {nk * nt} outputs of each contraction, {nk} "
               f"momenta and 65 Dyson solves")
+    # one BLAS thread: one output of each contraction (the bulk of the work)
+    with threadpool_limits(limits=1):
+        t1_p0, _, t1_s, _ = contractions(1, 0.0)
+    single = {"value": (t1_p0 + t1_s) * nk * nt, "unit": "s/iteration (contractions only)", "cores": 1,
+              "sample": f"one BLAS thread: one P0 output ({t1_p0:.2f} s) and one Sigma output ({t1_s:.2f} s), "
+                        f"scaled to {nk * nt} outputs of each"}
     return {"value": total, "unit": "s/iteration", "cores": int(cores), "kind": "oracle", "sample": sample,
-            "extrapolated": True}
+            "extrapolated": True, "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": single}
 
 
 def main():
@@ -237,20 +263,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--workload", default="cfg4")
     ap.add_argument("--tau-chunk", type=int, default=0)
-    ap.add_argument("--no-full", action="store_true", help="skip the full-matrix FP64 comparison")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated comparison runs: fp32, bf16x6, bf16x3 (reduced-precision contractions), "
+                         "full (no symmetry, all-pair V: cfg0/cfg1 only), unbatched (per-block launches)")
     ap.add_argument("--graph", type=int, default=1, help="1 (default): replay each iteration from a captured HIP graph; 0: eager launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp32", action="store_true",
-                    help="skip the runs of the block path with FP32 and split-bfloat16 contractions")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1 (default): each block path takes its launch plan from --plans, or times candidate "
-                         "plans (gwsym_autotune) when the file has none for this workload and device; 0: default plan")
+                         "plans (gwsym_autotune) when the file has none for this workload and device (small "
+                         "workloads only); 0: default plan")
     ap.add_argument("--plans", default=PLANS_FILE, help="JSON file of autotuned launch plans")
     ap.add_argument("--no-exchange", action="store_true", help="skip timing the exchange term (profiling runs)")
     ap.add_argument("--error-iterations", type=int, default=10,
-                    help="iterations over which the reduced-precision paths are compared with the FP64 one")
+                    help="iterations over which the reduced-precision legs are compared with the FP64 path")
     ap.add_argument("--update-plans", action="store_true", help="add newly autotuned plans to --plans")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="before the timed steps, copy a buffer of this many MiB once (a plain copy kernel "
@@ -260,6 +287,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the distributed path is a design "
               "description, not part of this build", file=sys.stderr)
         sys.exit(2)
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in ("fp32", "bf16x6", "bf16x3", "full", "unbatched"):
+            ap.error(f"unknown leg {x!r}")
 
     import torch
     from gwinputs import Inputs, workload
@@ -268,6 +299,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     wl = workload(args.workload)
+    if "full" in legs and wl.pairwise:
+        ap.error("the full-matrix leg needs V over every pair, which the 6^3 workloads cannot hold")
     log(f"[bench] workload {wl.name}: {wl.crystal} n={wl.n} nao={wl.nao} naux={wl.naux} ntau={wl.ntau} beta={wl.beta}")
     t = time.perf_counter()
     inp = Inputs(wl, device=dev)
@@ -302,25 +335,63 @@ def main():
         log(f"[bench] calibration copy of {args.copy_calib_mb} MiB done")
         del a, b
 
-    # ---- block-grouped, irreducible wedge, FP64 ----
+    def plan_for(path):
+        if not args.autotune:
+            return path.ctx.get_tuning(), "default"
+        tuning = path.ctx.autotune(cache=args.plans, update=args.update_plans, time_missing=not wl.pairwise)
+        return tuning, getattr(path.ctx, "plan_source", "default")
+
+    # ---- block-grouped, irreducible wedge, FP64 (the headline) ----
     t = time.perf_counter()
     blk = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk), F_all, V_src, torch, dev,
                graph=bool(args.graph))
     log(f"[bench] block path set up in {time.perf_counter() - t:.1f} s; N_target={blk.n_target:.6f}")
-    tuning, tune_s = blk.ctx.get_tuning(), 0.0
-    if args.autotune:
-        t = time.perf_counter()
-        tuning = blk.ctx.autotune(cache=args.plans, update=args.update_plans, time_missing=not wl.pairwise)
-        tune_s = time.perf_counter() - t
-        log(f"[bench] launch plan, {blk.ctx.plan_source} ({tune_s:.1f} s): {tuning}")
+    t = time.perf_counter()
+    tuning, plan_source = plan_for(blk)
+    log(f"[bench] launch plan, {plan_source} ({time.perf_counter() - t:.1f} s): {tuning}")
     s_blk = time_steps(blk, args.steps, args.warmup, torch)
+    blk.ctx.check()
     log(f"[bench] block: {s_blk:.4f} s/iteration")
     prof = profile_step(blk, torch)
     p0_macs, s_macs = blk.ctx.flop_counts()
-    flops_iter = 8.0 * (p0_macs + s_macs)
-    contr_ms = sum(prof[k][0] for k in ("p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction",
-                                         "row_block_multiply", "two_sided_block_multiply"))
     log("[bench] profile: " + ", ".join(f"{k} {v[0]:.1f} ms/{v[1]}" for k, v in prof.items()))
+
+    # per contraction: every kernel class it launches, block-executed flops, one call per iteration
+    def contraction(name, classes):
+        ms = sum(prof[k][0] for k in classes)
+        flops = 8.0 * sum(prof[k][2] for k in classes)
+        traffic = [measured_traffic(wl.name, k) for k in classes]
+        launches = {k: prof[k][1] for k in classes}
+        achieved = flops / (ms * 1e-3) / 1e12
+        return {"kernel": name, "kernels": list(classes), "bound": "mfma", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": (sum(traffic) if all(x is not None for x in traffic) else None),
+                "per_call_flops": flops, "per_call_ms": ms, "launches_per_call": launches}
+
+    contr = {name: contraction(name, cl) for name, cl in CONTRACTIONS.items()}
+    dom = max(contr, key=lambda k: contr[k]["per_call_ms"])
+    for name, r in contr.items():
+        log(f"[bench] {name}: {r['per_call_ms']:.1f} ms, {r['achieved']:.1f} TF/s = {r['frac']:.3f} of FP64 MFMA peak")
+    flops_iter = sum(r["per_call_flops"] for r in contr.values())
+    contr_ms = sum(r["per_call_ms"] for r in contr.values())
+
+    # per kernel class (for the profiles): bound chosen by the algorithmic intensity
+    def class_roofline(name):
+        ms, nl, macs, nbytes = prof[name]
+        flops = 8.0 * macs
+        avg_s = ms / nl * 1e-3
+        entry = {"avg_launch_ms": ms / nl, "launches": nl, "per_launch_flops": flops / nl,
+                 "per_launch_bytes": nbytes / nl}
+        if nbytes > 0 and flops / nbytes < RIDGE:
+            entry.update({"bound": "hbm", "achieved": nbytes / nl / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"})
+        else:
+            entry.update({"bound": "mfma", "achieved": flops / nl / avg_s / 1e12, "peak": PEAK_FP64_TFLOPS,
+                          "unit": "TFLOP/s"})
+        entry["frac"] = entry["achieved"] / entry["peak"]
+        entry["traffic"] = measured_traffic(wl.name, name)
+        return entry
+
+    kernels = {k: class_roofline(k) for cl in CONTRACTIONS.values() for k in cl if prof[k][1] > 0}
 
     # static self-energy (eq. sigma_hf) from the current G, once each: K, J and F = H0 + J + K
     exchange_ms = hartree_ms = fock_ms = None
@@ -343,32 +414,6 @@ def main():
             f"F = H0 + J + K {fock_ms:.2f} ms")
         del Kx
 
-    # dominant kernel class by time; its bound follows from the algorithmic intensity
-    def roofline(name):
-        ms, nl, macs, nbytes = prof[name]
-        flops = 8.0 * macs
-        avg_s = ms / nl * 1e-3
-        entry = {"kernel": name, "avg_launch_ms": ms / nl, "launches": nl,
-                 "per_launch_flops": flops / nl, "per_launch_bytes": nbytes / nl,
-                 "intensity_flop_per_byte": flops / nbytes if nbytes > 0 else None}
-        if nbytes > 0 and flops / nbytes < RIDGE:
-            achieved = nbytes / nl / avg_s / 1e9
-            entry.update({"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"})
-        else:
-            # the GEMM stages run on the FP64 MFMA, the block multiplies on the FP64 vector ALU
-            # (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s, the same figure)
-            achieved = flops / nl / avg_s / 1e12
-            entry.update({"bound": "alu" if name in VALU_CLASSES else "mfma", "achieved": achieved,
-                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"})
-        entry["frac"] = entry["achieved"] / entry["peak"]
-        entry["traffic"] = measured_traffic(name)
-        return entry
-
-    dom = max(prof, key=lambda k: prof[k][0])
-    roof = roofline(dom)
-    kernels = {k: roofline(k) for k in ("p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction",
-                                        "row_block_multiply", "two_sided_block_multiply") if prof[k][1] > 0}
-
     out = {"metric": METRIC, "value": s_blk, "unit": "s/iteration", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * s_blk, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -378,107 +423,73 @@ def main():
                       "mode": "irreducible wedge + isotypic blocks, grouped contractions", "precision": "fp64"},
            "contraction_tflops": flops_iter / (contr_ms * 1e-3) / 1e12 if contr_ms > 0 else None,
            "algorithmic_flops_per_iteration": flops_iter,
+           "contractions": contr,
            "profile_ms": {k: v[0] for k, v in prof.items()},
            "exchange_ms": exchange_ms, "hartree_ms": hartree_ms, "fock_ms": fock_ms,
-           "launch_plan": tuning, "launch_plan_source": getattr(blk.ctx, "plan_source", "default"),
-           "launch_plan_s": tune_s,
+           "launch_plan": tuning, "launch_plan_source": plan_source,
            "kernels": kernels,
-           "roofline": roof}
+           "roofline": contr[dom]}
 
-    # ---- full-matrix FP64 (no symmetry) on the same GPU ----
-    if wl.pairwise and not args.no_full:
-        need = 16.0 * wl.nk * wl.nk * wl.naux * wl.nao * wl.nao
-        out["full_fp64_s_per_iteration"] = None
-        out["full_fp64_note"] = (f"not run: V over every pair of the mesh alone is {need / 1e9:.0f} GB "
-                                 f"(and the form keeps two transformed copies), beyond one GPU's 288 GB")
-        log(f"[bench] full: {out['full_fp64_note']}")
-    elif not args.no_full:
+    # ---- comparison legs (not part of the headline) ----
+    if "full" in legs:
         full = Path(make_ctx(wl, gwsym.MODE_FULL, tau_chunk=args.tau_chunk), F_all, V_all, torch, dev)
-        # compare one iteration from the same G0 against the block path
-        blk2 = blk
-        blk2.ctx.g0(blk2.F, 0.0, blk2.G, blk2.nfree)
+        blk.ctx.g0(blk.F, 0.0, blk.G, blk.nfree)   # one iteration from the same G0 in both forms
         full.step()
-        blk2.step()
+        blk.step()
         torch.cuda.synchronize()
-        a, b = full.full(1, full.S), blk2.full(1, blk2.S)
+        a, b = full.full(1, full.S), blk.full(1, blk.S)
         err = float((a - b).abs().max() / b.abs().max())
         s_full = time_steps(full, 1, 0, torch)
         fp0, fs = full.ctx.flop_counts()
-        out["full_fp64_s_per_iteration"] = s_full
-        out["speedup_block_vs_full"] = s_full / s_blk
-        out["full_algorithmic_flops_per_iteration"] = 8.0 * (fp0 + fs)
-        out["sigma_rel_err_block_vs_full"] = err
+        out["full_fp64"] = {"s_per_iteration": s_full, "speedup_block_vs_full": s_full / s_blk,
+                            "algorithmic_flops_per_iteration": 8.0 * (fp0 + fs), "sigma_rel_err_block_vs_full": err}
         log(f"[bench] full: {s_full:.3f} s/iteration, Sigma block vs full {err:.2e}")
         del full
-
-    # ---- the same block path with reduced-precision contractions (FP64 transforms, inverses
-    # and mu): FP32 operands on the FP32 MFMA, and split-bfloat16 products on the bfloat16 MFMA
-    if wl.pairwise:
-        # the 6^3 workloads hold one path at a time (their errors against the oracle are checked
-        # by the sampled full-size parity tests)
-        ibz_blk = blk.ctx.table("ibz")
-        del blk
+    if "unbatched" in legs:
+        ub = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, sched=gwsym.SCHED_UNBATCHED), F_all,
+                  V_src, torch, dev)
+        s_ub = time_steps(ub, 1, 1, torch)
+        out["unbatched_fp64"] = {"s_per_iteration": s_ub, "speedup_grouped_vs_unbatched": s_ub / s_blk,
+                                 "schedule": "one launch per pair (block multiplies) and per (pair, block) (GEMMs), "
+                                             "in order, eager"}
+        log(f"[bench] unbatched: {s_ub:.3f} s/iteration")
+        del ub
+        torch.cuda.empty_cache()
+    reduced = [(k, p) for k, p in (("fp32", gwsym.FP32), ("bf16x6", gwsym.BF16X6), ("bf16x3", gwsym.BF16X3))
+               if k in legs]
+    ibz_blk = blk.ctx.table("ibz")
+    if wl.pairwise and reduced:
+        del blk    # the 6^3 workloads hold one path at a time
         torch.cuda.empty_cache()
         blk = None
-    if not args.no_fp32:
-        modes = (("fp32_contractions", gwsym.FP32), ("bf16x6_contractions", gwsym.BF16X6),
-                 ("bf16x3_contractions", gwsym.BF16X3))
-        if wl.pairwise:
-            modes = modes[1:2]
-        for key, prec in modes:
-            red = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=prec), F_all, V_src,
-                       torch, dev, graph=bool(args.graph))
-            red_tuning = (red.ctx.autotune(cache=args.plans, update=args.update_plans, time_missing=not wl.pairwise)
-                          if args.autotune else red.ctx.get_tuning())
-            s_red = time_steps(red, args.steps, args.warmup, torch)
-            if blk is not None and args.error_iterations > 0:
-                # errors against the FP64 block path over several iterations from the same G0
-                # (the FP64 path is held to the oracle at 1e-10 per iteration by the parity tests)
-                hist = iteration_errors(blk, red, args.error_iterations, torch)
-                log(f"[bench] {key}: over {args.error_iterations} iterations max P0 {max(h[0] for h in hist):.2e}, "
-                    f"Sigma {max(h[1] for h in hist):.2e}, occupations {max(h[2] for h in hist):.2e}")
-            if blk is None:
-                prof_red = profile_step(red, torch)
-                out[key] = {"s_per_iteration": s_red, "speedup_vs_fp64_block": s_blk / s_red,
-                            "launch_plan": red_tuning, "profile_ms": {k: v[0] for k, v in prof_red.items()}}
-                log(f"[bench] {key}: {s_red:.4f} s/iteration")
-                log(f"[bench] {key} profile: " + ", ".join(f"{k} {v[0]:.1f} ms" for k, v in prof_red.items()))
-                del red
-                torch.cuda.empty_cache()
-                continue
-            for pth in (blk, red):   # one iteration from the same G0 in both precisions
-                pth.ctx.g0(pth.F, 0.0, pth.G, pth.nfree)
-                pth.step()
-            torch.cuda.synchronize()
-            a, b = red.full(1, red.S), blk.full(1, blk.S)
-            err_s = float((a - b).abs().max() / b.abs().max())
-            a, b = red.full(2, red.P0), blk.full(2, blk.P0)
-            err_p0 = float((a - b).abs().max() / b.abs().max())
-            ga, gb = red.full(1, red.G), blk.full(1, blk.G)
-            nk_, nt_, no_ = blk.ctx.nk, blk.ctx.ntau, blk.ctx.nao
-            occ = lambda g: -torch.diagonal(g.view(nk_, nt_, no_, no_)[:, -1], dim1=-2, dim2=-1).real
-            occ_err = float((occ(ga) - occ(gb)).abs().max())
-            prof_red = profile_step(red, torch)
-            out[key] = {"s_per_iteration": s_red, "speedup_vs_fp64_block": s_blk / s_red,
-                        "p0_rel_err_vs_fp64": err_p0, "sigma_rel_err_vs_fp64": err_s,
-                        "occupation_max_abs_err_vs_fp64": occ_err, "launch_plan": red_tuning,
-                        "profile_ms": {k: v[0] for k, v in prof_red.items()}}
-            if args.error_iterations > 0:
-                out[key]["errors_over_iterations"] = {
-                    "iterations": args.error_iterations, "reference": "FP64 block path, same G0",
-                    "p0_rel_max": max(h[0] for h in hist), "sigma_rel_max": max(h[1] for h in hist),
-                    "occupation_abs_max": max(h[2] for h in hist),
-                    "per_iteration": [[float(f"{x:.3e}") for x in h] for h in hist]}
-            log(f"[bench] {key}: {s_red:.4f} s/iteration, P0 vs fp64 {err_p0:.2e}, Sigma {err_s:.2e}, "
-                f"occupations {occ_err:.2e}")
-            log(f"[bench] {key} profile: " + ", ".join(f"{k} {v[0]:.1f} ms" for k, v in prof_red.items()))
-            del red
+    for key, prec in reduced:
+        red = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, precision=prec), F_all, V_src,
+                   torch, dev, graph=bool(args.graph))
+        red_tuning, _ = plan_for(red)
+        s_red = time_steps(red, args.steps, args.warmup, torch)
+        entry = {"s_per_iteration": s_red, "speedup_vs_fp64_block": s_blk / s_red, "launch_plan": red_tuning}
+        if blk is not None and args.error_iterations > 0:
+            # errors against the FP64 block path over several iterations from the same G0 (the
+            # FP64 path is held to the oracle at 1e-10 per iteration by the parity tests)
+            hist = iteration_errors(blk, red, args.error_iterations, torch)
+            entry["errors_over_iterations"] = {
+                "iterations": args.error_iterations, "reference": "FP64 block path, same G0",
+                "p0_rel_max": max(h[0] for h in hist), "sigma_rel_max": max(h[1] for h in hist),
+                "occupation_abs_max": max(h[2] for h in hist),
+                "per_iteration": [[float(f"{x:.3e}") for x in h] for h in hist]}
+        prof_red = profile_step(red, torch)
+        entry["profile_ms"] = {k: v[0] for k, v in prof_red.items()}
+        out[key + "_contractions"] = entry
+        log(f"[bench] {key}: {s_red:.4f} s/iteration; profile " + ", ".join(f"{k} {v[0]:.1f} ms"
+                                                                            for k, v in prof_red.items()))
+        del red
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
-        ibz = blk.ctx.table("ibz") if blk is not None else ibz_blk
         vpairs = (lambda pr: inp.three_index(pr)) if wl.pairwise else (lambda pr: V_all[tuple(zip(*pr))])
-        out["cpu_baseline"] = cpu_baseline(wl, F_all, vpairs, int(ibz[1]), torch)
-        log(f"[bench] cpu oracle (extrapolated): {out['cpu_baseline']['value']:.1f} s/iteration")
+        out["cpu_baseline"] = cpu_baseline(wl, F_all, vpairs, int(ibz_blk[1]), torch)
+        log(f"[bench] cpu oracle (extrapolated): {out['cpu_baseline']['value']:.1f} s/iteration on "
+            f"{out['cpu_baseline']['cores']} threads ({out['cpu_baseline']['cpu_model']})")
     print(json.dumps(out), flush=True)
 
 

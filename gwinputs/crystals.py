@@ -85,10 +85,53 @@ def _ops_from_cart(lattice, cart_ops, trans_frac):
     return out
 
 
+HEX_C = 2.664   # c/a of hexagonal boron nitride
+
+
+def hexagonal_lattice(c: float = HEX_C) -> np.ndarray:
+    """Columns a1 = (1, 0, 0), a2 = (-1/2, sqrt(3)/2, 0), a3 = (0, 0, c), in units of a."""
+    return np.array([[1.0, 0.0, 0.0], [-0.5, np.sqrt(3.0) / 2.0, 0.0], [0.0, 0.0, c]]).T
+
+
+def close_group(gens):
+    """All products of the generators (W, w) acting on fractional coordinates, translations
+    reduced to [0, 1); identity first, then in order of discovery."""
+    def key(W, w):
+        return tuple(W.ravel()), tuple(np.round(np.mod(w, 1.0), 9) % 1.0)
+    ops = [(np.eye(3, dtype=np.int64), np.zeros(3))]
+    seen = {key(*ops[0])}
+    frontier = list(ops)
+    while frontier:
+        new = []
+        for W1, w1 in frontier:
+            for W2, w2 in gens:
+                W = W1 @ W2
+                w = np.mod(W1 @ w2 + w1, 1.0)
+                w[np.isclose(w, 1.0)] = 0.0
+                k = key(W, w)
+                if k not in seen:
+                    seen.add(k)
+                    ops.append((W, w))
+                    new.append((W, w))
+        frontier = new
+    return ops
+
+
+def p63mmc_ops():
+    """The 24 operations of P6_3/mmc (No. 194) in the hexagonal setting, from the screw axis
+    6_3 = (x - y, x, z + 1/2), the inversion and the two-fold axis (y, x, -z)."""
+    g6 = (np.array([[1, -1, 0], [1, 0, 0], [0, 0, 1]], dtype=np.int64), np.array([0.0, 0.0, 0.5]))
+    inv = (-np.eye(3, dtype=np.int64), np.zeros(3))
+    c2 = (np.array([[0, 1, 0], [1, 0, 0], [0, 0, -1]], dtype=np.int64), np.zeros(3))
+    return close_group([g6, inv, c2])
+
+
 def crystal(name: str) -> Crystal:
     """Named crystals: 'sc' (Pm-3m, one atom), 'rocksalt' (Fm-3m, atoms at 0
     and (1/2,1/2,1/2)a), 'diamond' (Fd-3m origin choice 1, atoms at 0 and
-    (1/4,1/4,1/4)a; the 24 operations outside T_d carry v = (1/4,1/4,1/4)a)."""
+    (1/4,1/4,1/4)a; the 24 operations outside T_d carry v = (1/4,1/4,1/4)a), and 'hbn'
+    (P6_3/mmc, No. 194, hexagonal boron nitride: B at (1/3, 2/3, 1/4) and (2/3, 1/3, 3/4), N at
+    (1/3, 2/3, 3/4) and (2/3, 1/3, 1/4); half of the operations carry v = (0, 0, 1/2))."""
     oh = cubic_point_group()
     if name == "sc":
         A = np.eye(3)
@@ -103,6 +146,9 @@ def crystal(name: str) -> Crystal:
         ops = _ops_from_cart(FCC, oh, tr)
         pos = np.array([[0.0, 0.0, 0.0], [0.25, 0.25, 0.25]])
         return Crystal("diamond", FCC.copy(), pos, [0, 0], ops, False)
+    if name == "hbn":
+        pos = np.array([[1 / 3, 2 / 3, 0.25], [2 / 3, 1 / 3, 0.75], [1 / 3, 2 / 3, 0.75], [2 / 3, 1 / 3, 0.25]])
+        return Crystal("hbn", hexagonal_lattice(), pos, [0, 0, 1, 1], p63mmc_ops(), False)
     raise ValueError(f"unknown crystal {name!r}")
 
 
@@ -242,6 +288,12 @@ def workload(name: str) -> Workload:
     if name == "wide_diamond":     # cfg4 orbital basis, non-symmorphic
         return Workload(name, "diamond", 2, shells_on_atoms(_AO26, 2),
                         shells_on_atoms([S, P, D, F_], 2), 16, 30.0, BASE_SEED + 16)
+    if name == "small_hbn":        # hexagonal P6_3/mmc (non-symmorphic screw axis), 2x2x2 mesh
+        return Workload(name, "hbn", 2, shells_on_atoms([S, P], 4),
+                        shells_on_atoms([S, P, D], 4), 12, 25.0, BASE_SEED + 19)
+    if name == "small_hbn3":       # the 3x3x3 mesh holds the K points (1/3, 1/3, 0) and (1/3, 1/3, 1/3)
+        return Workload(name, "hbn", 3, shells_on_atoms([S, P], 4),
+                        shells_on_atoms([S, P], 4), 10, 20.0, BASE_SEED + 20)
     if name == "pair_diamond":     # small_diamond with the pair-keyed V draws of the 6^3 meshes
         return Workload(name, "diamond", 2, shells_on_atoms([S, P, D], 2),
                         shells_on_atoms([S, P, D, F_], 2), 16, 30.0, BASE_SEED + 18, pairwise=True)

@@ -33,7 +33,7 @@ import torch
 from .crystals import Workload, crystal, kmap, minus_k, mesh_points, mesh_index
 from .rep import BasisRep
 
-TENSOR_F, TENSOR_V, TENSOR_AUXMAT = 1, 2, 3
+TENSOR_F, TENSOR_V, TENSOR_AUXMAT, TENSOR_ORBMAT = 1, 2, 3, 4
 
 
 def _philox(seed: int, tensor: int, a: int, b: int = 0) -> np.random.Generator:
@@ -150,6 +150,17 @@ class Inputs:
         if qs is not None:
             X = X[list(qs)]
         return self._t(X)
+
+    def orb_matrices(self, nmat: int, scale: float = 0.01) -> torch.Tensor:
+        """Symmetric Hermitian orbital-basis matrices Y^k_j, [Nk, nmat, nao, nao] (time reversal
+        and group averaging as for F); the orbital twin of aux_matrices, used to assemble
+        stand-in self-energies for Dyson-only tests."""
+        wl = self.wl
+        raw = np.stack([np.stack([_cnormal(_philox(wl.seed, TENSOR_ORBMAT, k, j), (wl.nao, wl.nao))
+                                  for j in range(nmat)]) for k in range(self.nk)])
+        raw = 0.5 * (raw + raw.conj().swapaxes(-1, -2))
+        Y = self._sym_two_index(self.ao, raw)
+        return self._t(scale * 0.5 * (Y + Y.conj().swapaxes(-1, -2)))
 
     # -- three-index tensor ---------------------------------------------------
     def _raw_V(self) -> torch.Tensor:

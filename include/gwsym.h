@@ -60,8 +60,9 @@ typedef enum {
   GWSYM_ESHAPE = -2,     /* sizes inconsistent with the context */
   GWSYM_ENOMEM = -3,     /* host or device allocation failed */
   GWSYM_EHIP = -4,       /* a HIP runtime call failed */
-  GWSYM_ESINGULAR = -5,  /* a matrix to invert was singular (checked on the host side only) */
-  GWSYM_ENOCONV = -6,    /* an iterative host routine did not converge */
+  GWSYM_ESINGULAR = -5,  /* a matrix of a Dyson equation was singular (reported by gwsym_check) */
+  GWSYM_ENOCONV = -6,    /* an iterative routine did not converge, or the chemical-potential
+                            search missed N_e (reported by gwsym_check) */
   GWSYM_ESTATE = -7      /* call made out of order (e.g. before build_symmetry_basis) */
 } gwsym_status;
 
@@ -84,6 +85,13 @@ typedef enum {
   GWSYM_BF16X3 = 3       /* two pieces hi + lo and three products: faster, about 1e-5 relative */
 } gwsym_precision;
 
+/* Launch schedule of the contractions (eq. P0, eq. sigma). */
+typedef enum {
+  GWSYM_SCHED_GROUPED = 0,   /* every stage of a tau chunk is one launch over all pairs and blocks */
+  GWSYM_SCHED_UNBATCHED = 1  /* one launch per pair for the block multiplies and per (pair, block)
+                                for the GEMMs, issued one after another: the per-block baseline */
+} gwsym_sched;
+
 typedef struct {
   double beta;        /* inverse temperature (1/Ha) */
   int ntau;           /* Chebyshev-Gauss-Lobatto tau points on [0, beta], >= 3 */
@@ -94,6 +102,7 @@ typedef struct {
   int half_tau;       /* 1: inputs are time-reversal symmetric, P0 is evaluated for
                          tau_j with j < ceil(ntau/2) and mirrored (Alg. 3 tau loop) */
   int tau_chunk;      /* tau points per contraction launch (0 = library default) */
+  int sched;          /* gwsym_sched */
 } gwsym_params;
 
 typedef struct {
@@ -205,10 +214,22 @@ int gwsym_self_energy(gwsym_ctx* ctx, const void* G_blk, const void* P_blk, void
 
 /* Chemical potential for a fixed electron count (Sec. 4.1, N_e): bisection over 64
  * steps on N(mu) = (s/Nk) sum_k Tr[-G^k(beta; mu)], G from eq. dyson with F_blk and
- * Sigma_blk (device).  Bracket: [lowest, highest] eigenvalue of F -/+ 20 Ha (the
- * eigenvalues come from the last gwsym_g0 call).  Writes *mu (device double). */
+ * Sigma_blk (device).  Bracket: [lowest, highest] eigenvalue of the F_blk passed in -/+ 20 Ha
+ * (a block eigen-solve of F on the device, no earlier call needed).  N is evaluated once more
+ * at the result: |N(mu) - n_target| above 1e-8 max(1, n_target) (the root was outside the
+ * bracket) sets a device flag that the next gwsym_check reports as GWSYM_ENOCONV.  Writes *mu
+ * (device double).  Asynchronous and graph-capturable like the other device calls.  Orbital
+ * blocks <= 60 (GWSYM_ESHAPE). */
 int gwsym_find_mu(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, double n_target,
                   double* mu, void* stream);
+
+/* Waits for the work queued on `stream`, then reads and clears the context's device status
+ * word, which the device calls set without synchronising: GWSYM_ESINGULAR when a batched
+ * inverse of eq. P02P (I - P0) or eq. dyson ((i w_n + mu) - F - Sigma) met an exactly zero
+ * pivot column since the last check (the results of that call are then not finite);
+ * GWSYM_ENOCONV when a gwsym_find_mu result missed n_target; else GWSYM_OK.
+ * Synchronises `stream`. */
+int gwsym_check(gwsym_ctx* ctx, void* stream);
 
 /* eq. dyson: Sigma(tau) -> Sigma(i w_n), G(i w_n) = [(i w_n + mu) I - F - Sigma(i w_n)]^{-1}
  * per block, i w_n -> tau.  mu is a device double.  Writes G_blk (device). */
@@ -255,8 +276,7 @@ int gwsym_iteration(gwsym_ctx* ctx, const void* F_blk, void* G_blk, void* P0_blk
  * gwsym_iteration with that F, all from the same G.  H0_blk is the non-interacting one-body
  * matrix (device, F layout); F_blk is written (device, F layout, must not alias H0_blk or
  * G_blk).  The chemical-potential search brackets the root by the lowest and highest
- * eigenvalue of the new F -/+ 20 Ha (the eigenvalues as gwsym_g0 computes them; that bracket
- * then stays for later gwsym_find_mu calls).  use_graph as for gwsym_iteration (the F update is captured with the
+ * eigenvalue of the new F -/+ 20 Ha, as gwsym_find_mu does.  use_graph as for gwsym_iteration (the F update is captured with the
  * rest).  GWSYM_FP64 only (GWSYM_EINVAL otherwise). */
 int gwsym_scf_iteration(gwsym_ctx* ctx, const void* H0_blk, void* F_blk, void* G_blk, void* P0_blk, void* P_blk,
                         void* Sigma_blk, double* mu, double n_target, int use_graph, void* stream);

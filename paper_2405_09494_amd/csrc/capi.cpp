@@ -24,6 +24,7 @@ int check_params(const gwsym_params* p, std::string& err) {
   if (p->precision < GWSYM_FP64 || p->precision > GWSYM_BF16X3) return err = "unknown precision", GWSYM_EINVAL;
   if (p->tau_chunk < 0) return err = "tau_chunk must be >= 0", GWSYM_EINVAL;
   if (!(p->spin > 0)) return err = "spin factor must be positive", GWSYM_EINVAL;
+  if (p->sched != GWSYM_SCHED_GROUPED && p->sched != GWSYM_SCHED_UNBATCHED) return err = "unknown schedule", GWSYM_EINVAL;
   return GWSYM_OK;
 }
 
@@ -266,6 +267,12 @@ int gwsym_scf_iteration(gwsym_ctx* ctx, const void* H0_blk, void* F_blk, void* G
   NEED(ctx->c.prm.precision == GWSYM_FP64, GWSYM_EINVAL, "the F update is computed in FP64 only");
   NEED(!(use_graph && stream == nullptr), GWSYM_EINVAL, "graph capture needs a created stream");
   return device_iteration(ctx->c, H0_blk, F_blk, G_blk, P0_blk, P_blk, Sigma_blk, mu, n_target, use_graph, stream);
+}
+
+int gwsym_check(gwsym_ctx* ctx, void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.dev, GWSYM_ESTATE, "gwsym_device_init must come first");
+  return device_check(ctx->c, stream);
 }
 
 int gwsym_profile(gwsym_ctx* ctx, int enable) {

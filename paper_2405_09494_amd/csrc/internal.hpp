@@ -171,6 +171,7 @@ int device_hartree(Ctx& c, const void* G, void* J, const void* add, int accumula
 int device_fock(Ctx& c, const void* H0, const void* G, void* F, void* stream);
 int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stream);
 int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double* mu, void* stream);
+int device_check(Ctx& c, void* stream);
 int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream);
 int device_iteration(Ctx& c, const void* H0, const void* F, void* G, void* P0, void* P, void* S, double* mu,
                      double ntarget, int use_graph, void* stream);

@@ -25,13 +25,11 @@ struct GemmPlanDev {
   int prefetch = 2;              // FP64 / FP32 forms: K sub-steps per group (2 or 4)
 };
 
-// rows [0, nrows) of a row-major slab (right multiply), or the slab width (left multiply)
-// One slab for a block-diagonal multiply.  Right multiply: nrows rows of ncol columns, each
-// row times the block-diagonal matrix at g_off (and, with out_off2 >= 0, also times the one at
-// g_off2 with the same blocks, into out_off2).  Left multiply: nb_rows rows of nrows
-// columns, G^H (at g_off) applied from the left.  Both-sided multiply: nb_rows rows of
-// nrows columns made of nrows / nb_rows square nb_rows x nb_rows matrices side by side, each
-// X -> Gl^H X Gr^H with Gl at (g_off, blk) and Gr at (g_off2, blk2).
+// One slab for a block-diagonal multiply (bdiag.hip).  Right multiply: nrows rows of n
+// columns, each row times the block-diagonal matrix at g_off (and, with out_off2 >= 0, also
+// times the one at g_off2 with the same blocks, into out_off2).  Both-sided multiply: n rows of
+// nrows columns made of nrows / n square n x n matrices side by side, each X -> Gl^H X Gr^H
+// with Gl at (g_off, blk) and Gr at (g_off2, blk2).
 struct RowSeg {
   int inbuf, outbuf, gbuf, blk;  // blk: offset of the block table entry in btab
   int64_t in_off, out_off, g_off;
@@ -39,12 +37,6 @@ struct RowSeg {
   int64_t g_off2;
   int64_t out_off2;   // right multiply: >= 0 writes a second product, by the matrix at g_off2
 };
-
-// n x n matrices per workgroup of the both-sided block multiply (at most 64 columns, n <= 32)
-__host__ __device__ inline int rbb_nq(int n) {
-  const int q = 64 / n;
-  return q > 1 ? q : 1;
-}
 
 struct RowSegList {
   void* segs = nullptr;
@@ -88,8 +80,8 @@ struct EigItem {
 void launch_brgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag = 0,
                    bool fp32 = false, unsigned f32mask = 0);
 void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s);
-// gmax: largest packed block-diagonal factor (sum of squared block sizes)
-void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, int gmax, hipStream_t s,
+// block-diagonal multiplies on the matrix cores (bdiag.hip); ncol = n <= 64
+void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s,
                            bool fp32 = false);
 void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s,
                           bool fp32);
@@ -100,6 +92,8 @@ void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStrea
                   unsigned f32mask);
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
+// upper triangle of each n x n block from its lower one (and a copy to out_off when >= 0)
+void launch_herm_fill(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s);
 void launch_hartree(const void* items, const int* first, int nib, int nitems, const double* w, const void* proj,
                     int naux, int nao, void* rpart, void* rho, const void* add, int accumulate, const Bases& b,
@@ -108,8 +102,9 @@ void launch_hartree(const void* items, const int* first, int nib, int nitems, co
 void launch_inverse(const void* items, int nitems, int nmax, const Bases& b, int mode, const double* mu,
                     double* trace, int* status, hipStream_t s);
 void launch_mu_init(const double* eps_range, double* state, double* mu, hipStream_t s);
+// probe 0: one bisection step; 1: residual check of the result (status bit 2)
 void launch_mu_update(const void* items, int nitems, const double* trace, const void* Blast, double scale,
-                      double ntarget, double* state, double* mu, hipStream_t s);
+                      double ntarget, double* state, double* mu, int probe, int* status, hipStream_t s);
 // largest orbital block for the free G0 (the Jacobi matrix stays under 64 KB of LDS)
 constexpr int JAC_N = 60;
 void launch_jacobi_g0(const void* items, int nitems, const Bases& b, const double* tau, int ntau, double beta,

@@ -6,9 +6,6 @@
 //                 (transforms, block changes of basis): C_b = alpha sum_t opA(A_{b,t})
 //                 opB(B_{b,t}) + beta C_b with uneven sizes, one launch per tile list.
 //  k_reduce       ordered sum of split-K partial tiles (deterministic, no atomics).
-//  k_rowblock_*   multiply many rows by a small block-diagonal matrix from the right, or
-//                 n x n matrices by two of them from both sides: the Green's function
-//                 factors of the Sigma and P0 contractions.
 //  k_inverse      batched Gauss-Jordan inverses for the two Dyson equations.
 //  k_jacobi_g0    batched Hermitian Jacobi eigen-decomposition and the free G0(tau).
 //  k_herm, k_copy packed-block helpers; k_mu_* the chemical-potential bisection.
@@ -815,227 +812,6 @@ void launch_to_f32(const void* in, void* out, int64_t n, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// Block-diagonal row / column multiplies.
-//
-// Right: out[row][:] = in[row][:] * blockdiag(G) for the rows of one segment; G is a packed
-// set of blocks (sizes from the block table `bt`, entry bt_off[blk_id]).
-// Left:  out[:][col] = blockdiag(G)^H * in[:][col] (columns of a row-major nb x ncols slab).
-
-
-// Right multiply of rows of ncol (<= 64) columns by a block-diagonal matrix: thread
-// (column c, row group g) forms out[r][c] = sum over k in the block of c of X[r][k] G[k][c] for
-// the rows r = g, g + NG, ...; each G element is read once and used for all those rows.
-// CW = 32 (ncol <= 32, 64 rows per workgroup) or 64 (32 rows per workgroup).
-template <typename V2, int CW, bool GLDS>
-__global__ __launch_bounds__(256) void k_rowblock_right(const RowSeg* __restrict__ segs, Bases bases,
-                                                        const int* __restrict__ btab, int ncol) {
-  constexpr int NG = 256 / CW, ROWS = 8 * NG;
-  extern __shared__ double2 lds_rr[];
-  const RowSeg sg = segs[blockIdx.y];
-  const int r0 = blockIdx.x * ROWS;
-  if (r0 >= sg.nrows) return;
-  const int nrows = min(ROWS, sg.nrows - r0);
-  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + int64_t(r0) * ncol;
-  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + int64_t(r0) * ncol;
-  const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
-  const bool dual = sg.out_off2 >= 0;
-  const V2* G2 = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + (dual ? sg.g_off2 : sg.g_off);
-  const int* bt = btab + sg.blk;  // bt[0] = count, then (off, size, poff) per block
-  V2* tile = reinterpret_cast<V2*>(lds_rr);   // nrows x ncol, then (GLDS) the packed blocks of G (and G2)
-  const int nb = bt[0];
-  for (int e = threadIdx.x; e < nrows * ncol; e += 256) tile[e] = in[e];
-  if (GLDS) {
-    V2* gs = tile + ROWS * ncol;
-    const int gsz = bt[3 * nb] + bt[3 * nb - 1] * bt[3 * nb - 1];   // poff + size^2 of the last block
-    for (int e = threadIdx.x; e < gsz; e += 256) gs[e] = G[e];
-    G = gs;
-    if (dual) {
-      V2* gs2 = gs + gsz;
-      for (int e = threadIdx.x; e < gsz; e += 256) gs2[e] = G2[e];
-      G2 = gs2;
-    }
-  }
-  __syncthreads();
-  const int c = threadIdx.x % CW, g = threadIdx.x / CW;
-  if (c >= ncol) return;
-  int b = 0;
-  while (b + 1 < nb && c >= bt[1 + 3 * (b + 1)]) ++b;
-  const int off = bt[1 + 3 * b], sz = bt[2 + 3 * b], po = bt[3 + 3 * b], cc = c - off;
-  V2 acc[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) acc[i] = V2{0, 0};
-  if (!dual) {
-    for (int k = 0; k < sz; ++k) {
-      const V2 gv = G[po + k * sz + cc];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) cfma(acc[i], tile[min(g + NG * i, nrows - 1) * ncol + off + k], gv);
-    }
-  } else {
-    V2 acc2[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc2[i] = V2{0, 0};
-    for (int k = 0; k < sz; ++k) {
-      const V2 gv = G[po + k * sz + cc], gv2 = G2[po + k * sz + cc];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const V2 x = tile[min(g + NG * i, nrows - 1) * ncol + off + k];
-        cfma(acc[i], x, gv);
-        cfma(acc2[i], x, gv2);
-      }
-    }
-    V2* out2 = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off2 + int64_t(r0) * ncol;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int r = g + NG * i;
-      if (r < nrows) out2[r * ncol + c] = acc2[i];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int r = g + NG * i;
-    if (r < nrows) out[r * ncol + c] = acc[i];
-  }
-}
-
-// X -> Gl^H X Gr^H for nq square n x n matrices side by side per workgroup (the polarization's
-// second factor with both Green's function blocks applied in one pass over the slab).  The
-// tile is at most 64 columns wide: lane = column, wave w = rows w, w + 4, ...; each Green's
-// function element is read once per lane and used for all of its rows, and the intermediate
-// stays in LDS.  The Green's function blocks are read through the caches, not staged in LDS:
-// the smaller LDS footprint admits more workgroups per CU, which measured faster at nao 26
-// (7 waves per SIMD for the 8-row form, 17.9 ms against 21.0 ms per iteration with staging).
-template <typename V2, int RPW>
-__global__ __launch_bounds__(256, RPW <= 8 ? 7 : 1) void k_rowblock_both(const RowSeg* __restrict__ segs, Bases bases,
-                                                                      const int* __restrict__ btab, int n) {
-  extern __shared__ double2 lds_rb[];
-  const RowSeg sg = segs[blockIdx.y];
-  const int nq = rbb_nq(n), w = nq * n;
-  const int c0 = blockIdx.x * w;
-  const int ncols = sg.nrows;   // slab width: whole matrices side by side
-  if (c0 >= ncols) return;
-  const int wv = min(w, ncols - c0);
-  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + c0;
-  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + c0;
-  const V2* Gl = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
-  const V2* Gr = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off2;
-  const int* btl = btab + sg.blk;
-  const int* btr = btab + sg.blk2;
-  V2* tile = reinterpret_cast<V2*>(lds_rb);   // n x w
-  const int nbl = btl[0], nbr = btr[0];
-  int* info = reinterpret_cast<int*>(tile + n * w);   // per index: (off, size, poff) of its block
-  for (int c = threadIdx.x; c < n; c += 256) {
-    int bl = 0, br = 0;
-    while (bl + 1 < nbl && c >= btl[1 + 3 * (bl + 1)]) ++bl;
-    while (br + 1 < nbr && c >= btr[1 + 3 * (br + 1)]) ++br;
-    info[3 * c] = btl[1 + 3 * bl];
-    info[3 * c + 1] = btl[2 + 3 * bl];
-    info[3 * c + 2] = btl[3 + 3 * bl];
-    info[3 * (n + c)] = btr[1 + 3 * br];
-    info[3 * (n + c) + 1] = btr[2 + 3 * br];
-    info[3 * (n + c) + 2] = btr[3 + 3 * br];
-  }
-  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int r = wave; r < n; r += 4) {
-    V2 v = {0, 0};
-    if (lane < wv) v = in[int64_t(r) * ncols + lane];
-    if (lane < w) tile[r * w + lane] = v;
-  }
-  __syncthreads();
-  // RPW rows per wave: n <= 4 RPW
-  V2 acc[RPW];
-  // left: Y[a'][col] = sum over a in the block of a' of conj(Gl[a][a']) X[a][col]
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int ap = wave + 4 * i;
-    V2 s = {0, 0};
-    if (ap < n) {
-      // the row and its block are the same for the whole wave (scalar registers)
-      const int off = __builtin_amdgcn_readfirstlane(info[3 * ap]);
-      const int sz = __builtin_amdgcn_readfirstlane(info[3 * ap + 1]);
-      const int po = __builtin_amdgcn_readfirstlane(info[3 * ap + 2]), rr = ap - off;
-      for (int k = 0; k < sz; ++k) cfma_conj(s, tile[(off + k) * w + lane], Gl[po + k * sz + rr]);
-    }
-    acc[i] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int ap = wave + 4 * i;
-    if (ap < n && lane < w) tile[ap * w + lane] = acc[i];
-  }
-  __syncthreads();
-  if (lane >= wv) return;
-  // right: W[a][q n + b'] = sum over b in the block of b' of Y[a][q n + b] conj(Gr[b'][b])
-  const int mq = lane / n, bp = lane - mq * n;
-  const int off = info[3 * (n + bp)], sz = info[3 * (n + bp) + 1], po = info[3 * (n + bp) + 2], cc = bp - off;
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) acc[i] = V2{0, 0};
-  for (int k = 0; k < sz; ++k) {
-    const V2 g = Gr[po + cc * sz + k];
-#pragma unroll
-    for (int i = 0; i < RPW; ++i) {
-      const int a = wave + 4 * i;
-      cfma_conj(acc[i], tile[min(a, n - 1) * w + mq * n + off + k], g);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int a = wave + 4 * i;
-    if (a < n) out[int64_t(a) * ncols + lane] = acc[i];
-  }
-}
-
-// Green's function blocks are staged in LDS when they fit next to the tile (LDS_CAP bytes).
-constexpr size_t LDS_CAP = 64 * 1024;
-
-template <typename V2, int CW>
-void launch_right_t(dim3 g, size_t el, size_t gmax, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab,
-                    int ncol) {
-  const size_t with = (el + 2 * gmax) * sizeof(V2);
-  if (with <= LDS_CAP) hipLaunchKernelGGL((k_rowblock_right<V2, CW, true>), g, dim3(256), with, s, sg, b, btab, ncol);
-  else hipLaunchKernelGGL((k_rowblock_right<V2, CW, false>), g, dim3(256), el * sizeof(V2), s, sg, b, btab, ncol);
-}
-
-void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, int gmax, hipStream_t s,
-                           bool fp32) {
-  if (l.nseg == 0) return;
-  const bool wide = ncol > 32;
-  const int rows = wide ? 32 : 64;
-  const dim3 g((l.maxrows + rows - 1) / rows, l.nseg);
-  const size_t el = size_t(rows) * ncol;
-  const RowSeg* sg = (const RowSeg*)l.segs;
-  if (fp32) {
-    if (wide) launch_right_t<float2, 64>(g, el, gmax, s, sg, b, btab, ncol);
-    else launch_right_t<float2, 32>(g, el, gmax, s, sg, b, btab, ncol);
-  } else {
-    if (wide) launch_right_t<double2, 64>(g, el, gmax, s, sg, b, btab, ncol);
-    else launch_right_t<double2, 32>(g, el, gmax, s, sg, b, btab, ncol);
-  }
-}
-
-template <typename V2, int RPW>
-void launch_both_r(dim3 g, int n, int w, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
-  const size_t ex = 6 * n * sizeof(int) + 16;
-  hipLaunchKernelGGL((k_rowblock_both<V2, RPW>), g, dim3(256), size_t(n) * w * sizeof(V2) + ex, s, sg, b, btab, n);
-}
-
-template <typename V2>
-void launch_both_t(dim3 g, int n, int w, hipStream_t s, const RowSeg* sg, const Bases& b, const int* btab) {
-  if (n <= 32) launch_both_r<V2, 8>(g, n, w, s, sg, b, btab);
-  else launch_both_r<V2, 16>(g, n, w, s, sg, b, btab);
-}
-
-void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s,
-                          bool fp32) {
-  if (l.nseg == 0) return;
-  const int w = rbb_nq(n) * n;
-  const dim3 g((l.maxrows + w - 1) / w, l.nseg);
-  const RowSeg* sg = (const RowSeg*)l.segs;
-  if (fp32) launch_both_t<float2>(g, n, w, s, sg, b, btab);
-  else launch_both_t<double2>(g, n, w, s, sg, b, btab);
-}
-
-// ----------------------------------------------------------------------------
 // Packed-block helpers.
 
 // out[blk] = Y[blk] + Y[blk]^H for every segment (one n x n block each).
@@ -1056,6 +832,25 @@ __global__ __launch_bounds__(256) void k_copy(const CopySeg* __restrict__ segs, 
   const double2* a = reinterpret_cast<const double2*>(bases.p[sg.inbuf]) + sg.in_off;
   double2* o = reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off;
   for (int64_t e = threadIdx.x; e < sg.len; e += 256) o[e] = a[e];
+}
+
+// Hermitian fill of n x n blocks whose lower triangle holds the result: X[a][b] = conj(X[b][a])
+// for a < b, in place; with out_off >= 0 the whole block is also copied there (the tau mirror).
+__global__ __launch_bounds__(256) void k_herm_fill(const CopySeg* __restrict__ segs, Bases bases) {
+  const CopySeg sg = segs[blockIdx.x];
+  double2* X = reinterpret_cast<double2*>(bases.p[sg.inbuf]) + sg.in_off;
+  double2* M = sg.out_off >= 0 ? reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off : nullptr;
+  const int n = sg.n;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int a = e / n, b = e - a * n;
+    const double2 v = a >= b ? X[e] : cconj(X[b * n + a]);
+    if (a < b) X[e] = v;
+    if (M) M[e] = v;
+  }
+}
+
+void launch_herm_fill(const void* segs, int nseg, const Bases& b, hipStream_t s) {
+  if (nseg) hipLaunchKernelGGL(k_herm_fill, dim3(nseg), dim3(256), 0, s, (const CopySeg*)segs, b);
 }
 
 // gather an n x n block with leading dimension len into a contiguous n x n block
@@ -1446,12 +1241,14 @@ void launch_hartree(const void* items, const int* first, int nib, int nitems, co
 
 // ----------------------------------------------------------------------------
 // Chemical potential bisection (one workgroup): N(mu) from the traces of G(i w_n) at the
-// current mu, then the bracket update.  state = [lo, hi, mu].
+// current mu, then the bracket update.  state = [lo, hi, mu].  probe 0 is one bisection step;
+// probe 1 checks the result after the last step: |N(mu) - N_target| above 1e-8 max(1, N_target)
+// means the bracket did not hold the root (status bit 2).
 
 __global__ __launch_bounds__(256) void k_mu_update(const MuItem* __restrict__ items, int nitems,
                                                    const double2* __restrict__ trace, const double2* __restrict__ Blast,
                                                    double scale, double ntarget, double* __restrict__ state,
-                                                   double* __restrict__ mu_out) {
+                                                   double* __restrict__ mu_out, int probe, int* __restrict__ status) {
   __shared__ double red[256];
   double s = 0.0;
   for (int e = threadIdx.x; e < nitems; e += 256) {
@@ -1468,6 +1265,10 @@ __global__ __launch_bounds__(256) void k_mu_update(const MuItem* __restrict__ it
   }
   if (threadIdx.x == 0) {
     const double N = -scale * red[0];
+    if (probe) {
+      if (!(fabs(N - ntarget) <= 1e-8 * fmax(1.0, fabs(ntarget)))) atomicOr(status, 2);
+      return;
+    }
     double lo = state[0], hi = state[1];
     const double mid = state[2];
     if (N < ntarget) lo = mid; else hi = mid;
@@ -1492,9 +1293,9 @@ void launch_mu_init(const double* eps_range, double* state, double* mu, hipStrea
   hipLaunchKernelGGL(k_mu_init, dim3(1), dim3(64), 0, s, eps_range, state, mu);
 }
 void launch_mu_update(const void* items, int nitems, const double* trace, const void* Blast, double scale,
-                      double ntarget, double* state, double* mu, hipStream_t s) {
+                      double ntarget, double* state, double* mu, int probe, int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_mu_update, dim3(1), dim3(256), 0, s, (const MuItem*)items, nitems, (const double2*)trace,
-                     (const double2*)Blast, scale, ntarget, state, mu);
+                     (const double2*)Blast, scale, ntarget, state, mu, probe, status);
 }
 
 // ----------------------------------------------------------------------------

@@ -110,9 +110,14 @@ struct GemmStage {
   // (e.g. zero off-diagonal blocks); by default the problem's own M N K T batch.  The
   // algorithmic bytes of a problem are one read of each operand and one write of C, in
   // complex128 (the fused block-diagonal factor is small and cached).
-  void add(const GemmProblem& p, double algo_macs = -1.0) {
+  // herm: the problem's output is Hermitian within each column batch (C[r][c] with c taken
+  // modulo cdiv); only the tiles that touch its lower triangle are generated, and the caller
+  // fills the upper triangle afterwards
+  std::vector<char> herm;
+  void add(const GemmProblem& p, double algo_macs = -1.0, bool lower_only = false) {
     pending.push_back(int(probs.size()));
     probs.push_back(p);
+    herm.push_back(lower_only ? 1 : 0);
     const double m = algo_macs >= 0 ? algo_macs : double(p.M) * p.N * p.K * double(p.T) * p.batch;
     macs += m;
     pending_macs += m;
@@ -144,6 +149,16 @@ struct GemmStage {
     pending_macs = 0;
     pending_bytes = 0;
     int slots = 0;
+    // a tile of rows [16 i, 16 (i + mh)) and columns [16 j, 16 (j + nn)) of a lower-only problem
+    // is needed when some row r and column c in it have r >= c mod cdiv
+    auto keep = [&](int id, int i, int mh, int j, int nn) {
+      const GemmProblem& p = probs[id];
+      if (!herm[id]) return true;
+      const int rmax = std::min(16 * (i + mh), p.M) - 1;
+      const int c0 = 16 * j, c1 = std::min(16 * (j + nn), p.N);
+      const int cmin = (c0 / p.cdiv != (c1 - 1) / p.cdiv) ? 0 : c0 % p.cdiv;
+      return rmax >= cmin;
+    };
     for (int id : pending) {
       const GemmProblem& p = probs[id];
       const int mu = units(p.M), nu = units(p.N);
@@ -159,17 +174,21 @@ struct GemmStage {
               // one full 32-column chunk per wave (a wave can walk several: nn = 2 x chunks),
               // a last 16-column unit on its own
               const int full = nu / 2;
-              for (int j = 0; j < full; j += per)
-                tiles.push_back({id, b, i, 2 * j, 0, p.T, -1, mh, 2 * std::min(per, full - j), 0});
-              if (nu % 2) tiles.push_back({id, b, i, 2 * full, 0, p.T, -1, mh, 1, 0});
+              for (int j = 0; j < full; j += per) {
+                const int nn = 2 * std::min(per, full - j);
+                if (keep(id, i, mh, 2 * j, nn)) tiles.push_back({id, b, i, 2 * j, 0, p.T, -1, mh, nn, 0});
+              }
+              if (nu % 2 && keep(id, i, mh, 2 * full, 1)) tiles.push_back({id, b, i, 2 * full, 0, p.T, -1, mh, 1, 0});
               continue;
             }
             for (int j = 0; j < nu; j += 16)   // up to eight 32-column chunks per workgroup
-              tiles.push_back({id, b, i, j, 0, p.T, -1, mh, std::min(16, nu - j), 0});
+              if (keep(id, i, mh, j, std::min(16, nu - j)))
+                tiles.push_back({id, b, i, j, 0, p.T, -1, mh, std::min(16, nu - j), 0});
             continue;
           }
           for (int j = 0; j < nu; j += 2) {
             const int nh = std::min(2, nu - j);
+            if (!keep(id, i, mh, j, nh)) continue;
             const int s0 = slots;
             for (int s = 0; s < split; ++s) {
               const int t0 = int(long(s) * p.T / split), t1 = int(long(s + 1) * p.T / split);
@@ -298,7 +317,7 @@ struct DevState {
   bool ws_exact = false;    // the next plan sizes the workspaces exactly (also shrinks them)
   void* partials = nullptr;
   size_t nslots = 0, partial_cap = 0;
-  double* scratch = nullptr;  // mu state (3), eps range (2), internal n_free (1)
+  double* mu_state = nullptr;  // mu state (3), eps range (2), internal n_free (1)
   double* trace = nullptr;
   double* occ = nullptr;
   double* erange = nullptr;
@@ -323,13 +342,23 @@ struct DevState {
   void* hj_rho = nullptr;
   int hj_nitems = 0;
   ListStage<CopySeg> p0_mirror, scr_herm, dys_herm, s_pack;
+  // launch order of the contractions: per step one block-multiply launch and ranges of GEMM
+  // launches (one step per tau chunk; in the unbatched schedule one per pair)
+  struct P0Step {
+    int both, g0, g1;
+  };
+  struct SStep {
+    int a0, a1, right, c0, c1;
+  };
+  std::vector<P0Step> p0_steps;
+  std::vector<SStep> s_steps;
+  std::vector<std::array<int, 3>> s_chunks;   // (first step, end step, gather launch) per chunk
   void* SCR = nullptr;      // full nao x nao self-energy products of one tau chunk
   ListStage<InvItem> scr_inv, dys_inv, mu_inv;
   ListStage<MuItem> mu_items;
   ListStage<EigItem> g0_items;
   std::vector<void*> allocs;
   Prof prof;
-  int gmax = 0;                          // largest packed orbital block-diagonal matrix
   hipGraphExec_t graph_exec = nullptr;   // captured iteration and the arguments it was captured with
   std::vector<const void*> graph_key;
   double graph_ntarget = 0;
@@ -466,6 +495,11 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
     dfree(d, l->d);
     *l = ListStage<CopySeg>{};
   }
+  d.p0_steps.clear();
+  d.s_steps.clear();
+  d.s_chunks.clear();
+  // unbatched: every pair's block multiply and every (pair, block) GEMM its own launch, in order
+  const bool ub = c.prm.sched == GWSYM_SCHED_UNBATCHED;
   if (d.graph_exec) {
     hipGraphExecDestroy(d.graph_exec);
     d.graph_exec = nullptr;
@@ -515,13 +549,12 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
     std::vector<int> kq(nk);
     for (int k = 0; k < nk; ++k) kq[k] = mesh.add(k, q0);
     for (int j0 = 0; j0 < nthalf; j0 += J) {
-      const int j1 = std::min(nthalf, j0 + J);
-      for (int j = j0; j < j1; ++j) {
-        const int jj = j - j0;
-        for (int k = 0; k < nk; ++k) {
-          const int ik = c.rep[k], ikq = c.rep[kq[k]];
+      const int j1 = std::min(nthalf, j0 + J), jc = j1 - j0;
+      auto segs = [&](int k) {
+        const int ik = c.rep[k], ikq = c.rep[kq[k]];
+        for (int j = j0; j < j1; ++j) {
           const i64 vp = (i64(i) * nk + k) * na * no * no;
-          const i64 wo = (i64(jj) * nk + k) * na * no * no;
+          const i64 wo = (i64(j - j0) * nk + k) * na * no * no;
           RowSeg r{};
           r.inbuf = B_VP; r.outbuf = B_W2; r.gbuf = B_G;
           r.blk = d.bt_ao[ik]; r.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed;
@@ -529,29 +562,52 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
           r.in_off = vp; r.out_off = wo; r.nrows = na * no;
           d.p0_both.add(r, double(na) * no * (sumsq_ao[ik] + sumsq_ao[ikq]), double(na) * no * no);
         }
-      }
+      };
       // one problem per auxiliary block for all tau of the chunk: the columns are (tau, Q'), so
-      // the Vp rows of the block are read once for every tau and small blocks fill the tiles
-      const int jc = j1 - j0;
-      for (size_t sg = 0; sg < BA.size.size(); ++sg) {
+      // the Vp rows of the block are read once for every tau and small blocks fill the tiles;
+      // the outer sum runs over the nkc points from k0 (all of them, or one pair unbatched)
+      auto gemm = [&](size_t sg, int k0, int nkc, int beta) {
         const int m = BA.size[sg], off = BA.off[sg];
         // A_(k,a) = Vp[i][k][a][rows of block sg][:], B_(k,a) = W[tau][k][a][rows of block sg][:]
-        GemmProblem p = gp(m, jc * m, no, nk * no, 1, B_VP, i64(i) * nk * na * no * no + i64(off) * no, no,
-                           i64(na) * no, 0, OP_N, B_W2, i64(off) * no, no, i64(na) * no, 0, OP_H, B_OUT,
-                           c.p_off[i] + i64(j0) * BA.packed + BA.poff[sg], m, 0, pscale);
+        const i64 ko = i64(k0) * na * no * no;
+        GemmProblem p = gp(m, jc * m, no, nkc * no, 1, B_VP, i64(i) * nk * na * no * no + ko + i64(off) * no, no,
+                           i64(na) * no, 0, OP_N, B_W2, ko + i64(off) * no, no, i64(na) * no, 0, OP_H, B_OUT,
+                           c.p_off[i] + i64(j0) * BA.packed + BA.poff[sg], m, 0, pscale, 0.0, beta);
         p.cdiv = m;
         p.sBcb = slab;
         p.sCcb = BA.packed;
-        d.p0_gemm.add(p, double(jc) * m * m * no * nk * no);
+        // P0^q(tau) is Hermitian (so is every term of the k sum, G being Hermitian): only the
+        // tiles on or below the diagonal are computed
+        d.p0_gemm.add(p, double(jc) * m * (m + 1) / 2 * no * nkc * no, true);
+      };
+      if (!ub) {
+        for (int k = 0; k < nk; ++k) segs(k);
+        for (size_t sg = 0; sg < BA.size.size(); ++sg) gemm(sg, 0, nk, 0);
+        d.p0_both.close();
+        d.p0_gemm.close();
+        const int l = int(d.p0_gemm.launches.size());
+        d.p0_steps.push_back({int(d.p0_both.launches.size()) - 1, l - 1, l});
+      } else {
+        for (int k = 0; k < nk; ++k) {
+          segs(k);
+          d.p0_both.close();
+          const int g0 = int(d.p0_gemm.launches.size());
+          for (size_t sg = 0; sg < BA.size.size(); ++sg) {
+            gemm(sg, k, 1, k > 0);
+            d.p0_gemm.close();
+          }
+          d.p0_steps.push_back({int(d.p0_both.launches.size()) - 1, g0, int(d.p0_gemm.launches.size())});
+        }
       }
-      d.p0_both.close();
-      d.p0_gemm.close();
     }
-    if (c.prm.half_tau)
-      for (int j = 0; j < nt / 2; ++j)
-        if (nt - 1 - j != j)
-          d.p0_mirror.items.push_back({B_OUT, B_OUT, 0, 0, c.p_off[i] + i64(j) * BA.packed,
-                                       c.p_off[i] + i64(nt - 1 - j) * BA.packed, BA.packed});
+    // upper triangles from the lower ones; with half tau also the mirrored tau
+    for (int j = 0; j < nthalf; ++j)
+      for (size_t sg = 0; sg < BA.size.size(); ++sg) {
+        const i64 o = c.p_off[i] + i64(j) * BA.packed + BA.poff[sg];
+        const bool mir = c.prm.half_tau && nt - 1 - j != j;
+        d.p0_mirror.items.push_back({B_OUT, B_OUT, BA.size[sg], 0, o,
+                                     mir ? c.p_off[i] + i64(nt - 1 - j) * BA.packed + BA.poff[sg] : -1, 0});
+      }
   }
   d.p0_mirror.close();
 
@@ -604,7 +660,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
       }
       // Y = P_blk^T Vs with the rows (unit, s') in one problem per (k', auxiliary block): the Vs
       // rows are read once for every tau of the chunk
-      for (int kp = 0; kp < nk; ++kp) {
+      auto gemmA = [&](int kp, bool each) {
         const int q = mesh.sub(k0, kp), iq = c.rep[q];
         const Blocks& BQ = c.baux[iq];
         const i64 vs = (i64(i) * nk + kp) * na * no * no;
@@ -617,15 +673,16 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
           p.sArb = BQ.packed;
           p.sCrb = slab;
           d.s_gemmA.add(p);
+          if (each) d.s_gemmA.close();
         }
-      }
+      };
       // Z(tau) = Y(unit) G^{k'}(tau) for every tau of the chunk; a unit's Y is read once for
       // both of its tau
-      for (int sl = 0; sl < nslot; ++sl) {
-        if (sl > 0 && slot_unit[sl] == slot_unit[sl - 1]) continue;   // the mirror slot, done below
-        const bool pair = sl + 1 < nslot && slot_unit[sl + 1] == slot_unit[sl];
-        for (int kp = 0; kp < nk; ++kp) {
-          const int ik = c.rep[kp];
+      auto right = [&](int kp) {
+        const int ik = c.rep[kp];
+        for (int sl = 0; sl < nslot; ++sl) {
+          if (sl > 0 && slot_unit[sl] == slot_unit[sl - 1]) continue;   // the mirror slot, done below
+          const bool pair = sl + 1 < nslot && slot_unit[sl + 1] == slot_unit[sl];
           RowSeg r{};
           r.inbuf = B_W1; r.outbuf = B_W2; r.gbuf = B_G; r.blk = d.bt_ao[ik];
           r.in_off = (i64(slot_unit[sl]) * nk + kp) * na * no * no;
@@ -639,22 +696,48 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
           r.nrows = na * no;
           d.s_right.add(r, double(na) * no * sumsq_ao[ik] * (pair ? 2 : 1), double(na) * no * no * (pair ? 1.5 : 1));
         }
-      }
+      };
       // only the diagonal blocks of Sigma are kept: consecutive orbital blocks are grouped into
       // bins of at most 16 rows and each bin's diagonal square is one problem, with the rows
-      // (slot, a) of all tau of the chunk stacked
-      for (const auto& bn : bins_ao[i]) {
-        const int r0 = bn.first, nb = bn.second;
-        GemmProblem p = gp(nslot * nb, nb, no, nk * na, 1, B_W2, i64(r0) * no, no, i64(no) * no, 0, OP_N, B_VS,
-                           i64(i) * nk * na * no * no + i64(r0) * no, no, i64(no) * no, 0, OP_H, B_SCR,
-                           i64(r0) * no + r0, no, 0, -1.0 / nk);
-        p.rdiv = nb;
-        p.sArb = slab;
-        p.sCrb = i64(no) * no;
-        double algo = 0;
-        for (size_t rb = 0; rb < BO.size.size(); ++rb)
-          if (BO.off[rb] >= r0 && BO.off[rb] < r0 + nb) algo += double(BO.size[rb]) * BO.size[rb];
-        d.s_gemmC.add(p, double(nslot) * algo * no * double(nk) * na);
+      // (slot, a) of all tau of the chunk stacked; the outer sum runs over the nkc points from kp0
+      auto gemmC = [&](int kp0, int nkc, bool each) {
+        for (const auto& bn : bins_ao[i]) {
+          const int r0 = bn.first, nb = bn.second;
+          const i64 ko = i64(kp0) * na * no * no;
+          GemmProblem p = gp(nslot * nb, nb, no, nkc * na, 1, B_W2, ko + i64(r0) * no, no, i64(no) * no, 0, OP_N, B_VS,
+                             i64(i) * nk * na * no * no + ko + i64(r0) * no, no, i64(no) * no, 0, OP_H, B_SCR,
+                             i64(r0) * no + r0, no, 0, -1.0 / nk, 0.0, kp0 > 0 ? 1 : 0);
+          p.rdiv = nb;
+          p.sArb = slab;
+          p.sCrb = i64(no) * no;
+          double algo = 0;
+          for (size_t rb = 0; rb < BO.size.size(); ++rb)
+            if (BO.off[rb] >= r0 && BO.off[rb] < r0 + nb) algo += double(BO.size[rb]) * BO.size[rb];
+          d.s_gemmC.add(p, double(nslot) * algo * no * double(nkc) * na);
+          if (each) d.s_gemmC.close();
+        }
+      };
+      const int step0 = int(d.s_steps.size());
+      if (!ub) {
+        for (int kp = 0; kp < nk; ++kp) gemmA(kp, false);
+        for (int kp = 0; kp < nk; ++kp) right(kp);
+        gemmC(0, nk, false);
+        d.s_gemmA.close();
+        d.s_right.close();
+        d.s_gemmC.close();
+        const int la = int(d.s_gemmA.launches.size()), lc = int(d.s_gemmC.launches.size());
+        d.s_steps.push_back({la - 1, la, int(d.s_right.launches.size()) - 1, lc - 1, lc});
+      } else {
+        for (int kp = 0; kp < nk; ++kp) {
+          const int a0 = int(d.s_gemmA.launches.size());
+          gemmA(kp, true);
+          right(kp);
+          d.s_right.close();
+          const int c0 = int(d.s_gemmC.launches.size());
+          gemmC(kp, 1, true);
+          d.s_steps.push_back({a0, int(d.s_gemmA.launches.size()), int(d.s_right.launches.size()) - 1, c0,
+                               int(d.s_gemmC.launches.size())});
+        }
       }
       for (int sl = 0; sl < nslot; ++sl)
         for (size_t rb = 0; rb < BO.size.size(); ++rb) {
@@ -662,10 +745,8 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
           d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(sl) * no * no + i64(off) * no + off,
                                     c.g_off[i] + i64(slot_tau[sl]) * BO.packed + BO.poff[rb], no});
         }
-      d.s_gemmA.close();
-      d.s_right.close();
-      d.s_gemmC.close();
       d.s_pack.close();
+      d.s_chunks.push_back({step0, int(d.s_steps.size()), int(d.s_pack.launches.size()) - 1});
       u0 = u1;
     }
   }
@@ -690,7 +771,6 @@ int device_init(Ctx& c, void* stream) {
   DevState& d = *dp;
   const int nk = c.nk, no = c.nao, na = c.naux, nt = c.ntau, nw = c.nw, nib = c.nibz;
   d.p0_gemm.wave = d.s_gemmA.wave = d.s_gemmC.wave = true;
-  for (int i = 0; i < nib; ++i) d.gmax = std::max<int>(d.gmax, int(c.bao[i].packed));
   int st;
   // U tables
   {
@@ -833,10 +913,14 @@ int device_init(Ctx& c, void* stream) {
     // V_S(s) = sum_Q U_{Qs} V(Q), so a density vector maps as rho_s = (U^H rho)_s and the
     // projector (1/|G|) sum_g Obar(g) becomes U^H Pi U
     const int kg = mesh.sub(c.ibz[0], c.ibz[0]);
-    CMat Pi(na, na);
-    for (int a = 0; a < c.nop; ++a) {
-      const CMat O = orbital_rep(c, true, a, kg);
-      for (size_t e = 0; e < Pi.a.size(); ++e) Pi.a[e] += O.a[e] / double(c.nop);
+    // (without symmetry every point is summed explicitly: no projection)
+    CMat Pi = CMat::eye(na);
+    if (c.prm.mode != GWSYM_MODE_FULL) {
+      Pi = CMat(na, na);
+      for (int a = 0; a < c.nop; ++a) {
+        const CMat O = orbital_rep(c, true, a, kg);
+        for (size_t e = 0; e < Pi.a.size(); ++e) Pi.a[e] += O.a[e] / double(c.nop);
+      }
     }
     const CMat P2 = matmul(Pi, Pi);
     double dev2 = 0;
@@ -976,7 +1060,7 @@ int device_init(Ctx& c, void* stream) {
   }
   void* t;
   if ((st = dalloc(c, d, &t, 16 * sizeof(double)))) return st;
-  d.scratch = static_cast<double*>(t);
+  d.mu_state = static_cast<double*>(t);
   if ((st = dalloc(c, d, &t, std::max<size_t>(1, d.mu_inv.items.size()) * 2 * sizeof(double)))) return st;
   d.trace = static_cast<double*>(t);
   if ((st = dalloc(c, d, &t, std::max<size_t>(1, d.g0_items.items.size()) * sizeof(double)))) return st;
@@ -987,7 +1071,7 @@ int device_init(Ctx& c, void* stream) {
   if ((st = dalloc(c, d, &t, sizeof(int)))) return st;
   d.status = static_cast<int*>(t);
   HIPCHECK(hipMemsetAsync(d.status, 0, sizeof(int), s));
-  HIPCHECK(hipMemsetAsync(d.scratch, 0, 16 * sizeof(double), s));
+  HIPCHECK(hipMemsetAsync(d.mu_state, 0, 16 * sizeof(double), s));
   HIPCHECK(hipStreamSynchronize(s));
   c.dev = true;
   return GWSYM_OK;
@@ -1246,7 +1330,7 @@ int device_g0(Ctx& c, const void* F, double mu, void* G, double* nfree, void* st
   b.p[B_OUT] = G;
   const int n = int(d.g0_items.items.size());
   launch_jacobi_g0(d.g0_items.d, n, b, d.tau, c.ntau, c.prm.beta, mu, d.occ, d.erange, d.vwork, s);
-  launch_g0_reduce(d.occ, d.wts, d.erange, n, c.prm.spin / c.nk, nfree ? nfree : d.scratch + 5, d.scratch + 3, s);
+  launch_g0_reduce(d.occ, d.wts, d.erange, n, c.prm.spin / c.nk, nfree ? nfree : d.mu_state + 5, d.mu_state + 3, s);
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
 }
@@ -1270,15 +1354,18 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
     b.p[B_VP] = d.VP32;
     mask = 1u << B_W2;
   }
-  for (size_t l = 0; l < d.p0_gemm.launches.size(); ++l) {
-    const Range& rb = d.p0_both.launches[l];
+  for (const auto& st : d.p0_steps) {
+    const Range& rb = d.p0_both.launches[st.both];
     RowSegList L{static_cast<RowSeg*>(d.p0_both.d) + rb.t0, rb.nt, rb.r0};
     timed(d, s, PC_LEFT, rb.macs, [&] { launch_rowblock_both(L, b, d.btab, c.nao, s, f32); }, rb.bytes);
-    const Range& rg = d.p0_gemm.launches[l];
-    timed(d, s, PC_P0, rg.macs, [&] { launch_wgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, arith, mask); }, rg.bytes);
+    for (int l = st.g0; l < st.g1; ++l) {
+      const Range& rg = d.p0_gemm.launches[l];
+      timed(d, s, PC_P0, rg.macs, [&] { launch_wgemm(plan_of(d.p0_gemm, rg), b, d.partials, s, 1, arith, mask); },
+            rg.bytes);
+    }
   }
   const Range& m = d.p0_mirror.launches[0];
-  timed(d, s, PC_OTHER, 0, [&] { launch_copy(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s); });
+  timed(d, s, PC_OTHER, 0, [&] { launch_herm_fill(static_cast<CopySeg*>(d.p0_mirror.d) + m.t0, m.nt, b, s); });
   HIPCHECK(hipGetLastError());
   c.last_macs[0] = d.p0_gemm.macs;
   return GWSYM_OK;
@@ -1304,15 +1391,24 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
     b.p[B_VS] = d.VS32;
     mask = (1u << B_W1) | (1u << B_W2);
   }
-  for (size_t l = 0; l < d.s_gemmA.launches.size(); ++l) {
-    const Range& ra = d.s_gemmA.launches[l];
-    timed(d, s, PC_SA, ra.macs, [&] { launch_wgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, arith, mask); }, ra.bytes);
-    const Range& rr = d.s_right.launches[l];
-    RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
-    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, d.gmax, s, f32); }, rr.bytes);
-    const Range& rc = d.s_gemmC.launches[l];
-    timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, arith, mask); }, rc.bytes);
-    const Range& rp = d.s_pack.launches[l];
+  for (const auto& ch : d.s_chunks) {
+    for (int si = ch[0]; si < ch[1]; ++si) {
+      const auto& st = d.s_steps[si];
+      for (int l = st.a0; l < st.a1; ++l) {
+        const Range& ra = d.s_gemmA.launches[l];
+        timed(d, s, PC_SA, ra.macs, [&] { launch_wgemm(plan_of(d.s_gemmA, ra), b, d.partials, s, 2, arith, mask); },
+              ra.bytes);
+      }
+      const Range& rr = d.s_right.launches[st.right];
+      RowSegList R{static_cast<RowSeg*>(d.s_right.d) + rr.t0, rr.nt, rr.r0};
+      timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s, f32); }, rr.bytes);
+      for (int l = st.c0; l < st.c1; ++l) {
+        const Range& rc = d.s_gemmC.launches[l];
+        timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.s_gemmC, rc), b, d.partials, s, 3, arith, mask); },
+              rc.bytes);
+      }
+    }
+    const Range& rp = d.s_pack.launches[ch[2]];
     timed(d, s, PC_OTHER, 0, [&] { launch_pack(static_cast<CopySeg*>(d.s_pack.d) + rp.t0, rp.nt, b, s); });
   }
   HIPCHECK(hipGetLastError());
@@ -1335,7 +1431,7 @@ int device_exchange(Ctx& c, const void* G, void* K, void* stream) {
   for (size_t l = 0; l < d.hx_gemm.launches.size(); ++l) {
     const Range& rr = d.hx_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.hx_right.d) + rr.t0, rr.nt, rr.r0};
-    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, d.gmax, s, false); }, rr.bytes);
+    timed(d, s, PC_RIGHT, rr.macs, [&] { launch_rowblock_right(R, b, d.btab, c.nao, s, false); }, rr.bytes);
     const Range& rc = d.hx_gemm.launches[l];
     timed(d, s, PC_SC, rc.macs, [&] { launch_wgemm(plan_of(d.hx_gemm, rc), b, d.partials, s, 3, 0, 0u); }, rc.bytes);
     const Range& rp = d.hx_pack.launches[l];
@@ -1392,6 +1488,28 @@ int device_screened(Ctx& c, const void* P0, void* P, void* stream) {
   return GWSYM_OK;
 }
 
+namespace {
+
+// eq. dyson on the bases given: Sigma(tau) -> Sigma(i w) into B_W1, the inverses into B_W2,
+// i w -> tau into B_W1 and the Hermitian sum into G.  The two frequency workspaces and the
+// split-K partial tiles are whatever the caller passes.
+void dyson_launches(Ctx& c, DevState& d, Bases& b, void* partials, const double* mu, hipStream_t s, bool prof) {
+  auto run = [&](int cls, double macs, auto f) {
+    if (prof) timed(d, s, cls, macs, f);
+    else f();
+  };
+  run(PC_XFORM, d.dys_fwd.launches[0].macs,
+      [&] { launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, partials, s); });
+  run(PC_INV, 0.0, [&] {
+    launch_inverse(d.dys_inv.d, int(d.dys_inv.items.size()), nmax_of(d.dys_inv), b, INV_G, mu, nullptr, d.status, s);
+  });
+  run(PC_XFORM, d.dys_bwd.launches[0].macs,
+      [&] { launch_brgemm(plan_of(d.dys_bwd, d.dys_bwd.launches[0]), b, partials, s); });
+  run(PC_OTHER, 0.0, [&] { launch_herm(d.dys_herm.d, int(d.dys_herm.items.size()), b, s); });
+}
+
+}  // namespace
+
 int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevState& d = *static_cast<DevState*>(c.dev_state);
@@ -1401,14 +1519,7 @@ int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G
   b.p[B_IN] = const_cast<void*>(S);
   b.p[B_F] = const_cast<void*>(F);
   b.p[B_OUT] = G;
-  timed(d, s, PC_XFORM, d.dys_fwd.launches[0].macs,
-        [&] { launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s); });
-  timed(d, s, PC_INV, 0,
-        [&] { launch_inverse(d.dys_inv.d, int(d.dys_inv.items.size()), nmax_of(d.dys_inv), b, INV_G, mu, nullptr, d.status,
-                       s); });
-  timed(d, s, PC_XFORM, d.dys_bwd.launches[0].macs,
-        [&] { launch_brgemm(plan_of(d.dys_bwd, d.dys_bwd.launches[0]), b, d.partials, s); });
-  timed(d, s, PC_OTHER, 0, [&] { launch_herm(d.dys_herm.d, int(d.dys_herm.items.size()), b, s); });
+  dyson_launches(c, d, b, d.partials, mu, s, true);
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
 }
@@ -1418,41 +1529,65 @@ int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double*
   DevState& d = *static_cast<DevState*>(c.dev_state);
   int st;
   if ((st = need_partials(c, d))) return st;
+  for (const EigItem& e : d.g0_items.items)
+    if (e.n > JAC_N) return c.err = "orbital block larger than 60 in find_mu", GWSYM_ESHAPE;
   Bases b = bases_of(d);
   b.p[B_IN] = const_cast<void*>(S);
   b.p[B_F] = const_cast<void*>(F);
+  // bracket from the spectrum of the F passed in: the block eigen-solver of g0 with no tau
+  // points (eigenvalue range only, no Green's function written)
+  const int ng = int(d.g0_items.items.size());
+  timed(d, s, PC_OTHER, 0, [&] {
+    launch_jacobi_g0(d.g0_items.d, ng, b, d.tau, 0, c.prm.beta, 0.0, d.occ, d.erange, d.vwork, s);
+    launch_g0_reduce(d.occ, d.wts, d.erange, ng, c.prm.spin / c.nk, d.mu_state + 5, d.mu_state + 3, s);
+  });
   timed(d, s, PC_XFORM, d.dys_fwd.launches[0].macs,
         [&] { launch_brgemm(plan_of(d.dys_fwd, d.dys_fwd.launches[0]), b, d.partials, s); });
   const void* Blast = static_cast<const cplx*>(d.TR) + 2 * i64(c.nw) * c.ntau + i64(c.ntau - 1) * c.nw;
-  launch_mu_init(d.scratch + 3, d.scratch, mu, s);
+  launch_mu_init(d.mu_state + 3, d.mu_state, mu, s);
   const int n = int(d.mu_inv.items.size());
-  for (int it = 0; it < 64; ++it) {
+  // a fixed 64 bisection steps, all on the device, then N at the result: a residual above
+  // 1e-8 N_target is flagged (the root was outside the bracket)
+  for (int it = 0; it < 65; ++it) {
+    const int probe = it == 64;
     timed(d, s, PC_INV, 0, [&] { launch_inverse(d.mu_inv.d, n, nmax_of(d.mu_inv), b, INV_TRACE, mu, d.trace, d.status, s); });
     timed(d, s, PC_OTHER, 0, [&] {
-      launch_mu_update(d.mu_items.d, n, d.trace, Blast, c.prm.spin / c.nk, ntarget, d.scratch, mu, s);
+      launch_mu_update(d.mu_items.d, n, d.trace, Blast, c.prm.spin / c.nk, ntarget, d.mu_state, mu, probe, d.status, s);
     });
   }
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
 }
 
+// Reads and clears the device status word of the context after the work queued on `stream`:
+// bit 0 a singular matrix in a Dyson inverse, bit 1 a chemical potential search whose result
+// missed N_target.
+int device_check(Ctx& c, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int h = 0;
+  HIPCHECK(hipMemcpyAsync(&h, d.status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (h == 0) return GWSYM_OK;
+  HIPCHECK(hipMemsetAsync(d.status, 0, sizeof(int), s));
+  HIPCHECK(hipStreamSynchronize(s));
+  if (h & 1) {
+    c.err = "a matrix of a Dyson equation (I - P0 or (i w + mu) - F - Sigma) was singular";
+    return GWSYM_ESINGULAR;
+  }
+  c.err = "the chemical potential search missed N_target (its root was outside the bracket)";
+  return GWSYM_ENOCONV;
+}
+
 int device_iteration(Ctx& c, const void* H0, const void* F, void* G, void* P0, void* P, void* S, double* mu,
                      double ntarget, int use_graph, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevState& d = *static_cast<DevState*>(c.dev_state);
-  if (H0 && d.ws_elems < size_t(c.g_off[c.nibz])) {
-    c.err = "workspace smaller than one Green's function";
-    return GWSYM_ESHAPE;
-  }
   auto body = [&]() -> int {
     int st;
-    // self-consistent form: F = H0 + J + K from the same G as the polarization and Sigma; the
-    // bracket of the mu search then comes from the spectrum of the new F (the block eigen-solver
-    // of g0, its free G written into the workspace, which the stages below overwrite)
-    if (H0) {
-      if ((st = device_fock(c, H0, G, const_cast<void*>(F), stream))) return st;
-      if ((st = device_g0(c, F, 0.0, d.W1, nullptr, stream))) return st;
-    }
+    // self-consistent form: F = H0 + J + K from the same G as the polarization and Sigma (the
+    // mu search brackets its root from the spectrum of this new F)
+    if (H0 && (st = device_fock(c, H0, G, const_cast<void*>(F), stream))) return st;
     if ((st = device_polarization(c, G, P0, stream))) return st;
     if ((st = device_screened(c, P0, P, stream))) return st;
     if ((st = device_self_energy(c, G, P, S, stream))) return st;

@@ -20,6 +20,7 @@ lib = C.CDLL(_LIB_PATH)
 
 MODE_FULL, MODE_ROTATE, MODE_BLOCK = 0, 1, 2
 FP64, FP32, BF16X6, BF16X3 = 0, 1, 2, 3
+SCHED_GROUPED, SCHED_UNBATCHED = 0, 1
 KIND_F, KIND_G, KIND_P = 0, 1, 2
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ESINGULAR", -6: "ENOCONV",
@@ -28,7 +29,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ES
 
 class Params(C.Structure):
     _fields_ = [("beta", C.c_double), ("ntau", C.c_int), ("nw", C.c_int), ("spin", C.c_double),
-                ("mode", C.c_int), ("precision", C.c_int), ("half_tau", C.c_int), ("tau_chunk", C.c_int)]
+                ("mode", C.c_int), ("precision", C.c_int), ("half_tau", C.c_int), ("tau_chunk", C.c_int),
+                ("sched", C.c_int)]
 
 
 class Crystal(C.Structure):
@@ -88,6 +90,7 @@ lib.gwsym_autotune.argtypes = [_vp, _vp, C.POINTER(Tuning)]
 lib.gwsym_get_tuning.argtypes = [_vp, C.POINTER(Tuning)]
 lib.gwsym_set_tuning.argtypes = [_vp, C.POINTER(Tuning), _vp]
 lib.gwsym_flop_counts.argtypes = [_vp, C.POINTER(C.c_double)]
+lib.gwsym_check.argtypes = [_vp, _vp]
 lib.gwsym_profile.argtypes = [_vp, C.c_int]
 lib.gwsym_profile_read.argtypes = [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]
@@ -97,7 +100,7 @@ EXPORTED = ["gwsym_create", "gwsym_destroy", "gwsym_last_error", "gwsym_build_sy
             "gwsym_from_block", "gwsym_g0", "gwsym_polarization", "gwsym_screened_interaction",
             "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_exchange",
             "gwsym_hartree", "gwsym_fock", "gwsym_scf_iteration", "gwsym_autotune", "gwsym_get_tuning",
-            "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read"]
+            "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read", "gwsym_check"]
 
 PROFILE_CLASSES = ["p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction", "row_block_multiply",
                    "two_sided_block_multiply", "transforms", "inverses", "other"]
@@ -125,8 +128,9 @@ def _stream(stream):
 class Context:
     """One symmetry-adapted GW problem: crystal, mesh, bases, grids, device state."""
 
-    def __init__(self, beta, ntau, nw, spin=2.0, mode=MODE_BLOCK, precision=FP64, half_tau=True, tau_chunk=0):
-        self.params = Params(beta, ntau, nw, spin, mode, precision, int(half_tau), tau_chunk)
+    def __init__(self, beta, ntau, nw, spin=2.0, mode=MODE_BLOCK, precision=FP64, half_tau=True, tau_chunk=0,
+                 sched=SCHED_GROUPED):
+        self.params = Params(beta, ntau, nw, spin, mode, precision, int(half_tau), tau_chunk, sched)
         h = _vp()
         self._check(lib.gwsym_create(C.byref(self.params), C.byref(h)), None)
         self.h = h
@@ -258,13 +262,19 @@ class Context:
         self._check(lib.gwsym_iteration(self.h, _ptr(F_blk), _ptr(G_blk), _ptr(P0_blk), _ptr(P_blk), _ptr(S_blk),
                                         _ptr(mu), float(n_target or 0.0), int(bool(use_graph)), _stream(stream)))
 
+    def check(self, stream=None):
+        """Waits for the queued work and raises GwsymError for a flagged singular inverse
+        (ESINGULAR) or an unbracketed chemical potential (ENOCONV); clears the flags."""
+        self._check(lib.gwsym_check(self.h, _stream(stream)))
+
     # -- launch plan ----------------------------------------------------------------
     def plan_key(self):
         """Hash of what a contraction plan depends on: parameters, sizes and block structure."""
         import hashlib
         h = hashlib.sha256()
         p = self.params
-        h.update(repr((p.beta, p.ntau, p.nw, p.mode, p.precision, p.half_tau)).encode())
+        h.update(repr((p.beta, p.ntau, p.nw, p.mode, p.precision, p.half_tau)
+                      + ((p.sched,) if p.sched else ())).encode())
         for name in ("dims", "ibz", "rep", "ao_blocks", "aux_blocks"):
             h.update(self.table(name).tobytes())
         return h.hexdigest()

@@ -44,11 +44,11 @@ def oracle_run(name, iterations=1):
 class DeviceRun:
     """Device buffers and calls of one workload in one mode."""
 
-    def __init__(self, name, mode, half_tau=True, tau_chunk=0, precision=0, identity_only=False):
+    def __init__(self, name, mode, half_tau=True, tau_chunk=0, precision=0, identity_only=False, sched=0):
         wl, inp, F, V = inputs(name)
         self.wl = wl
         self.ctx = make_context(wl, mode=mode, half_tau=half_tau, tau_chunk=tau_chunk, precision=precision,
-                                identity_only=identity_only)
+                                identity_only=identity_only, sched=sched)
         c = self.ctx
         dev = torch.device("cuda:0")
         self.dev = dev

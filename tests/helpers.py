@@ -10,13 +10,13 @@ def crystal_arrays(cr):
     return cr.lattice, cr.positions, rot, trans
 
 
-def make_context(wl, mode=None, precision=0, half_tau=True, tau_chunk=0, build=True, identity_only=False):
+def make_context(wl, mode=None, precision=0, half_tau=True, tau_chunk=0, build=True, identity_only=False, sched=0):
     """identity_only: give the library the trivial group (every block is the whole matrix,
     every mesh point is irreducible) although the inputs have the crystal's symmetry."""
     from paper_2405_09494_amd import gwsym
     if mode is None:
         mode = gwsym.MODE_BLOCK
-    ctx = gwsym.Context(wl.beta, wl.ntau, wl.nw, wl.spin, mode, precision, half_tau, tau_chunk)
+    ctx = gwsym.Context(wl.beta, wl.ntau, wl.nw, wl.spin, mode, precision, half_tau, tau_chunk, sched)
     if build:
         cr = crystal(wl.crystal)
         lat, pos, rot, trans = crystal_arrays(cr)

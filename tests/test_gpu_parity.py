@@ -47,7 +47,7 @@ def test_g0(name, mode):
 CASES = [("cfg0", "full"), ("cfg0", "block"), ("small_sc2", "block"), ("small_rocksalt", "block"),
          ("small_rocksalt", "rotate"), ("small_diamond", "block"), ("small_diamond", "rotate"),
          ("small_diamond", "full"), ("small_sc4", "block"), ("wide_rocksalt", "block"), ("wide_diamond", "block"),
-         ("wide_diamond", "rotate")]
+         ("wide_diamond", "rotate"), ("small_hbn", "block"), ("small_hbn", "rotate"), ("small_hbn3", "block")]
 
 
 @pytest.mark.parametrize("name,mode", CASES)
@@ -87,6 +87,23 @@ def test_degenerate(name, mode, identity_only):
     """A single k point, and the trivial group (one block per matrix, every point irreducible)."""
     say(f"[degenerate] {name} {mode} identity_only={identity_only}")
     run = DeviceRun(name, MODES[mode], identity_only=identity_only)
+    ref = oracle_run(name)
+    r = ref["iters"][0]
+    run.g0()
+    c = run.ctx
+    c.iteration(run.F, run.G, run.P0, run.P, run.S, run.mu, ref["n_target"] or 0.0)
+    for kind, buf, key in ((2, run.P0, "P0"), (2, run.P, "P"), (1, run.S, "Sigma"), (1, run.G, "G")):
+        e = rel(run.full(kind, buf), r[key])
+        say(f"  {key} {e:.2e}")
+        assert e < TOL
+
+
+@pytest.mark.parametrize("name,mode", [("small_diamond", "block"), ("small_sc4", "block"), ("cfg0", "full"),
+                                       ("wide_rocksalt", "block")])
+def test_unbatched_schedule(name, mode):
+    """The per-pair, per-block schedule (one launch each, one after another) meets the same bar."""
+    say(f"[unbatched] {name} {mode}")
+    run = DeviceRun(name, MODES[mode], tau_chunk=3, sched=1)
     ref = oracle_run(name)
     r = ref["iters"][0]
     run.g0()

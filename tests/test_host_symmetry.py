@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(gwsym.EXPORTED)
 
 
-@pytest.mark.parametrize("name", ["cfg0", "small_sc4", "small_rocksalt", "small_diamond"])
+@pytest.mark.parametrize("name", ["cfg0", "small_sc4", "small_rocksalt", "small_diamond", "small_hbn", "small_hbn3"])
 def test_orbital_representation_matches_generator(name):
     wl = workload(name)
     ctx = make_context(wl)
@@ -56,7 +56,7 @@ def test_table2_counts_through_library():
     oh = cubic_point_group()
     zb_ops = _ops_from_cart(FCC, [R for R in oh if in_td(R)], [np.zeros(3)] * 24)
     zincblende = Crystal("zincblende", FCC.copy(), np.array([[0, 0, 0], [0.25, 0.25, 0.25]]), [0, 1], zb_ops)
-    groups = {"227": crystal("diamond"), "216": zincblende}
+    groups = {"227": crystal("diamond"), "216": zincblende, "194": crystal("hbn")}
     for g, d in gold["groups"].items():
         for nk, cnt in d["nik"].items():
             assert _count(groups[g], int(nk)).nibz == cnt, (g, nk)
@@ -116,7 +116,21 @@ def test_diamond_x_point_blocks_are_even():
         assert all(b % 2 == 0 for b in ctx.blocks(aux=True)[i]), ctx.blocks(aux=True)[i]
 
 
-@pytest.mark.parametrize("name", ["small_sc4", "small_rocksalt", "small_diamond"])
+def test_hexagonal_screw_axis_blocks_are_even():
+    # P6_3/mmc: on the zone face k_z = pi/c (the points A and L of the 2x2x2 mesh) the screw axis
+    # makes every irrep of the projective little-group representation two-dimensional (bands
+    # stick in pairs there), so every isotypic block has even dimension
+    ctx = make_context(workload("small_hbn"))
+    ibz = ctx.table("ibz")
+    n = 2
+    face = [i for i, k in enumerate(ibz) if k % n == 1]
+    assert len(face) == 2
+    for i in face:
+        assert all(b % 2 == 0 for b in ctx.blocks()[i]), ctx.blocks()[i]
+        assert all(b % 2 == 0 for b in ctx.blocks(aux=True)[i]), ctx.blocks(aux=True)[i]
+
+
+@pytest.mark.parametrize("name", ["small_sc4", "small_rocksalt", "small_diamond", "small_hbn", "small_hbn3"])
 def test_block_basis_diagonalises_symmetric_inputs(name):
     wl = workload(name)
     ctx = make_context(wl)

@@ -280,6 +280,52 @@ def test_particle_number_and_mu(diamond_run):
     assert abs(oracle.particle_number(r["G"], wl.spin) - diamond_run["n_target"]) < 1e-10
 
 
+# ----------------------------------------------------------------------------- N_e (free count)
+
+def test_free_count_one_level_closed_form():
+    # one level at energy e: the count is s f(e - mu), f(x) = 1/(1 + e^{beta x}); a level far
+    # below mu holds s electrons, one far above none, one at mu half of s, and
+    # beta (e - mu) = ln 3 gives f = 1/4 (Sec. 4.1: N_e counts the occupied states with spin)
+    s, beta = 2.0, 50.0
+    F = np.array([[[0.7]]], complex)
+    assert abs(oracle.free_count(F, 0.7, beta, s) - 1.0) < 1e-15
+    assert abs(oracle.free_count(F, 0.7 + 5.0, beta, s) - s) < 1e-15
+    assert oracle.free_count(F, 0.7 - 5.0, beta, s) < 1e-100
+    mu = 0.7 - np.log(3.0) / beta
+    assert abs(oracle.free_count(F, mu, beta, s) - s * 0.25) < 1e-15
+    # two k points, two levels each: the mean over k of the summed occupations
+    F2 = np.array([np.diag([-0.2, 0.4]), np.diag([0.1, 0.3])], complex)
+    f = lambda x: 1.0 / (1.0 + np.exp(beta * x))
+    want = s * (f(-0.2) + f(0.4) + f(0.1) + f(0.3)) / 2
+    assert abs(oracle.free_count(F2, 0.0, beta, s) - want) < 1e-15
+
+
+def test_free_count_equals_particle_number_of_closed_form_g0():
+    # the count is the trace of gamma = -G0(beta) of the closed form, whose occupations are
+    # pinned to the Fermi function above and whose Dyson limit is pinned to (i w + mu - F)^{-1}
+    rng = np.random.default_rng(31)
+    nk, nao, beta, s = 4, 6, 30.0, 2.0
+    A = rng.standard_normal((nk, nao, nao)) + 1j * rng.standard_normal((nk, nao, nao))
+    F = 0.4 * _herm(A)
+    tau = oracle.tau_grid(beta, 12)
+    for mu in (-0.7, 0.0, 0.25):
+        G0 = oracle.g0_closed_form(F, mu, beta, tau)
+        assert abs(oracle.free_count(F, mu, beta, s) - oracle.particle_number(G0, s)) < 1e-12
+    # and a flipped Fermi function (occupying the states above mu) is far off
+    e = np.linalg.eigvalsh(F) + 0.7
+    flipped = s * (1.0 / (1.0 + np.exp(-beta * e))).sum() / nk
+    assert abs(flipped - oracle.free_count(F, -0.7, beta, s)) > 1.0
+
+
+def test_planted_free_count_mistakes_are_caught():
+    # flipped occupations (1 - f) and a dropped spin factor each break the one-level values
+    F = np.array([[[0.7]]], complex)
+    for old, new in [("1.0 / (1 + np.exp(-beta * np.abs(e))))", "np.exp(-beta * np.abs(e)) / (1 + np.exp(-beta * np.abs(e))))"),
+                     ("return spin * f.sum()", "return f.sum()")]:
+        bad = _mutant(oracle.free_count, old, new)
+        assert abs(bad(F, 0.7 + 5.0, 50.0, 2.0) - 2.0) > 0.5
+
+
 # ----------------------------------------------------------------------------- Table 2 counts
 
 def _ibz_count(ops_frac, n):
@@ -302,7 +348,8 @@ def test_table2_irreducible_counts():
     A = crystal("rocksalt").lattice
     Ai = np.linalg.inv(A)
     frac = {"Oh": [np.rint(Ai @ R @ A).astype(np.int64) for R in oh],
-            "Td": [np.rint(Ai @ R @ A).astype(np.int64) for R in oh if in_td(R)]}
+            "Td": [np.rint(Ai @ R @ A).astype(np.int64) for R in oh if in_td(R)],
+            "D6h": [W for W, _ in crystal("hbn").ops]}
     for g, d in gold["groups"].items():
         for nkk, cnt in d["nik"].items():
             assert _ibz_count(frac[d["point_group"]], int(nkk)) == cnt, (g, nkk)
