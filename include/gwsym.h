@@ -92,10 +92,22 @@ typedef enum {
                                 for the GEMMs, issued one after another: the per-block baseline */
 } gwsym_sched;
 
+/* Imaginary-time and Matsubara grids (Sec. 5.1). */
+typedef enum {
+  GWSYM_GRID_CHEBYSHEV = 0,  /* ntau Chebyshev-Gauss-Lobatto points, frequencies n = 0 .. nw-1 */
+  GWSYM_GRID_IR = 1          /* sparse sampling on the intermediate-representation basis of the
+                                logistic kernel with Lambda = beta ir_wmax and cutoff ir_eps: tau = 0,
+                                the zeros of the first dropped basis function and beta; the
+                                Matsubara indices where its transform changes sign.  ntau and nw
+                                are chosen by the library (pass 0; read them from "dims"), the
+                                frequency indices from "freq_f" / "freq_b". */
+} gwsym_grid;
+
 typedef struct {
   double beta;        /* inverse temperature (1/Ha) */
-  int ntau;           /* Chebyshev-Gauss-Lobatto tau points on [0, beta], >= 3 */
-  int nw;             /* Matsubara frequencies stored for n >= 0 (fermionic and bosonic) */
+  int ntau;           /* GWSYM_GRID_CHEBYSHEV: tau points on [0, beta], >= 3 */
+  int nw;             /* GWSYM_GRID_CHEBYSHEV: Matsubara frequencies stored for n >= 0 (fermionic
+                         and bosonic) */
   double spin;        /* spin factor s multiplying P0 and N_e (2 for closed shells) */
   int mode;           /* gwsym_mode */
   int precision;      /* gwsym_precision */
@@ -103,6 +115,9 @@ typedef struct {
                          tau_j with j < ceil(ntau/2) and mirrored (Alg. 3 tau loop) */
   int tau_chunk;      /* tau points per contraction launch (0 = library default) */
   int sched;          /* gwsym_sched */
+  int grid;           /* gwsym_grid */
+  double ir_wmax;     /* GWSYM_GRID_IR: real-frequency cutoff omega_max (Ha) of the basis */
+  double ir_eps;      /* GWSYM_GRID_IR: singular values kept above ir_eps times the largest */
 } gwsym_params;
 
 typedef struct {
@@ -165,6 +180,7 @@ int64_t gwsym_table_size(const gwsym_ctx* ctx, const char* name);
  *   "O_ao"        complex[nop][nk][nao][nao]: O^k(alpha) mapping k to alpha k
  *   "O_aux"       complex[nop][nk][naux][naux]
  *   "tau"         double[ntau];  "Tf","Tb" complex[nw][ntau];  "Bf","Bb" complex[ntau][nw]
+ *   "freq_f","freq_b" int64[nw]: Matsubara index n of each stored fermionic / bosonic frequency
  *                 (X(tau) = Y + Y^H with Y = B X(i nu); for bosons the n = 0 column
  *                  carries half weight)
  */

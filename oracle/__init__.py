@@ -7,4 +7,5 @@ from .gw import (tau_grid, matsubara, transform_matrices, to_freq, to_tau, fermi
                  polarization_unit, self_energy_unit,
                  g0_closed_form, free_count, polarization, self_energy, screened, dyson,
                  particle_number, find_mu, gw_iteration, exchange, hartree,
-                 exchange_unit, hartree_unit)
+                 exchange_unit, hartree_unit, ir_basis, ir_eval, ir_fourier, ir_grid, ir_transform_matrices,
+                 logistic_kernel)

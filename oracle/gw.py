@@ -25,6 +25,9 @@ Readings of the paper used here (each also listed in the design notes):
     degree-(ntau-1) interpolating polynomial; the inverse transform is the
     least-squares inverse over n >= 0 and the conjugate rows n < 0.
   * nw = 2 ntau + 1 frequencies stored for n >= 0.
+  * IR grids (Sec. 5.1): tau = 0, the zeros of the first dropped singular function of the
+    logistic kernel and beta; Matsubara indices where its transform changes sign, both
+    statistics filled to one length (ir_grid).
   * S^k = identity (orthonormal synthetic basis).
 """
 from __future__ import annotations
@@ -94,6 +97,160 @@ def to_tau(Xw: np.ndarray, Binv: np.ndarray, conj_rows: np.ndarray) -> np.ndarra
     stacked = np.concatenate([Xw, np.conj(np.swapaxes(Xw[..., conj_rows, :, :], -1, -2))],
                              axis=-3)
     return np.einsum("tr,...rab->...tab", Binv, stacked)
+
+
+# ----------------------------------------------------------------------------
+# sparse sampling on the intermediate-representation basis (Sec. 5.1: the tau and Matsubara
+# grids of the paper's calculations).  The basis is the singular value expansion of the
+# logistic kernel K(x, y) = exp(-L y (x + 1)/2) / (1 + exp(-L y)) on x = 2 tau/beta - 1 and
+# y = omega / wmax in [-1, 1], L = beta wmax: the same tau functions serve fermions and bosons.
+# Discretised by composite Gauss-Legendre rules (panels halving towards x = +-1 and y = 0 down
+# to 1/L), the singular vectors of sqrt(w_x) K sqrt(w_y) give u_l at the nodes, continued
+# inside each panel by the Legendre series through its nodes.
+
+
+def _ir_panels(lam):
+    k = int(np.ceil(np.log2(lam))) + 2
+    xb = sorted({-1.0, 0.0, 1.0} | {s * (1.0 - 2.0 ** -j) for j in range(1, k) for s in (1, -1)})
+    yb = sorted({-1.0, 0.0, 1.0} | {s * 2.0 ** -j for j in range(1, k) for s in (1, -1)})
+    return np.array(xb), np.array(yb)
+
+
+def _gauss_panels(breaks, order):
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    h = 0.5 * np.diff(breaks)
+    m = 0.5 * (breaks[1:] + breaks[:-1])
+    return (m[:, None] + h[:, None] * xg[None]).ravel(), (h[:, None] * wg[None]).ravel()
+
+
+def logistic_kernel(lam, x, y):
+    """exp(-lam y (x + 1)/2) / (1 + exp(-lam y)), in the form that never overflows"""
+    x, y = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float))
+    ay = np.abs(y)
+    e = np.where(y >= 0, -lam * y * (x + 1) / 2, lam * y * (1 - x) / 2)
+    return np.exp(e) / (1.0 + np.exp(-lam * ay))
+
+
+def ir_basis(lam, eps, order=16):
+    """Singular functions u_0..u_L (L = number of s_l / s_0 > eps) as per-panel Legendre
+    coefficients: dict(lam, L, s, xb, coef[panel, degree, l], order)."""
+    xb, yb = _ir_panels(lam)
+    x, wx = _gauss_panels(xb, order)
+    y, wy = _gauss_panels(yb, order)
+    A = np.sqrt(wx)[:, None] * logistic_kernel(lam, x[:, None], y[None, :]) * np.sqrt(wy)[None, :]
+    U, S, _ = np.linalg.svd(A)
+    L = int(np.sum(S / S[0] > eps))
+    u = U[:, :L + 1] / np.sqrt(wx)[:, None]
+    # fix the sign of each function: positive at x = 1 (u_l(1) != 0 for this kernel)
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    Pn = np.polynomial.legendre.legvander(xg, order - 1)                  # [node, degree]
+    norm = (2 * np.arange(order) + 1) / 2
+    coef = np.stack([norm[:, None] * (Pn * wg[:, None]).T @ u[p * order:(p + 1) * order]
+                     for p in range(len(xb) - 1)])                        # [panel, degree, l]
+    sign = np.sign(coef[-1].sum(axis=0))                                  # u_l(1) = sum_n c_n P_n(1)
+    return dict(lam=lam, L=L, s=S[:L + 1], xb=xb, coef=coef * sign[None, None, :], order=order)
+
+
+def ir_eval(b, x):
+    """u_l(x) for the basis b, [len(x), L + 1]"""
+    x = np.atleast_1d(np.asarray(x, float))
+    p = np.clip(np.searchsorted(b["xb"], x, side="right") - 1, 0, len(b["xb"]) - 2)
+    a, c = b["xb"][p], b["xb"][p + 1]
+    V = np.polynomial.legendre.legvander((2 * x - a - c) / (c - a), b["order"] - 1)
+    return np.einsum("qn,qnl->ql", V, b["coef"][p])
+
+
+def ir_fourier(b, beta, nu):
+    """hat u_l(i nu) = int_0^beta sqrt(2/beta) u_l(2 tau/beta - 1) exp(i nu tau) d tau, panel by
+    panel from the Legendre series: int_{-1}^{1} P_n(t) exp(i a t) dt = 2 i^n j_n(a)."""
+    from scipy.special import spherical_jn
+    nu = np.asarray(nu, float)
+    out = np.zeros((len(nu), b["L"] + 1), complex)
+    for p in range(len(b["xb"]) - 1):
+        h, m = 0.5 * (b["xb"][p + 1] - b["xb"][p]), 0.5 * (b["xb"][p + 1] + b["xb"][p])
+        a = nu * beta * h / 2
+        J = np.stack([2.0 * (1j ** n) * spherical_jn(n, a) for n in range(b["order"])], axis=1)
+        out += (np.exp(1j * nu * beta * (m + 1) / 2) * h)[:, None] * (J @ b["coef"][p])
+    return out * np.sqrt(beta / 2)
+
+
+def _roots(b, l):
+    """the zeros of u_l on (-1, 1): sign changes on a fine grid refined by bisection"""
+    x = np.concatenate([np.linspace(b["xb"][p], b["xb"][p + 1], 64, endpoint=False)
+                        for p in range(len(b["xb"]) - 1)] + [[1.0]])
+    f = ir_eval(b, x)[:, l]
+    out = []
+    for i in np.nonzero(np.sign(f[:-1]) * np.sign(f[1:]) < 0)[0]:
+        lo, hi, flo = x[i], x[i + 1], f[i]
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            fm = ir_eval(b, [mid])[0, l]
+            if np.sign(fm) == np.sign(flo):
+                lo, flo = mid, fm
+            else:
+                hi = mid
+        out.append(0.5 * (lo + hi))
+    return np.array(out)
+
+
+def _matsubara_sign_changes(b, beta, boson, nmax):
+    """Matsubara indices n >= 0 at which hat u_L changes sign (its nonzero part: real for
+    fermions of one parity, imaginary for the other), the bosonic n = 0 always included"""
+    n = np.arange(nmax)
+    nu = (2 * n + (0 if boson else 1)) * np.pi / beta
+    uh = ir_fourier(b, beta, nu)[:, b["L"]]
+    part = uh.real if np.abs(uh.real).max() > np.abs(uh.imag).max() else uh.imag
+    idx = [int(i) for i in np.nonzero(np.sign(part[:-1]) * np.sign(part[1:]) < 0)[0]]
+    if boson and 0 not in idx:
+        idx = [0] + idx
+    return np.array(idx)
+
+
+def ir_grid(beta, wmax, eps, nmax=None):
+    """Sampling points of the IR basis: tau = 0, the zeros of u_L mapped to tau (symmetric about
+    beta/2) and beta; Matsubara indices n >= 0 where hat u_L changes sign, for fermions and for
+    bosons, the shorter list extended by the next indices so both hold nw entries.  Returns
+    dict(basis, tau, nf, nb)."""
+    b = ir_basis(beta * wmax, eps)
+    r = _roots(b, b["L"])
+    r = 0.5 * (r - r[::-1])                                   # exact mirror symmetry
+    tau = np.concatenate([[0.0], beta * (r + 1) / 2, [beta]])
+    nmax = nmax or int(4 * beta * wmax / np.pi) + 64
+    nf = _matsubara_sign_changes(b, beta, False, nmax)
+    nb = _matsubara_sign_changes(b, beta, True, nmax)
+    nw = max(len(nf), len(nb), (b["L"] + 2) // 2)      # the bosonic stacked system needs 2 nw - 1 >= L
+
+    def pad(a):
+        # fill the widest gap: the integer geometric mean of the pair with the largest ratio
+        a = [int(v) for v in a]
+        while len(a) < nw:
+            i = max(range(len(a) - 1), key=lambda i: (a[i + 1] + 1) / (a[i] + 1))
+            m = int(round(np.sqrt((a[i] + 1) * (a[i + 1] + 1)))) - 1
+            if m <= a[i] or m >= a[i + 1]:
+                m = a[-1] + 1
+                a.append(m)
+            else:
+                a.insert(i + 1, m)
+        return np.array(a, dtype=int)
+
+    return dict(basis=b, tau=tau, nf=pad(nf), nb=pad(nb), beta=beta)
+
+
+def ir_transform_matrices(grid, boson):
+    """The IR counterpart of transform_matrices: X(i nu_n) = sum_j Tfwd[n, j] X(tau_j) through
+    the least-squares fit of the tau samples with u_0..u_{L-1}, and Binv from the stacked system
+    [X(i nu_n); X(i nu_n)^H] of the sampled frequencies and their negatives (bosonic n = 0
+    once).  Returns (Tfwd, Binv, conj_rows)."""
+    b, beta = grid["basis"], grid["beta"]
+    L = b["L"]
+    n = grid["nb"] if boson else grid["nf"]
+    nu = (2 * n + (0 if boson else 1)) * np.pi / beta
+    Ut = np.sqrt(2 / beta) * ir_eval(b, 2 * grid["tau"] / beta - 1)[:, :L]    # [tau, l]
+    Fm = ir_fourier(b, beta, nu)[:, :L]                                       # [n, l]
+    Tfwd = Fm @ np.linalg.pinv(Ut)
+    conj_rows = np.nonzero(n != 0)[0] if boson else np.arange(len(n))
+    S = np.vstack([Fm, Fm[conj_rows].conj()])
+    return Tfwd, Ut @ np.linalg.pinv(S), conj_rows
 
 
 # ----------------------------------------------------------------------------
@@ -255,24 +412,37 @@ def hartree_unit(G: np.ndarray, Vdiag: np.ndarray, k: int, spin: float) -> np.nd
 # screened interaction (eq. P02P) and Dyson equation (eq. dyson)
 
 
-def screened(P0: np.ndarray, beta: float, nw: int):
+def _transforms(beta, nt, nw, boson, grid):
+    """the Chebyshev transforms, or those of an IR grid (ir_grid)"""
+    if grid is not None:
+        return ir_transform_matrices(grid, boson)
+    return transform_matrices(beta, nt, nw, boson)
+
+
+def _fermion_freqs(beta, nw, grid):
+    if grid is not None:
+        return (2 * grid["nf"] + 1) * np.pi / beta
+    return matsubara(beta, nw, boson=False)
+
+
+def screened(P0: np.ndarray, beta: float, nw: int, grid=None):
     """P(i Omega_n) = [I - P0(i Omega_n)]^{-1} P0(i Omega_n), then back to tau.
-    Returns (P(tau), P0(i Omega), P(i Omega))."""
+    Returns (P(tau), P0(i Omega), P(i Omega)).  grid: None (Chebyshev) or an IR grid."""
     nk, nt, naux, _ = P0.shape
-    Tb, Bb, rows = transform_matrices(beta, nt, nw, boson=True)
+    Tb, Bb, rows = _transforms(beta, nt, nw, True, grid)
     P0w = to_freq(P0, Tb)
     I = np.eye(naux)
     Pw = np.linalg.solve(I - P0w, P0w)
     return to_tau(Pw, Bb, rows), P0w, Pw
 
 
-def dyson(F: np.ndarray, Sigma: np.ndarray, mu: float, beta: float, nw: int):
+def dyson(F: np.ndarray, Sigma: np.ndarray, mu: float, beta: float, nw: int, grid=None):
     """G(i w_n) = [(i w_n + mu) I - F - Sigma~(i w_n)]^{-1} (S = I), then back to tau.
-    Returns (G(tau), G(i w), Sigma~(i w))."""
+    Returns (G(tau), G(i w), Sigma~(i w)).  grid: None (Chebyshev) or an IR grid."""
     nk, nt, nao, _ = Sigma.shape
-    Tf, Bf, rows = transform_matrices(beta, nt, nw, boson=False)
+    Tf, Bf, rows = _transforms(beta, nt, nw, False, grid)
     Sw = to_freq(Sigma, Tf)
-    w = matsubara(beta, nw, boson=False)
+    w = _fermion_freqs(beta, nw, grid)
     I = np.eye(nao)
     A = (1j * w[:, None, None] + mu) * I[None] - F[:, None] - Sw
     Gw = np.linalg.inv(A)
@@ -285,13 +455,13 @@ def particle_number(G: np.ndarray, spin: float) -> float:
     return float(np.real(spin / nk * np.trace(-G[:, -1], axis1=-2, axis2=-1).sum()))
 
 
-def find_mu(F, Sigma, n_target, beta, nw, spin, steps=64):
+def find_mu(F, Sigma, n_target, beta, nw, spin, steps=64, grid=None):
     """Bisection on the strictly increasing N(mu) over [min eps - 20, max eps + 20]."""
     e = np.linalg.eigvalsh(F)
     lo, hi = e.min() - 20.0, e.max() + 20.0
     for _ in range(steps):
         mid = 0.5 * (lo + hi)
-        G, _, _ = dyson(F, Sigma, mid, beta, nw)
+        G, _, _ = dyson(F, Sigma, mid, beta, nw, grid)
         if particle_number(G, spin) < n_target:
             lo = mid
         else:
@@ -303,12 +473,13 @@ def find_mu(F, Sigma, n_target, beta, nw, spin, steps=64):
 # one iteration (Alg. 2 order: P0 -> P -> Sigma -> Dyson)
 
 
-def gw_iteration(F, V, G, mu, beta, nw, spin, add, sub, n_target=None, mu_steps=64):
-    """One GW iteration from G.  With n_target None, mu stays fixed."""
+def gw_iteration(F, V, G, mu, beta, nw, spin, add, sub, n_target=None, mu_steps=64, grid=None):
+    """One GW iteration from G.  With n_target None, mu stays fixed.  grid: None (Chebyshev
+    tau grid of G's length) or an IR grid (ir_grid) whose tau points G is sampled on."""
     P0 = polarization(G, V, add, spin)
-    P, P0w, Pw = screened(P0, beta, nw)
+    P, P0w, Pw = screened(P0, beta, nw, grid)
     Sigma = self_energy(G, V, P, sub)
     if n_target is not None:
-        mu = find_mu(F, Sigma, n_target, beta, nw, spin, mu_steps)
-    Gn, Gw, Sw = dyson(F, Sigma, mu, beta, nw)
+        mu = find_mu(F, Sigma, n_target, beta, nw, spin, mu_steps, grid)
+    Gn, Gw, Sw = dyson(F, Sigma, mu, beta, nw, grid)
     return dict(P0=P0, P=P, P0w=P0w, Pw=Pw, Sigma=Sigma, Sigmaw=Sw, G=Gn, Gw=Gw, mu=mu)

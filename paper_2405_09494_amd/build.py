@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgwsym.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["capi.cpp", "symmetry.cpp", "grids.cpp", "host_linalg.cpp", "kernels.hip", "bdiag.hip", "pipeline.hip"]
+SOURCES = ["capi.cpp", "symmetry.cpp", "grids.cpp", "grids_ir.cpp", "host_linalg.cpp", "kernels.hip", "bdiag.hip", "pipeline.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

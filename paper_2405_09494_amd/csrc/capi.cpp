@@ -17,9 +17,17 @@ const char* g_static_err = "no context";
 int check_params(const gwsym_params* p, std::string& err) {
   if (!p) return err = "params is NULL", GWSYM_EINVAL;
   if (!(p->beta > 0)) return err = "beta must be positive", GWSYM_EINVAL;
-  if (p->ntau < 3) return err = "ntau must be >= 3", GWSYM_EINVAL;
-  if (p->nw < 1) return err = "nw must be >= 1", GWSYM_EINVAL;
-  if (2 * p->nw - 1 < p->ntau) return err = "need 2 nw - 1 >= ntau for the inverse transform", GWSYM_EINVAL;
+  if (p->grid != GWSYM_GRID_CHEBYSHEV && p->grid != GWSYM_GRID_IR) return err = "unknown grid", GWSYM_EINVAL;
+  if (p->grid == GWSYM_GRID_IR) {
+    if (!(p->ir_wmax > 0)) return err = "ir_wmax must be positive", GWSYM_EINVAL;
+    if (!(p->ir_eps >= 1e-14 && p->ir_eps <= 1e-2)) return err = "ir_eps must lie in [1e-14, 1e-2]", GWSYM_EINVAL;
+    if (!(p->beta * p->ir_wmax >= 1.0 && p->beta * p->ir_wmax <= 1e5))
+      return err = "beta ir_wmax must lie in [1, 1e5]", GWSYM_EINVAL;
+  } else {
+    if (p->ntau < 3) return err = "ntau must be >= 3", GWSYM_EINVAL;
+    if (p->nw < 1) return err = "nw must be >= 1", GWSYM_EINVAL;
+    if (2 * p->nw - 1 < p->ntau) return err = "need 2 nw - 1 >= ntau for the inverse transform", GWSYM_EINVAL;
+  }
   if (p->mode < 0 || p->mode > 2) return err = "unknown mode", GWSYM_EINVAL;
   if (p->precision < GWSYM_FP64 || p->precision > GWSYM_BF16X3) return err = "unknown precision", GWSYM_EINVAL;
   if (p->tau_chunk < 0) return err = "tau_chunk must be >= 0", GWSYM_EINVAL;
@@ -77,6 +85,10 @@ bool table(const Ctx& c, const std::string& name, std::vector<int64_t>& iv, std:
         const CMat O = orbital_rep(c, name == "O_aux", a, k);
         cv.insert(cv.end(), O.a.begin(), O.a.end());
       }
+  } else if (name == "freq_f") {
+    ints(c.nfreq_f);
+  } else if (name == "freq_b") {
+    ints(c.nfreq_b);
   } else if (name == "tau") {
     kind = 1;
     dv = c.tau;
@@ -132,9 +144,9 @@ int gwsym_build_symmetry_basis(gwsym_ctx* ctx, const gwsym_crystal* crystal) {
   Ctx& c = ctx->c;
   if (c.built) return c.err = "symmetry basis already built", GWSYM_ESTATE;
   try {
+    build_grids(c);   // first: the packed layouts count tau points
     const int st = build_symmetry(c, crystal);
     if (st != GWSYM_OK) return st;
-    build_grids(c);
   } catch (const std::bad_alloc&) {
     return c.err = "host allocation failed", GWSYM_ENOMEM;
   } catch (const std::exception& e) {

@@ -13,7 +13,14 @@
 namespace gw {
 
 void build_grids(Ctx& c) {
+  if (c.prm.grid == GWSYM_GRID_IR) {
+    build_ir_grids(c);
+    return;
+  }
   const int nt = c.prm.ntau, nw = c.prm.nw, N1 = nt - 1;
+  c.nfreq_f.resize(nw);
+  c.nfreq_b.resize(nw);
+  for (int n = 0; n < nw; ++n) c.nfreq_f[n] = c.nfreq_b[n] = n;
   const double beta = c.prm.beta;
   c.ntau = nt;
   c.nw = nw;

@@ -141,6 +141,7 @@ struct Ctx {
   // grids
   std::vector<double> tau;
   std::vector<cplx> Tf, Tb, Bf, Bb;        // [nw][ntau], [ntau][nw]
+  std::vector<int> nfreq_f, nfreq_b;       // Matsubara index n of each stored frequency (>= 0)
 
   // device state (device.hip)
   void* dev_state = nullptr;
@@ -157,6 +158,8 @@ CMat orbital_rep(const Ctx& c, bool aux, int op, int k);
 int build_symmetry(Ctx& c, const gwsym_crystal* cr);
 // grids.cpp
 void build_grids(Ctx& c);
+// grids_ir.cpp: tau and Matsubara sampling on the IR basis (sets ntau, nw and the matrices)
+void build_ir_grids(Ctx& c);
 // device.hip
 int device_init(Ctx& c, void* stream);
 void device_free(Ctx& c);

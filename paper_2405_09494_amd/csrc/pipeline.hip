@@ -981,7 +981,7 @@ int device_init(Ctx& c, void* stream) {
         InvItem it{};
         it.n = B.size[r]; it.xbuf = B_W1; it.fbuf = B_F; it.outbuf = B_W2;
         it.x_off = gw_off[i] + i64(n) * B.packed + B.poff[r]; it.f_off = c.f_off[i] + B.poff[r];
-        it.out_off = it.x_off; it.w = (2.0 * n + 1.0) * M_PI / c.prm.beta;
+        it.out_off = it.x_off; it.w = (2.0 * c.nfreq_f[n] + 1.0) * M_PI / c.prm.beta;
         d.dys_inv.items.push_back(it);
         d.mu_inv.items.push_back(it);
         d.mu_items.items.push_back({n, 0, double(star[i])});

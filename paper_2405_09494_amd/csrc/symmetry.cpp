@@ -472,8 +472,8 @@ int build_symmetry(Ctx& c, const gwsym_crystal* cr) {
       }
     }
     c.f_off[i + 1] = c.f_off[i] + c.bao[i].packed;
-    c.g_off[i + 1] = c.g_off[i] + i64(c.prm.ntau) * c.bao[i].packed;
-    c.p_off[i + 1] = c.p_off[i] + i64(c.prm.ntau) * c.baux[i].packed;
+    c.g_off[i + 1] = c.g_off[i] + i64(c.ntau) * c.bao[i].packed;
+    c.p_off[i + 1] = c.p_off[i] + i64(c.ntau) * c.baux[i].packed;
   }
   return GWSYM_OK;
 }

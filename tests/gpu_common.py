@@ -26,16 +26,19 @@ def inputs(name):
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_run(name, iterations=1):
+def oracle_run(name, iterations=1, ir=None):
+    """ir: None (the workload's Chebyshev grid) or (wmax, eps) of an IR grid built by the oracle"""
     wl, inp, F, V = inputs(name)
-    tau = oracle.tau_grid(wl.beta, wl.ntau)
+    grid = oracle.ir_grid(wl.beta, ir[0], ir[1]) if ir else None
+    tau = grid["tau"] if grid else oracle.tau_grid(wl.beta, wl.ntau)
+    nw = len(grid["nf"]) if grid else wl.nw
     G = oracle.g0_closed_form(F, 0.0, wl.beta, tau)
     add, sub = add_k(wl.n), sub_table(wl.n)
     nt = None if wl.mu_fixed else oracle.free_count(F, 0.0, wl.beta, wl.spin)
     out = dict(G0=G, n_target=nt, iters=[])
     mu = 0.0
     for _ in range(iterations):
-        r = oracle.gw_iteration(F, V, G, mu, wl.beta, wl.nw, wl.spin, add, sub, n_target=nt)
+        r = oracle.gw_iteration(F, V, G, mu, wl.beta, nw, wl.spin, add, sub, n_target=nt, grid=grid)
         out["iters"].append(r)
         G, mu = r["G"], r["mu"]
     return out
@@ -44,11 +47,11 @@ def oracle_run(name, iterations=1):
 class DeviceRun:
     """Device buffers and calls of one workload in one mode."""
 
-    def __init__(self, name, mode, half_tau=True, tau_chunk=0, precision=0, identity_only=False, sched=0):
+    def __init__(self, name, mode, half_tau=True, tau_chunk=0, precision=0, identity_only=False, sched=0, ir=None):
         wl, inp, F, V = inputs(name)
         self.wl = wl
         self.ctx = make_context(wl, mode=mode, half_tau=half_tau, tau_chunk=tau_chunk, precision=precision,
-                                identity_only=identity_only, sched=sched)
+                                identity_only=identity_only, sched=sched, ir=ir)
         c = self.ctx
         dev = torch.device("cuda:0")
         self.dev = dev

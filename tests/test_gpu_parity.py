@@ -98,6 +98,34 @@ def test_degenerate(name, mode, identity_only):
         assert e < TOL
 
 
+# IR grids: library and oracle each build their own (independent double-precision SVDs of the
+# logistic kernel, which agree to about 1e-10 in the transforms at eps = 1e-6); the bar is set
+# a hundred times above that agreement
+IR = (5.0, 1e-6)
+TOL_IR = 1e-8
+
+
+@pytest.mark.parametrize("name,mode", [("cfg0", "full"), ("small_diamond", "block"), ("small_hbn", "block"),
+                                       ("small_sc4", "block")])
+def test_iteration_ir_grid(name, mode):
+    """One iteration on the sparse-sampling IR grid (Sec. 5.1) against the oracle on its IR grid."""
+    say(f"[ir grid] {name} {mode}")
+    run = DeviceRun(name, MODES[mode], ir=IR)
+    ref = oracle_run(name, 1, IR)
+    r = ref["iters"][0]
+    run.g0()
+    assert rel(run.full(1, run.G), ref["G0"]) < TOL_IR
+    c = run.ctx
+    c.iteration(run.F, run.G, run.P0, run.P, run.S, run.mu, ref["n_target"] or 0.0)
+    c.check()
+    for kind, buf, key in ((2, run.P0, "P0"), (2, run.P, "P"), (1, run.S, "Sigma"), (1, run.G, "G")):
+        e = rel(run.full(kind, buf), r[key])
+        say(f"  {key} {e:.2e}")
+        assert e < TOL_IR
+    if ref["n_target"] is not None:
+        assert abs(run.mu.item() - r["mu"]) < TOL_IR
+
+
 @pytest.mark.parametrize("name,mode", [("small_diamond", "block"), ("small_sc4", "block"), ("cfg0", "full"),
                                        ("wide_rocksalt", "block")])
 def test_unbatched_schedule(name, mode):

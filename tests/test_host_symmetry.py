@@ -260,3 +260,33 @@ def test_pairwise_inputs_are_symmetric():
                 X = inp.aux.matrix(op, q)
                 rot = np.einsum("QP,Pij->Qij", X, L[None] @ V[k1, k2] @ R.conj().T[None])
                 assert np.abs(V[inp.kmap[op, k1], inp.kmap[op, k2]] - rot).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("beta,wmax,eps", [(30.0, 5.0, 1e-6), (400.0, 5.0, 1e-6)])
+def test_ir_grid_matches_oracle(beta, wmax, eps):
+    """The library's IR sampling grid (its own SVD of the logistic kernel) against the oracle's:
+    the same tau points and Matsubara indices, transforms equal to the agreement two
+    double-precision SVDs allow at this cutoff (about the rounding over s_L / s_0)."""
+    from paper_2405_09494_amd import gwsym
+    wl = workload("small_diamond")
+    ctx = gwsym.Context(beta, 0, 0, wl.spin, gwsym.MODE_BLOCK, ir=(wmax, eps))
+    ctx.build_symmetry_basis(*crystal_arrays(crystal(wl.crystal)), wl.n, wl.ao, wl.aux)
+    g = oracle.ir_grid(beta, wmax, eps)
+    assert ctx.ntau == len(g["tau"]) and ctx.nw == len(g["nf"])
+    assert np.abs(ctx.table("tau") - g["tau"]).max() < 1e-10 * beta
+    assert list(ctx.table("freq_f")) == list(g["nf"]) and list(ctx.table("freq_b")) == list(g["nb"])
+    Tf, Bf, _ = oracle.ir_transform_matrices(g, False)
+    Tb, Bb, _ = oracle.ir_transform_matrices(g, True)
+    Bb = Bb[:, :ctx.nw].copy()
+    Bb[:, np.nonzero(g["nb"] == 0)[0]] *= 0.5        # the library's halved n = 0 column
+    for name, ref in (("Tf", Tf), ("Tb", Tb), ("Bf", Bf[:, :ctx.nw]), ("Bb", Bb)):
+        got = ctx.table(name).reshape(ref.shape)
+        assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max(), name
+
+
+def test_ir_grid_parameter_errors():
+    from paper_2405_09494_amd import gwsym
+    with pytest.raises(gwsym.GwsymError):
+        gwsym.Context(30.0, 0, 0, 2.0, gwsym.MODE_BLOCK, ir=(-1.0, 1e-6))
+    with pytest.raises(gwsym.GwsymError):
+        gwsym.Context(30.0, 0, 0, 2.0, gwsym.MODE_BLOCK, ir=(5.0, 0.5))

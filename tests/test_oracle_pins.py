@@ -544,3 +544,92 @@ def test_static_units_match_whole_zone(diamond_run):
         Jk = oracle.hartree_unit(G0, Vdiag, k, wl.spin)
         assert np.abs(Kk - K[k]).max() < 1e-14 * np.abs(K).max()
         assert np.abs(Jk - J[k]).max() < 1e-14 * np.abs(J).max()
+
+
+# ----------------------------------------------------------------------------- IR sampling grids (Sec. 5.1)
+
+IR_CASES = [(30.0, 5.0, 1e-6), (100.0, 4.0, 1e-8)]
+
+
+@pytest.mark.parametrize("beta,wmax,eps", IR_CASES)
+def test_ir_basis_properties(beta, wmax, eps):
+    g = oracle.ir_grid(beta, wmax, eps)
+    b = g["basis"]
+    L = b["L"]
+    # orthonormal on [-1, 1] (a finer rule than the one that built them), singular values falling
+    xf, wf = np.polynomial.legendre.leggauss(48)
+    u = np.concatenate([oracle.ir_eval(b, 0.5 * (q - p) * xf + 0.5 * (q + p)) * np.sqrt(0.5 * (q - p) * wf)[:, None]
+                        for p, q in zip(b["xb"][:-1], b["xb"][1:])])
+    assert np.abs(u.T @ u - np.eye(L + 1)).max() < 1e-10
+    assert (np.diff(b["s"]) < 0).all() and b["s"][L - 1] > eps * b["s"][0] >= b["s"][L]
+    # the logistic kernel is centrosymmetric: u_l(-x) = (-1)^l u_l(x) for the well-resolved l
+    x = np.linspace(-1, 1, 101)
+    par = oracle.ir_eval(b, -x)[:, :10] - oracle.ir_eval(b, x)[:, :10] * (-1.0) ** np.arange(10)
+    assert np.abs(par).max() < 1e-8
+    # tau grid: 0, the L zeros of u_L, beta; mirror symmetric
+    tau = g["tau"]
+    assert len(tau) == L + 2 and tau[0] == 0.0 and tau[-1] == beta
+    assert np.abs(tau + tau[::-1] - beta).max() < 1e-12 * beta
+    assert (np.diff(tau) > 0).all()
+    # (u_L is determined to about the double-precision rounding over s_L / s_0, so are its zeros)
+    assert np.abs(oracle.ir_eval(b, 2 * tau[1:-1] / beta - 1)[:, L]).max() < 1e-6 * np.abs(oracle.ir_eval(b, x)[:, L]).max()
+    # the frequency fits are determined: 2 nw rows (bosons: 2 nw - 1) for L unknowns
+    assert len(g["nf"]) == len(g["nb"]) and 2 * len(g["nb"]) - 1 >= L
+    assert 0 in g["nb"] and (np.diff(g["nf"]) > 0).all() and (np.diff(g["nb"]) > 0).all()
+
+
+@pytest.mark.parametrize("beta,wmax,eps", IR_CASES)
+def test_ir_transforms_against_closed_forms(beta, wmax, eps):
+    g = oracle.ir_grid(beta, wmax, eps)
+    tau = g["tau"]
+    Tf, Bf, rf = oracle.ir_transform_matrices(g, False)
+    Tb, Bb, rb = oracle.ir_transform_matrices(g, True)
+    # free fermion levels inside the cutoff: G0(tau) -> the analytic 1/(i w_n - e), to the basis accuracy
+    levels = np.array([-0.9 * wmax, -0.3, 0.05, 1.7, 0.8 * wmax])
+    G = -oracle.fermi_factor_parts(levels, tau, beta)                       # [tau, level]
+    w = (2 * g["nf"] + 1) * np.pi / beta
+    ref = 1.0 / (1j * w[:, None] - levels[None, :])
+    assert np.abs(Tf @ G - ref).max() < 50 * eps * np.abs(ref).max()
+    back = Bf @ np.concatenate([Tf @ G, (Tf @ G)[rf].conj()])
+    assert np.abs(back - G).max() < 50 * eps
+    # the two-level polarization of the Chebyshev pin: tau form -> -2 s |v|^2 (f1 - f2) D / (W^2 + D^2)
+    e1, e2, s, v = -0.3, 0.5, 2.0, 0.7
+    f1, f2 = 1 / (1 + np.exp(beta * e1)), 1 / (1 + np.exp(beta * e2))
+    h1, h2 = 1 / (1 + np.exp(-beta * e1)), 1 / (1 + np.exp(-beta * e2))     # 1 - f without cancellation
+    dl = e2 - e1
+    P0 = -s * v ** 2 * (f1 * h2 * np.exp(-dl * tau) + f2 * h1 * np.exp(dl * tau))
+    Om = 2 * g["nb"] * np.pi / beta
+    refb = -2 * s * v ** 2 * (f1 - f2) * dl / (Om ** 2 + dl ** 2)
+    assert np.abs(Tb @ P0 - refb).max() < 50 * eps * np.abs(refb).max()
+
+
+def test_ir_round_trip_is_exact_on_the_basis():
+    g = oracle.ir_grid(30.0, 5.0, 1e-6)
+    b, beta, L = g["basis"], 30.0, g["basis"]["L"]
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(L)
+    for boson in (False, True):
+        n = g["nb"] if boson else g["nf"]
+        nu = (2 * n + (0 if boson else 1)) * np.pi / beta
+        Ut = np.sqrt(2 / beta) * oracle.ir_eval(b, 2 * g["tau"] / beta - 1)[:, :L]
+        Fm = oracle.ir_fourier(b, beta, nu)[:, :L]
+        T, B, rows = oracle.ir_transform_matrices(g, boson)
+        Xt = Ut @ x
+        assert np.abs(T @ Xt - Fm @ x).max() < 1e-11 * np.abs(Fm @ x).max()
+        Xw = T @ Xt
+        # real X(tau) is its own Hermitian conjugate: the conjugate rows are conj(X(i nu))
+        assert np.abs(B @ np.concatenate([Xw, Xw[rows].conj()]) - Xt).max() < 1e-11 * np.abs(Xt).max()
+
+
+def test_ir_fourier_against_quadrature():
+    # the Legendre-Bessel panel formula against brute-force quadrature of u_l e^{i nu tau}
+    g = oracle.ir_grid(20.0, 3.0, 1e-6)
+    b, beta = g["basis"], 20.0
+    nu = np.array([np.pi / beta, 7 * np.pi / beta, 40 * np.pi / beta])
+    xq, wq = np.polynomial.legendre.leggauss(400)
+    ref = np.zeros((3, b["L"] + 1), complex)
+    for p, q in zip(b["xb"][:-1], b["xb"][1:]):
+        x = 0.5 * (q - p) * xq + 0.5 * (q + p)
+        w = 0.5 * (q - p) * wq * beta / 2 * np.sqrt(2 / beta)
+        ref += (np.exp(1j * np.outer(nu, beta * (x + 1) / 2)) * w) @ oracle.ir_eval(b, x)
+    assert np.abs(oracle.ir_fourier(b, beta, nu) - ref).max() < 1e-12
