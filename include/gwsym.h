@@ -252,6 +252,17 @@ int gwsym_check(gwsym_ctx* ctx, void* stream);
 int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, const double* mu,
                   void* G_blk, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gwsym_dyson_G with the same arguments and result,
+ * whose frequency workspaces and split-K partial tiles live in a file-scope device array of the
+ * library (64 MiB per GPU, held until the process ends) instead of the context's buffers; the
+ * call allocates nothing.  GWSYM_ESHAPE when the workload needs more than the array
+ * (2 nw sum_i packed_ao(i) complex numbers plus the partial tiles: the small and 4x4x4
+ * workloads fit, the 6x6x6 ones do not).  Every call on one GPU shares the array: calls that
+ * overlap on a GPU (other streams, other contexts) race. */
+int gwsym_dyson_G_noalloc(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, const double* mu,
+                          void* G_blk, void* stream);
+
 /* eq. sigma_hf, exchange term: K^k = -(1/Nk) sum_{k'} sum_Q V^{k,k'}(Q) gamma^{k'} V^{k',k}(Q)
  * with the density matrix gamma^k = G^k(0^-) = -G^k(beta), taken from the last tau point of
  * G_blk (device, G layout).  Writes K_blk (device) in the F layout: block-packed, one matrix

@@ -261,6 +261,14 @@ int gwsym_dyson_G(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, cons
   return device_dyson(ctx->c, F_blk, Sigma_blk, mu, G_blk, stream);
 }
 
+int gwsym_dyson_G_noalloc(gwsym_ctx* ctx, const void* F_blk, const void* Sigma_blk, const double* mu, void* G_blk,
+                          void* stream) {
+  if (!ctx) return GWSYM_EINVAL;
+  NEED(ctx->c.dev, GWSYM_ESTATE, "gwsym_device_init must come first");
+  NEED(F_blk && Sigma_blk && mu && G_blk, GWSYM_EINVAL, "NULL buffer");
+  return device_dyson_noalloc(ctx->c, F_blk, Sigma_blk, mu, G_blk, stream);
+}
+
 int gwsym_iteration(gwsym_ctx* ctx, const void* F_blk, void* G_blk, void* P0_blk, void* P_blk, void* Sigma_blk,
                     double* mu, double n_target, int use_graph, void* stream) {
   if (!ctx) return GWSYM_EINVAL;

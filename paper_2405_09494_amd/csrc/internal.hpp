@@ -176,6 +176,7 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
 int device_find_mu(Ctx& c, const void* F, const void* S, double ntarget, double* mu, void* stream);
 int device_check(Ctx& c, void* stream);
 int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream);
+int device_dyson_noalloc(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream);
 int device_iteration(Ctx& c, const void* H0, const void* F, void* G, void* P0, void* P, void* S, double* mu,
                      double ntarget, int use_graph, void* stream);
 int device_profile(Ctx& c, int enable);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -761,6 +762,8 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   return GWSYM_OK;
 }
 
+int init_noalloc_scratch(Ctx& c);
+
 // ---------------------------------------------------------------------------------------
 // device_init: tables, workspaces and the work lists that do not depend on V.
 
@@ -1073,6 +1076,7 @@ int device_init(Ctx& c, void* stream) {
   HIPCHECK(hipMemsetAsync(d.status, 0, sizeof(int), s));
   HIPCHECK(hipMemsetAsync(d.mu_state, 0, 16 * sizeof(double), s));
   HIPCHECK(hipStreamSynchronize(s));
+  if ((st = init_noalloc_scratch(c))) return st;
   c.dev = true;
   return GWSYM_OK;
 }
@@ -1520,6 +1524,68 @@ int device_dyson(Ctx& c, const void* F, const void* S, const double* mu, void* G
   b.p[B_F] = const_cast<void*>(F);
   b.p[B_OUT] = G;
   dyson_launches(c, d, b, d.partials, mu, s, true);
+  HIPCHECK(hipGetLastError());
+  return GWSYM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free form of the Dyson step for callers that cannot allocate (code under graph
+// capture, tight serving loops): its frequency workspaces and split-K partial tiles live in one
+// file-scope device array instead of the context's buffers, so a call allocates nothing.  Each
+// GPU holds its own copy of the array until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device (set up in device_init).  Calls
+// that overlap on one GPU share the array and race.
+
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};   // device address of `scratch` per device id
+}  // namespace
+
+// once per device, with that device current
+int init_noalloc_scratch(Ctx& c) {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return c.err = "device id beyond the scratch table", GWSYM_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return GWSYM_OK;
+  void* p = nullptr;
+  HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return c.err = "no device address for the scratch array", GWSYM_EHIP;
+  g_scratch_dev[dev] = p;
+  return GWSYM_OK;
+}
+
+int device_dyson_noalloc(Ctx& c, const void* F, const void* S, const double* mu, void* G, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevState& d = *static_cast<DevState*>(c.dev_state);
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  void* base = (dev >= 0 && dev < MAX_DEVICES) ? g_scratch_dev[dev] : nullptr;
+  if (!base) return c.err = "the scratch array was not set up on this device (gwsym_device_init runs there first)",
+                    GWSYM_ESTATE;
+  // layout: W1 (frequency Sigma, then G(tau) before the Hermitian sum), W2 (G(i w)), partials
+  const size_t wf = size_t(c.nw) * size_t(c.g_off[c.nibz]);
+  const size_t wt = size_t(c.g_off[c.nibz]);
+  const size_t w1 = (std::max(wf, wt) * 16 + 255) & ~size_t(255), w2 = (wf * 16 + 255) & ~size_t(255);
+  const size_t slots = size_t(std::max(d.dys_fwd.max_slots, d.dys_bwd.max_slots));
+  const size_t need = w1 + w2 + slots * 32 * 32 * 16;
+  if (need > NOALLOC_BYTES) {
+    c.err = "the allocation-free Dyson step needs " + std::to_string(need) + " bytes of scratch, more than its " +
+            std::to_string(NOALLOC_BYTES) + "-byte array";
+    return GWSYM_ESHAPE;
+  }
+  Bases b = bases_of(d);
+  unsigned char* p = static_cast<unsigned char*>(base);
+  b.p[B_W1] = p;
+  b.p[B_W2] = p + w1;
+  b.p[B_IN] = const_cast<void*>(S);
+  b.p[B_F] = const_cast<void*>(F);
+  b.p[B_OUT] = G;
+  dyson_launches(c, d, b, p + w1 + w2, mu, s, false);
   HIPCHECK(hipGetLastError());
   return GWSYM_OK;
 }

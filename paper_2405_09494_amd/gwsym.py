@@ -82,6 +82,7 @@ lib.gwsym_screened_interaction.argtypes = [_vp, _vp, _vp, _vp]
 lib.gwsym_self_energy.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.gwsym_find_mu.argtypes = [_vp, _vp, _vp, C.c_double, _vp, _vp]
 lib.gwsym_dyson_G.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+lib.gwsym_dyson_G_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 lib.gwsym_iteration.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int, _vp]
 lib.gwsym_exchange.argtypes = [_vp, _vp, _vp, _vp]
 lib.gwsym_hartree.argtypes = [_vp, _vp, _vp, _vp]
@@ -101,7 +102,7 @@ EXPORTED = ["gwsym_create", "gwsym_destroy", "gwsym_last_error", "gwsym_build_sy
             "gwsym_from_block", "gwsym_g0", "gwsym_polarization", "gwsym_screened_interaction",
             "gwsym_self_energy", "gwsym_find_mu", "gwsym_dyson_G", "gwsym_iteration", "gwsym_exchange",
             "gwsym_hartree", "gwsym_fock", "gwsym_scf_iteration", "gwsym_autotune", "gwsym_get_tuning",
-            "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read", "gwsym_check"]
+            "gwsym_set_tuning", "gwsym_flop_counts", "gwsym_profile", "gwsym_profile_read", "gwsym_check", "gwsym_dyson_G_noalloc"]
 
 PROFILE_CLASSES = ["p0_contraction", "sigma_aux_contraction", "sigma_orb_contraction", "row_block_multiply",
                    "two_sided_block_multiply", "transforms", "inverses", "other"]
@@ -247,6 +248,10 @@ class Context:
 
     def dyson_G(self, F_blk, S_blk, mu, G_blk, stream=None):
         self._check(lib.gwsym_dyson_G(self.h, _ptr(F_blk), _ptr(S_blk), _ptr(mu), _ptr(G_blk), _stream(stream)))
+
+    def dyson_G_noalloc(self, F_blk, S_blk, mu, G_blk, stream=None):
+        self._check(lib.gwsym_dyson_G_noalloc(self.h, _ptr(F_blk), _ptr(S_blk), _ptr(mu), _ptr(G_blk),
+                                              _stream(stream)))
 
     def exchange(self, G_blk, K_blk, stream=None):
         self._check(lib.gwsym_exchange(self.h, _ptr(G_blk), _ptr(K_blk), _stream(stream)))
