@@ -49,13 +49,32 @@ template <> struct Mf<float2> {
   static __device__ __forceinline__ int row(int lane, int j) { return 4 * (lane >> 4) + j; }
 };
 
-// complex accumulate c += a b on one 16 x 16 tile (four real MFMAs)
+// Complex accumulate c += a b on one 16 x 16 tile with three real MFMAs (3M): cr, ci and cx
+// collect sum a_r b_r, sum a_i b_i and sum (a_r + a_i)(b_r + b_i); the tile's value is
+// (cr - ci) + i (cx - cr - ci).  a is the row (A) fragment and b the column (B) fragment; as
+// and bs are a_r + a_i and b_r + b_i, formed once where a held operand is loaded.
 template <typename V2>
-__device__ __forceinline__ void cmma(const V2 a, const V2 b, typename Mf<V2>::A4& cr, typename Mf<V2>::A4& ci) {
+__device__ __forceinline__ void cmma(const V2 a, typename Mf<V2>::R as, const V2 b, typename Mf<V2>::R bs,
+                                     typename Mf<V2>::A4& cr, typename Mf<V2>::A4& ci, typename Mf<V2>::A4& cx) {
+  cr = Mf<V2>::mma(a.x, b.x, cr);
+  ci = Mf<V2>::mma(a.y, b.y, ci);
+  cx = Mf<V2>::mma(as, bs, cx);
+}
+
+// the same with four real MFMAs (4M), for kernels whose registers cannot hold a third accumulator
+template <typename V2>
+__device__ __forceinline__ void cmma4(const V2 a, const V2 b, typename Mf<V2>::A4& cr, typename Mf<V2>::A4& ci) {
   cr = Mf<V2>::mma(a.x, b.x, cr);
   ci = Mf<V2>::mma(a.x, b.y, ci);
   cr = Mf<V2>::mma(-a.y, b.y, cr);
   ci = Mf<V2>::mma(a.y, b.x, ci);
+}
+
+template <typename V2>
+__device__ __forceinline__ V2 cval(const typename Mf<V2>::A4& cr, const typename Mf<V2>::A4& ci,
+                                   const typename Mf<V2>::A4& cx, int j) {
+  using R = typename Mf<V2>::R;
+  return V2{R(cr[j] - ci[j]), R(cx[j] - cr[j] - ci[j])};
 }
 
 // Per index x < n of a basis: first index, size and packed offset of its block.
@@ -146,8 +165,8 @@ __global__ __launch_bounds__(256) void k_bd_right(const RowSeg* __restrict__ seg
         const int k = k0 + 4 * ks + kq;
         V2 a = arow[min(k, n - 1)];
         if (k >= n) a = V2{0, 0};
-        cmma<V2>(a, gf[ks], cr, ci);
-        if (dual) cmma<V2>(a, gf2[ks], dr, di);
+        cmma4<V2>(a, gf[ks], cr, ci);
+        if (dual) cmma4<V2>(a, gf2[ks], dr, di);
       }
     }
 #pragma unroll
@@ -203,13 +222,15 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
   // ---- right: rows r = (s, a) = s n + a of [0, w), columns c of [0, n), K = b in the block of c.
   // Wave w owns column tile w mod nct (Gr fragments loaded once) and every (8 / nct)-th row tile.
   const int nrt = (w + 15) / 16, nct = (n + 15) / 16, rstep = 8 / nct;
-  A4 yr[4], yi[4];
+  A4 yr[4], yi[4], yx[4];
   int gct = -1, k0 = 0, nks = 0;
   V2 gf[KS_MAX];
+  R gs[KS_MAX];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     yr[q] = A4{0, 0, 0, 0};
     yi[q] = yr[q];
+    yx[q] = yr[q];
     const int ct = wave % nct, rt = wave / nct + rstep * q;
     if (wave >= rstep * nct || rt >= nrt) continue;
     const int c = 16 * ct + li;
@@ -228,6 +249,7 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
         V2 g = Gr[cb.po + cc * cb.sz + (in ? kk : 0)];   // (Gr^H)[k][c] = conj Gr[c][k]
         g.y = -g.y;
         gf[ks] = in ? g : V2{0, 0};
+        gs[ks] = gf[ks].x + gf[ks].y;
       }
     }
     const int r = min(16 * rt + li, w - 1), s = r / n, a = r - s * n;
@@ -238,7 +260,7 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
         const int k = k0 + 4 * ks + kq;
         V2 x = arow[min(k, n - 1)];
         if (k >= n) x = V2{0, 0};
-        cmma<V2>(x, gf[ks], yr[q], yi[q]);
+        cmma<V2>(x, x.x + x.y, gf[ks], gs[ks], yr[q], yi[q], yx[q]);
       }
     }
   }
@@ -252,7 +274,7 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
       const int r = 16 * rt + M::row(lane, j);
       if (c < n && r < w) {
         const int s = r / n, a = r - s * n;
-        tile[a * ld + s * n + c] = V2{R(yr[q][j]), R(yi[q][j])};
+        tile[a * ld + s * n + c] = cval<V2>(yr[q], yi[q], yx[q], j);
       }
     }
   }
@@ -279,24 +301,25 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
         V2 g = Gl[rb.po + (in ? kk : 0) * rb.sz + aa];   // (Gl^H)[a'][k] = conj Gl[k][a']
         g.y = -g.y;
         gf[ks] = in ? g : V2{0, 0};
+        gs[ks] = gf[ks].x + gf[ks].y;
       }
     }
     const int jc = min(16 * ct + li, w - 1);
-    A4 cr = A4{0, 0, 0, 0}, ci = cr;
+    A4 cr = A4{0, 0, 0, 0}, ci = cr, cx = cr;
 #pragma unroll
     for (int ks = 0; ks < KS_MAX; ++ks) {
       if (ks < nks) {
         const int k = k0 + 4 * ks + kq;
         V2 y = tile[min(k, n - 1) * ld + jc];
         if (k >= n) y = V2{0, 0};
-        cmma<V2>(gf[ks], y, cr, ci);
+        cmma<V2>(gf[ks], gs[ks], y, y.x + y.y, cr, ci, cx);
       }
     }
     const int j = 16 * ct + li;
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       const int a = 16 * rt + M::row(lane, jj);
-      if (a < n && j < w) out[int64_t(a) * ncols + j] = V2{R(cr[jj]), R(ci[jj])};
+      if (a < n && j < w) out[int64_t(a) * ncols + j] = cval<V2>(cr, ci, cx, jj);
     }
   }
 }

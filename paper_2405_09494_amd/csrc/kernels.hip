@@ -498,36 +498,54 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   const int nchunk = N2 ? (tl.nn >> 1) : 1;
   const int nsub = (tl.t1 - tl.t0) * nk4, ngrp = (nsub + GS - 1) / GS, total = ngrp * nchunk;
   A4 c00r = {0, 0, 0, 0}, c00i = c00r, c01r = c00r, c01i = c00r, c10r = c00r, c10i = c00r, c11r = c00r, c11i = c00r;
+  // FP64 and FP32 forms take three real products per complex one (3M): the r, i and x
+  // accumulators hold sum a_r b_r, sum a_i b_i and sum (a_r + a_i)(b_r + b_i), and the complex
+  // sum is (r - i) + i (x - r - i); the split-bfloat16 forms keep real and imaginary parts
+  constexpr bool M3 = NS == 0;
+  A4 c00x = c00r, c01x = c00r, c10x = c00r, c11x = c00r;
   // FP32 forms: the FP32 accumulators are added into FP64 sums every 256 k values of the
   // sequence, so the rounding of a tile's sum does not grow with the length of its outer range
   constexpr bool F32 = !std::is_same<R, double>::value;
   constexpr int FLUSH = 256 / (4 * GS);   // groups per FP32 partial sum
   d4 s00r = {0, 0, 0, 0}, s00i = s00r, s01r = s00r, s01i = s00r, s10r = s00r, s10i = s00r, s11r = s00r, s11i = s00r;
   int since = 0;
+  // complex value of a tile's accumulators (in FP64 for the sums of the FP32 forms)
+  auto re_of = [&](const A4& r, const A4& i) __attribute__((always_inline)) {
+    const d4 dr = __builtin_convertvector(r, d4), di = __builtin_convertvector(i, d4);
+    return M3 ? dr - di : dr;
+  };
+  auto im_of = [&](const A4& r, const A4& i, const A4& x) __attribute__((always_inline)) {
+    const d4 dr = __builtin_convertvector(r, d4), di = __builtin_convertvector(i, d4);
+    return M3 ? __builtin_convertvector(x, d4) - dr - di : di;
+  };
   auto flush = [&]() __attribute__((always_inline)) {
     if constexpr (F32) {
       const A4 z = {0, 0, 0, 0};
-      s00r += __builtin_convertvector(c00r, d4);
-      s00i += __builtin_convertvector(c00i, d4);
+      s00r += re_of(c00r, c00i);
+      s00i += im_of(c00r, c00i, c00x);
       c00r = z;
       c00i = z;
+      c00x = z;
       if (N2) {
-        s01r += __builtin_convertvector(c01r, d4);
-        s01i += __builtin_convertvector(c01i, d4);
+        s01r += re_of(c01r, c01i);
+        s01i += im_of(c01r, c01i, c01x);
         c01r = z;
         c01i = z;
+        c01x = z;
       }
       if (M2) {
-        s10r += __builtin_convertvector(c10r, d4);
-        s10i += __builtin_convertvector(c10i, d4);
+        s10r += re_of(c10r, c10i);
+        s10i += im_of(c10r, c10i, c10x);
         c10r = z;
         c10i = z;
+        c10x = z;
       }
       if (M2 && N2) {
-        s11r += __builtin_convertvector(c11r, d4);
-        s11i += __builtin_convertvector(c11i, d4);
+        s11r += re_of(c11r, c11i);
+        s11i += im_of(c11r, c11i, c11x);
         c11r = z;
         c11i = z;
+        c11x = z;
       }
     }
   };
@@ -622,33 +640,24 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
         const R a0r = R(a[h][0].x), a0i = R(a[h][0].y) * sA, a1r = R(a[h][1].x), a1i = R(a[h][1].y) * sA;
         const R b0r = R(b[h][0].x) * m[h], b0i = R(b[h][0].y) * (sB * m[h]);
         const R b1r = R(b[h][1].x) * m[h], b1i = R(b[h][1].y) * (sB * m[h]);
+        const R a0s = a0r + a0i, a1s = a1r + a1i, b0s = b0r + b0i, b1s = b1r + b1i;
         c00r = mfma16(a0r, b0r, c00r);
-        c00i = mfma16(a0r, b0i, c00i);
+        c00i = mfma16(a0i, b0i, c00i);
+        c00x = mfma16(a0s, b0s, c00x);
         if (N2) {
           c01r = mfma16(a0r, b1r, c01r);
-          c01i = mfma16(a0r, b1i, c01i);
+          c01i = mfma16(a0i, b1i, c01i);
+          c01x = mfma16(a0s, b1s, c01x);
         }
         if (M2) {
           c10r = mfma16(a1r, b0r, c10r);
-          c10i = mfma16(a1r, b0i, c10i);
+          c10i = mfma16(a1i, b0i, c10i);
+          c10x = mfma16(a1s, b0s, c10x);
         }
         if (M2 && N2) {
           c11r = mfma16(a1r, b1r, c11r);
-          c11i = mfma16(a1r, b1i, c11i);
-        }
-        c00r = mfma16(-a0i, b0i, c00r);
-        c00i = mfma16(a0i, b0r, c00i);
-        if (N2) {
-          c01r = mfma16(-a0i, b1i, c01r);
-          c01i = mfma16(a0i, b1r, c01i);
-        }
-        if (M2) {
-          c10r = mfma16(-a1i, b0i, c10r);
-          c10i = mfma16(a1i, b0r, c10i);
-        }
-        if (M2 && N2) {
-          c11r = mfma16(-a1i, b1i, c11r);
-          c11i = mfma16(a1i, b1r, c11i);
+          c11i = mfma16(a1i, b1i, c11i);
+          c11x = mfma16(a1s, b1s, c11x);
         }
       }
     } else {
@@ -711,18 +720,22 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
         s11r = s00r;
         s11i = s00r;
       } else {
-        store(cn0, 0, 0, c00r, c00i);
-        if (N2) store(cn0, 0, 1, c01r, c01i);
-        if (M2) store(cn0, 1, 0, c10r, c10i);
-        if (M2 && N2) store(cn0, 1, 1, c11r, c11i);
+        store(cn0, 0, 0, re_of(c00r, c00i), im_of(c00r, c00i, c00x));
+        if (N2) store(cn0, 0, 1, re_of(c01r, c01i), im_of(c01r, c01i, c01x));
+        if (M2) store(cn0, 1, 0, re_of(c10r, c10i), im_of(c10r, c10i, c10x));
+        if (M2 && N2) store(cn0, 1, 1, re_of(c11r, c11i), im_of(c11r, c11i, c11x));
         c00r = A4{0, 0, 0, 0};
         c00i = c00r;
+        c00x = c00r;
         c01r = c00r;
         c01i = c00r;
+        c01x = c00r;
         c10r = c00r;
         c10i = c00r;
+        c10x = c00r;
         c11r = c00r;
         c11i = c00r;
+        c11x = c00r;
       }
       cp = 0;
       ++cc;
