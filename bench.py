@@ -80,8 +80,11 @@ CONTRACTIONS = {"polarization (eq. P0)": ("p0_contraction", "two_sided_block_mul
                 "self-energy (eq. sigma)": ("sigma_aux_contraction", "row_block_multiply", "sigma_orb_contraction")}
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.perf_counter() - _T0:7.1f} s]", *a, file=sys.stderr, flush=True)
 
 
 def make_ctx(wl, mode, half_tau=True, tau_chunk=0, precision=0, sched=0):
@@ -104,9 +107,15 @@ class Path:
         self.ctx, self.torch = ctx, torch
         self.graph = torch.cuda.Stream() if graph else None
         ctx.device_init()
+        log("[bench] device state initialised")
         ibz = torch.as_tensor(ctx.table("ibz"), device=dev)
-        ctx.load_V(V_src(ibz) if callable(V_src) else V_src[ibz].contiguous())
+        V = V_src(ibz) if callable(V_src) else V_src[ibz].contiguous()
         torch.cuda.synchronize()
+        log("[bench] irreducible rows of V ready")
+        ctx.load_V(V)
+        del V
+        torch.cuda.synchronize()
+        log("[bench] V in block form (both device copies)")
         z = lambda n: torch.zeros(n, dtype=torch.complex128, device=dev)
         self.F, self.G, self.P0, self.P, self.S = z(ctx.f_size), z(ctx.g_size), z(ctx.p_size), z(ctx.p_size), z(ctx.g_size)
         ctx.to_block(0, F_all[ibz].contiguous(), self.F)
@@ -343,7 +352,9 @@ def main():
 
     # ---- block-grouped, irreducible wedge, FP64 (the headline) ----
     t = time.perf_counter()
-    blk = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk), F_all, V_src, torch, dev,
+    ctx_blk = make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk)
+    log("[bench] symmetry-adapted basis built")
+    blk = Path(ctx_blk, F_all, V_src, torch, dev,
                graph=bool(args.graph))
     log(f"[bench] block path set up in {time.perf_counter() - t:.1f} s; N_target={blk.n_target:.6f}")
     t = time.perf_counter()

@@ -262,29 +262,62 @@ class Inputs:
                 out[c0:c0 + chunk] += T
         return out / self.h
 
+    def _paired_rows(self, p1: int):
+        """Paired V^{x,p2} for every p2 of the mesh and x in {p1, -p1}, as _paired_pairs makes
+        them, from the raw rows V^{x,.} and columns V^{.,x} drawn once: each pairing reads the
+        raw sets of x and of -x."""
+        m1 = int(self.mk[p1])
+        xs = [p1] if m1 == p1 else [p1, m1]
+        all_k = np.arange(self.nk)
+        row = {x: self._raw_pairs(np.full(self.nk, x), all_k) for x in xs}
+        col = {x: self._raw_pairs(all_k, np.full(self.nk, x)) for x in xs}
+        mk = torch.as_tensor(self.mk, device=self.device)
+        out = {}
+        for x in xs:
+            mx = int(self.mk[x])
+            W = row[x].clone()
+            W += col[x].conj().transpose(-1, -2)
+            W += row[mx][mk].conj()
+            W += col[mx][mk].transpose(-1, -2)
+            out[x] = W * 0.25
+        return out
+
     def _three_index_row(self, k1: int, k2s) -> torch.Tensor:
         """The same projection for pairs (k1, k2) with one k1: every operation alpha reads the raw
-        row p1 = alpha^{-1} k1, so each distinct p1 (the star of k1) is paired once and reused."""
+        row p1 = alpha^{-1} k1, so each distinct p1 (the star of k1) is paired once and reused,
+        together with -p1 when that is in the star too.  Per operation the orbital factors and
+        the auxiliary rotation run as large GEMMs: R^{p2} over the stacked rows (Q, a) of each
+        pair, the auxiliary template over Q (its column phases scale the rows first), and L over
+        the stacked columns (pair, Q, b)."""
         wl = self.wl
         dev = self.device
         k2s = np.asarray(k2s, dtype=np.int64)
-        out = torch.zeros((len(k2s), wl.naux, wl.nao, wl.nao), dtype=torch.complex128, device=dev)
+        npair, na, no = len(k2s), wl.naux, wl.nao
+        out = torch.zeros((npair, na, no, no), dtype=torch.complex128, device=dev)
         by_p1 = {}
         for a in range(self.h):
             by_p1.setdefault(int(self.inv_kmap[a, k1]), []).append(a)
-        all_k = np.arange(self.nk)
-        for p1, alphas in by_p1.items():
-            W = self._paired_pairs(np.full(self.nk, p1), all_k)      # W[p2] = paired V^{p1,p2}
-            for a in alphas:
-                p2 = self.inv_kmap[a, k2s]
-                q0 = self.sub[p1, p2]
-                Oao = self._omats(self.ao, a)
-                L = Oao[p1]
-                R = Oao[torch.as_tensor(p2, device=dev)].conj().transpose(-1, -2).contiguous()
-                X = self._omats(self.aux, a)[torch.as_tensor(q0, device=dev)]
-                T = L[None, None] @ W[torch.as_tensor(p2, device=dev)] @ R[:, None]
-                T = (X @ T.reshape(len(k2s), wl.naux, wl.nao * wl.nao)).reshape(T.shape)
-                out += T
+        done = set()
+        for p1 in by_p1:
+            if p1 in done:
+                continue
+            W = self._paired_rows(p1)
+            for x, Wx in W.items():
+                if x not in by_p1:
+                    continue
+                done.add(x)
+                for a in by_p1[x]:
+                    p2 = torch.as_tensor(self.inv_kmap[a, k2s], device=dev)
+                    q0 = torch.as_tensor(self.sub[x, self.inv_kmap[a, k2s]], device=dev)
+                    Oao = self._omats(self.ao, a)
+                    L = Oao[x]
+                    R = Oao[p2].conj().transpose(-1, -2)
+                    T = Wx[p2].reshape(npair, na * no, no) @ R                       # V R
+                    ph = self._t(self.aux.column_phases(a))[q0]                     # [pair, Q]
+                    T = (T.reshape(npair, na, no * no) * ph[:, :, None]).reshape(npair, na, no * no)
+                    T = self._t(self.aux.template(a)) @ T                            # O_aux V R
+                    T = T.reshape(npair * na, no, no).transpose(1, 2).reshape(-1, no) @ L.transpose(0, 1)
+                    out += T.reshape(npair, na, no, no).transpose(-1, -2)            # L (.) per matrix
             del W
         return out / self.h
 

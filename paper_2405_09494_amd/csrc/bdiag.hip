@@ -100,39 +100,37 @@ __device__ __forceinline__ void tile_span(const int* __restrict__ bt, int t0, in
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-// One 16 x 16 output tile over the K range of its blocks: the block-diagonal factor's
-// fragments (one per lane and K step of four) are loaded into registers first, all at once, so
-// their latencies overlap; the other operand's fragments come from LDS inside the MFMA loop.
-// KS_MAX: K steps of the widest tile (n <= 4 KS_MAX).
-constexpr int KS_MAX = 16;
+// Each 16 x 16 output tile runs over the K range of its blocks only.  The block-diagonal
+// factor's fragments (one per lane and K step of four) are loaded into registers once per
+// workgroup, branch-free, so their latencies overlap; the other operand's fragments come from
+// LDS inside the MFMA loop.
 
-// k_bd_right: a workgroup of four waves stages 64 rows of one slab in LDS (row stride n + 1).
-// Wave w owns one column tile (w mod nct) and a share of the four row tiles; it loads the
-// fragments of G (and, for a segment with out_off2 >= 0, of G2) for that column tile once and
-// reuses them for all of its row tiles.  out[r][c] = sum_k in[r][k] G[k][c], k in the block of c.
-template <typename V2>
-__global__ __launch_bounds__(256) void k_bd_right(const RowSeg* __restrict__ segs, Bases bases,
-                                                  const int* __restrict__ btab, int n) {
+// k_bd_right: out[r][c] = sum_k in[r][k] G[k][c] (k in the block of c) over the rows of one
+// segment, and, for a segment with out_off2 >= 0, out2 the same with G2.  A workgroup of eight
+// waves walks `per` consecutive chunks of 64 rows of one segment: wave w owns column tile
+// w mod nct and every (8 / nct)-th row tile, loads its fragments of G (and G2) once and keeps
+// them for every chunk; the next chunk is loaded into registers (all loads in flight at once)
+// while the current one is multiplied out of LDS.  KS: K steps of the widest column tile
+// (n <= 4 KS); PF: chunk elements per thread (64 n / 512).
+
+template <typename V2, int KS, int PF>
+__global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ segs, Bases bases,
+                                                  const int* __restrict__ btab, int n, int per) {
   using M = Mf<V2>;
   using R = typename M::R;
   using A4 = typename M::A4;
   extern __shared__ double2 lds_right[];
   V2* rows = reinterpret_cast<V2*>(lds_right);
   const RowSeg sg = segs[blockIdx.y];
-  const int r0 = blockIdx.x * 64;
-  if (r0 >= sg.nrows) return;
-  const int nr = min(64, sg.nrows - r0), ld = n + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, kq = lane >> 4;
-  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + int64_t(r0) * n;
-  for (int e = threadIdx.x; e < nr * n; e += 256) {
-    const int r = e / n;
-    rows[r * ld + (e - r * n)] = in[e];
-  }
-  __syncthreads();
+  const int nch = (sg.nrows + 63) / 64;
+  const int c0 = blockIdx.x * per;
+  if (c0 >= nch) return;
+  const int c1 = min(nch, c0 + per), ld = n + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, kq = lane >> 4;
   const bool dual = sg.out_off2 >= 0;   // uniform over the workgroup
-  const int nct = (n + 15) / 16, nrt = (nr + 15) / 16;
-  if (wave >= 4 / nct * nct) return;    // three column tiles: the fourth wave has none
-  const int ct = wave % nct, rstep = 4 / nct;
+  const int nct = (n + 15) / 16, rstep = 8 / nct;
+  const bool act = wave < rstep * nct;  // three column tiles: the last two waves have none
+  const int ct = wave % nct;
   const int* bt = btab + sg.blk;
   const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
   const V2* G2 = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + (dual ? sg.g_off2 : sg.g_off);
@@ -140,202 +138,298 @@ __global__ __launch_bounds__(256) void k_bd_right(const RowSeg* __restrict__ seg
   tile_span(bt, 16 * ct, n, lo, hi);
   const int k0 = lo & ~3, nks = (hi - k0 + 3) / 4;
   const int c = 16 * ct + li;
-  const BlkOf cb = blk_lookup(bt, min(c, n - 1));
-  const int cc = min(c, n - 1) - cb.off;
-  // every lane loads an in-block address (its own column's first element when k is outside
-  // the block) and zeroes what lies outside: no branches, so the loads stay in flight together
-  V2 gf[KS_MAX], gf2[KS_MAX];
+  V2 gf[KS], gf2[KS];
+  {
+    const BlkOf cb = blk_lookup(bt, min(c, n - 1));
+    const int cc = min(c, n - 1) - cb.off;
+    // every lane loads an in-block address and zeroes what lies outside: no branches
 #pragma unroll
-  for (int ks = 0; ks < KS_MAX; ++ks) {
-    const int kk = k0 + 4 * ks + kq - cb.off;
-    const bool in_b = ks < nks && c < n && kk >= 0 && kk < cb.sz;
-    const int ge = cb.po + (in_b ? kk : 0) * cb.sz + cc;
-    const V2 g = G[ge], g2 = G2[ge];
-    gf[ks] = in_b ? g : V2{0, 0};
-    gf2[ks] = in_b ? g2 : V2{0, 0};
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kk = k0 + 4 * ks + kq - cb.off;
+      const bool in_b = act && ks < nks && c < n && kk >= 0 && kk < cb.sz;
+      const int ge = cb.po + (in_b ? kk : 0) * cb.sz + cc;
+      const V2 g = G[ge], g2 = G2[ge];
+      gf[ks] = in_b ? g : V2{0, 0};
+      gf2[ks] = in_b ? g2 : V2{0, 0};
+    }
   }
-  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + int64_t(r0) * n;
-  V2* out2 = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + (dual ? sg.out_off2 : sg.out_off) + int64_t(r0) * n;
-  for (int rt = wave / nct; rt < nrt; rt += rstep) {   // uniform
-    const V2* arow = rows + min(16 * rt + li, nr - 1) * ld;
-    A4 cr = A4{0, 0, 0, 0}, ci = cr, dr = cr, di = cr;
+  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off;
+  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off;
+  V2* out2 = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + (dual ? sg.out_off2 : sg.out_off);
+  R pfx[PF], pfy[PF];   // real and imaginary parts apart: arrays of scalars stay in registers
+  auto height = [&](int ch) { return min(64, sg.nrows - 64 * ch); };
+  auto fetch = [&](int ch) {   // past the chunk's end every lane reloads element 0: no branches
+    const int ne = height(ch) * n;
+    const V2* src = in + int64_t(ch) * 64 * n;
 #pragma unroll
-    for (int ks = 0; ks < KS_MAX; ++ks) {
-      if (ks < nks) {   // uniform
-        const int k = k0 + 4 * ks + kq;
-        V2 a = arow[min(k, n - 1)];
-        if (k >= n) a = V2{0, 0};
-        cmma4<V2>(a, gf[ks], cr, ci);
-        if (dual) cmma4<V2>(a, gf2[ks], dr, di);
+    for (int t = 0; t < PF; ++t) {
+      const int e = tid + 512 * t;
+      const V2 v = src[e < ne ? e : 0];
+      pfx[t] = v.x;
+      pfy[t] = v.y;
+    }
+  };
+  auto stash = [&](int ch) {
+    const int ne = height(ch) * n;
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int e = tid + 512 * t;
+      if (e < ne) {
+        const int r = e / n;
+        rows[r * ld + (e - r * n)] = V2{pfx[t], pfy[t]};
       }
     }
+  };
+  fetch(c0);
+  stash(c0);
+  if (c0 + 1 < c1) fetch(c0 + 1);
+  __syncthreads();
+  for (int ch = c0; ch < c1; ++ch) {
+    const int nr = height(ch), nrt = (nr + 15) / 16;
+    const int64_t obase = int64_t(ch) * 64 * n;
+    if (act) {
+      for (int rt = wave / nct; rt < nrt; rt += rstep) {   // uniform
+        const V2* arow = rows + min(16 * rt + li, nr - 1) * ld;
+        A4 cr = A4{0, 0, 0, 0}, ci = cr, dr = cr, di = cr;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 16 * rt + M::row(lane, j);
-      if (c < n && r < nr) {
-        out[int64_t(r) * n + c] = V2{R(cr[j]), R(ci[j])};
-        if (dual) out2[int64_t(r) * n + c] = V2{R(dr[j]), R(di[j])};
+        for (int ks = 0; ks < KS; ++ks) {
+          if (ks < nks) {   // uniform
+            const int k = k0 + 4 * ks + kq;
+            V2 a = arow[min(k, n - 1)];
+            if (k >= n) a = V2{0, 0};
+            cmma4<V2>(a, gf[ks], cr, ci);
+            if (dual) cmma4<V2>(a, gf2[ks], dr, di);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = 16 * rt + M::row(lane, j);
+          if (c < n && r < nr) {
+            out[obase + int64_t(r) * n + c] = V2{R(cr[j]), R(ci[j])};
+            if (dual) out2[obase + int64_t(r) * n + c] = V2{R(dr[j]), R(di[j])};
+          }
+        }
       }
+    }
+    if (ch + 1 < c1) {
+      __syncthreads();   // every wave is done with this chunk's rows
+      stash(ch + 1);
+      if (ch + 2 < c1) fetch(ch + 2);
+      __syncthreads();
     }
   }
 }
 
 void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s, bool fp32) {
   if (l.nseg == 0) return;
-  const dim3 g((l.maxrows + 63) / 64, l.nseg);
+  const int nch = (l.maxrows + 63) / 64;   // chunks of the tallest segment
+  // about sixteen workgroups per CU over the launch, each walking `per` chunks of one segment
+  const int ptarget = int(std::max<long>(1, std::min<long>(nch, long(nch) * l.nseg / 4096)));
+  const int parts = (nch + ptarget - 1) / ptarget;
+  const int per = (nch + parts - 1) / parts;
+  const dim3 g(parts, l.nseg);
   const RowSeg* sg = (const RowSeg*)l.segs;
   const size_t lds = size_t(64) * (ncol + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
-  if (fp32) hipLaunchKernelGGL(k_bd_right<float2>, g, dim3(256), lds, s, sg, b, btab, ncol);
-  else hipLaunchKernelGGL(k_bd_right<double2>, g, dim3(256), lds, s, sg, b, btab, ncol);
+  if (ncol <= 52) {
+    if (fp32) hipLaunchKernelGGL((k_bd_right<float2, 13, 7>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+    else hipLaunchKernelGGL((k_bd_right<double2, 13, 7>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+  } else {
+    if (fp32) hipLaunchKernelGGL((k_bd_right<float2, 16, 8>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+    else hipLaunchKernelGGL((k_bd_right<double2, 16, 8>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
-// k_bd_both: eight waves; the slice of S matrices (n x S n, row stride ld = S n + 1 in LDS).
-// Right product Y = X Gr^H over the rows (s, a) (items: row tile x column tile, at most four
-// per wave, held in registers until every wave has read the slice, then written back in
-// place); left product W = Gl^H Y over the columns (s, b) (written to global memory).
-template <typename V2>
+// ---------------------------------------------------------------------------------------
+// k_bd_both: W_s = Gl^H X_s Gr^H for the matrices s of one segment (a slab of n rows and
+// na n columns, matrix s in columns [s n, (s + 1) n)).  A workgroup of eight waves walks `per`
+// consecutive groups of S matrices (S n <= 64) of one segment.  Each wave loads its fragments
+// of Gr^H (one column tile) and Gl^H (one row tile) once and keeps them for every group; a
+// group's slice of X is loaded into registers while the previous group is being multiplied,
+// then stored to LDS (X), the right product goes to a second LDS buffer (Y) and the left
+// product straight to global memory.
+// KS: K steps of the widest tile (n <= 4 KS); PF: slice elements per thread, n (S n) / 512.
+constexpr int BOTH_WAVES = 8;
+
+template <typename V2, int KS, int PF>
 __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs, Bases bases,
-                                                 const int* __restrict__ btab, int n, int S) {
+                                                 const int* __restrict__ btab, int n, int S, int per) {
   using M = Mf<V2>;
   using R = typename M::R;
   using A4 = typename M::A4;
   extern __shared__ double2 lds_both[];
-  V2* tile = reinterpret_cast<V2*>(lds_both);
   const RowSeg sg = segs[blockIdx.y];
   const int ncols = sg.nrows;   // slab width: na matrices of n columns side by side
-  const int s0 = blockIdx.x * S;
-  if (s0 * n >= ncols) return;
-  const int sv = min(S, ncols / n - s0), w = sv * n, ld = S * n + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, kq = lane >> 4;
-  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off + s0 * n;
-  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off + s0 * n;
+  const int nmat = ncols / n, ngrp = (nmat + S - 1) / S;
+  const int g0 = blockIdx.x * per;
+  if (g0 >= ngrp) return;
+  const int g1 = min(ngrp, g0 + per);
+  const int ld = S * n + 1;
+  V2* X = reinterpret_cast<V2*>(lds_both);
+  V2* Y = X + n * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, kq = lane >> 4;
+  const V2* in = reinterpret_cast<const V2*>(bases.p[sg.inbuf]) + sg.in_off;
+  V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off;
   const V2* Gl = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
   const V2* Gr = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off2;
   const int* btl = btab + sg.blk;
   const int* btr = btab + sg.blk2;
-  for (int e = threadIdx.x; e < n * w; e += 512) {
-    const int a = e / w, j = e - a * w;
-    tile[a * ld + j] = in[int64_t(a) * ncols + j];
-  }
-  __syncthreads();
-  // ---- right: rows r = (s, a) = s n + a of [0, w), columns c of [0, n), K = b in the block of c.
-  // Wave w owns column tile w mod nct (Gr fragments loaded once) and every (8 / nct)-th row tile.
-  const int nrt = (w + 15) / 16, nct = (n + 15) / 16, rstep = 8 / nct;
-  A4 yr[4], yi[4], yx[4];
-  int gct = -1, k0 = 0, nks = 0;
-  V2 gf[KS_MAX];
-  R gs[KS_MAX];
+
+  // ---- held fragments.  Right product: wave -> column tile ctr = wave mod nct, row tiles
+  // wave / nct + rstep j.  Left product: wave -> row tile rtl = wave mod nrt2, column tiles
+  // wave / nrt2 + cstep j.  nct, nrt2 <= 4, so each wave has at most two items per pass.
+  const int nct = (n + 15) / 16, rstep = BOTH_WAVES / nct;
+  const int nrt2 = nct, cstep = rstep;
+  const bool act = wave < rstep * nct;   // waves beyond the last full round have no items
+  const int ctr = wave % nct, rtl = wave % nrt2;
+  int k0r, nksr, k0l, nksl;
+  V2 gr[KS], gl[KS];
+  {
+    int lo, hi;
+    tile_span(btr, 16 * ctr, n, lo, hi);
+    k0r = lo & ~3;
+    nksr = (hi - k0r + 3) / 4;
+    const int c = 16 * ctr + li;
+    const BlkOf cb = blk_lookup(btr, min(c, n - 1));
+    const int cc = min(c, n - 1) - cb.off;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    yr[q] = A4{0, 0, 0, 0};
-    yi[q] = yr[q];
-    yx[q] = yr[q];
-    const int ct = wave % nct, rt = wave / nct + rstep * q;
-    if (wave >= rstep * nct || rt >= nrt) continue;
-    const int c = 16 * ct + li;
-    if (ct != gct) {
-      gct = ct;
-      int lo, hi;
-      tile_span(btr, 16 * ct, n, lo, hi);
-      k0 = lo & ~3;
-      nks = (hi - k0 + 3) / 4;
-      const BlkOf cb = blk_lookup(btr, min(c, n - 1));
-      const int cc = min(c, n - 1) - cb.off;
-#pragma unroll
-      for (int ks = 0; ks < KS_MAX; ++ks) {
-        const int kk = k0 + 4 * ks + kq - cb.off;
-        const bool in = ks < nks && c < n && kk >= 0 && kk < cb.sz;
-        V2 g = Gr[cb.po + cc * cb.sz + (in ? kk : 0)];   // (Gr^H)[k][c] = conj Gr[c][k]
-        g.y = -g.y;
-        gf[ks] = in ? g : V2{0, 0};
-        gs[ks] = gf[ks].x + gf[ks].y;
-      }
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kk = k0r + 4 * ks + kq - cb.off;
+      const bool ok = act && ks < nksr && c < n && kk >= 0 && kk < cb.sz;
+      V2 g = Gr[cb.po + cc * cb.sz + (ok ? kk : 0)];   // (Gr^H)[k][c] = conj Gr[c][k]
+      g.y = -g.y;
+      gr[ks] = ok ? g : V2{0, 0};
     }
-    const int r = min(16 * rt + li, w - 1), s = r / n, a = r - s * n;
-    const V2* arow = tile + a * ld + s * n;
+    tile_span(btl, 16 * rtl, n, lo, hi);
+    k0l = lo & ~3;
+    nksl = (hi - k0l + 3) / 4;
+    const int ap = 16 * rtl + li;
+    const BlkOf rb = blk_lookup(btl, min(ap, n - 1));
+    const int aa = min(ap, n - 1) - rb.off;
 #pragma unroll
-    for (int ks = 0; ks < KS_MAX; ++ks) {
-      if (ks < nks) {
-        const int k = k0 + 4 * ks + kq;
-        V2 x = arow[min(k, n - 1)];
-        if (k >= n) x = V2{0, 0};
-        cmma<V2>(x, x.x + x.y, gf[ks], gs[ks], yr[q], yi[q], yx[q]);
-      }
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kk = k0l + 4 * ks + kq - rb.off;
+      const bool ok = act && ks < nksl && ap < n && kk >= 0 && kk < rb.sz;
+      V2 g = Gl[rb.po + (ok ? kk : 0) * rb.sz + aa];   // (Gl^H)[a'][k] = conj Gl[k][a']
+      g.y = -g.y;
+      gl[ks] = ok ? g : V2{0, 0};
     }
   }
+
+  // ---- slices: element e = a w + j of group g (w = matrices of the group times n)
+  R pfx[PF], pfy[PF];   // real and imaginary parts apart: arrays of scalars stay in registers
+  auto width = [&](int g) { return min(S, nmat - g * S) * n; };
+  auto fetch = [&](int g) {   // past the slice's end every lane reloads element 0: no branches
+    const int w = width(g);
+    const V2* src = in + int64_t(g) * S * n;
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int e = tid + 512 * t, ec = e < n * w ? e : 0;
+      const int a = ec / w, j = ec - a * w;
+      const V2 v = src[int64_t(a) * ncols + j];
+      pfx[t] = v.x;
+      pfy[t] = v.y;
+    }
+  };
+  auto stash = [&](int g) {
+    const int w = width(g);
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int e = tid + 512 * t;
+      if (e < n * w) {
+        const int a = e / w, j = e - a * w;
+        X[a * ld + j] = V2{pfx[t], pfy[t]};
+      }
+    }
+  };
+  fetch(g0);
+  stash(g0);
+  if (g0 + 1 < g1) fetch(g0 + 1);
   __syncthreads();
+  for (int g = g0; g < g1; ++g) {
+    const int w = width(g), nrt = (w + 15) / 16;
+    // right: Y[a][s n + c] = sum_b X[a][s n + b] Gr^H[b][c], rows r = s n + a of [0, w)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int ct = wave % nct, rt = wave / nct + rstep * q, c = 16 * ct + li;
-    if (wave >= rstep * nct || rt >= nrt) continue;
+    for (int jt = 0; jt < 2; ++jt) {
+      const int rt = wave / nct + rstep * jt;
+      if (!act || rt >= nrt) break;   // uniform per wave
+      const int r = min(16 * rt + li, w - 1), s = r / n, a = r - s * n;
+      const V2* arow = X + a * ld + s * n;
+      A4 cr = A4{0, 0, 0, 0}, ci = cr, cx = cr;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = 16 * rt + M::row(lane, j);
-      if (c < n && r < w) {
-        const int s = r / n, a = r - s * n;
-        tile[a * ld + s * n + c] = cval<V2>(yr[q], yi[q], yx[q], j);
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks < nksr) {
+          const int k = k0r + 4 * ks + kq;
+          V2 x = arow[min(k, n - 1)];
+          if (k >= n) x = V2{0, 0};
+          cmma<V2>(x, x.x + x.y, gr[ks], gr[ks].x + gr[ks].y, cr, ci, cx);
+        }
+      }
+      const int c = 16 * ctr + li;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rr = 16 * rt + M::row(lane, j);
+        if (c < n && rr < w) {
+          const int s2 = rr / n, a2 = rr - s2 * n;
+          Y[a2 * ld + s2 * n + c] = cval<V2>(cr, ci, cx, j);
+        }
       }
     }
-  }
-  __syncthreads();
-  // ---- left: rows a' of [0, n), columns j of [0, w), K = a in the block of a'.  Wave w owns
-  // row tile w mod nrt2 (Gl fragments loaded once) and every (8 / nrt2)-th column tile.
-  const int nrt2 = (n + 15) / 16, nct2 = (w + 15) / 16, cstep = 8 / nrt2;
-  int grt = -1;
-  for (int ct = wave / nrt2; ct < nct2 && wave < cstep * nrt2; ct += cstep) {
-    const int rt = wave % nrt2;
-    const int ap = 16 * rt + li;
-    if (rt != grt) {
-      grt = rt;
-      int lo, hi;
-      tile_span(btl, 16 * rt, n, lo, hi);
-      k0 = lo & ~3;
-      nks = (hi - k0 + 3) / 4;
-      const BlkOf rb = blk_lookup(btl, min(ap, n - 1));
-      const int aa = min(ap, n - 1) - rb.off;
+    __syncthreads();   // Y complete, X free
+    if (g + 1 < g1) {
+      stash(g + 1);
+      if (g + 2 < g1) fetch(g + 2);
+    }
+    // left: W[a'][s n + b] = sum_a Gl^H[a'][a] Y[a][s n + b], to global memory
+    V2* dst = out + int64_t(g) * S * n;
 #pragma unroll
-      for (int ks = 0; ks < KS_MAX; ++ks) {
-        const int kk = k0 + 4 * ks + kq - rb.off;
-        const bool in = ks < nks && ap < n && kk >= 0 && kk < rb.sz;
-        V2 g = Gl[rb.po + (in ? kk : 0) * rb.sz + aa];   // (Gl^H)[a'][k] = conj Gl[k][a']
-        g.y = -g.y;
-        gf[ks] = in ? g : V2{0, 0};
-        gs[ks] = gf[ks].x + gf[ks].y;
+    for (int jt = 0; jt < 2; ++jt) {
+      const int ct = wave / nrt2 + cstep * jt;
+      if (!act || ct >= nrt) break;   // column tiles of the group: same count as row tiles above
+      const int jc = min(16 * ct + li, w - 1);
+      A4 cr = A4{0, 0, 0, 0}, ci = cr, cx = cr;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if (ks < nksl) {
+          const int k = k0l + 4 * ks + kq;
+          V2 y = Y[min(k, n - 1) * ld + jc];
+          if (k >= n) y = V2{0, 0};
+          cmma<V2>(gl[ks], gl[ks].x + gl[ks].y, y, y.x + y.y, cr, ci, cx);
+        }
+      }
+      const int jj = 16 * ct + li;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int a = 16 * rtl + M::row(lane, j);
+        if (a < n && jj < w) dst[int64_t(a) * ncols + jj] = cval<V2>(cr, ci, cx, j);
       }
     }
-    const int jc = min(16 * ct + li, w - 1);
-    A4 cr = A4{0, 0, 0, 0}, ci = cr, cx = cr;
-#pragma unroll
-    for (int ks = 0; ks < KS_MAX; ++ks) {
-      if (ks < nks) {
-        const int k = k0 + 4 * ks + kq;
-        V2 y = tile[min(k, n - 1) * ld + jc];
-        if (k >= n) y = V2{0, 0};
-        cmma<V2>(gf[ks], gs[ks], y, y.x + y.y, cr, ci, cx);
-      }
-    }
-    const int j = 16 * ct + li;
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int a = 16 * rt + M::row(lane, jj);
-      if (a < n && j < w) out[int64_t(a) * ncols + j] = cval<V2>(cr, ci, cx, jj);
-    }
+    __syncthreads();   // Y free, the next slice in X
   }
 }
 
-// matrices per workgroup: the right product's rows (s, a) fill at most eight 16-row tiles, so
-// that its items fit four per wave
-inline int both_S(int n) { return std::max(1, 128 / n); }
+// groups of S matrices: the right product's rows (s, a) fill at most four 16-row tiles
+inline int both_S(int n) { return std::max(1, 64 / n); }
 
 void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, int n, hipStream_t s, bool fp32) {
   if (l.nseg == 0) return;
   const int S = both_S(n);
-  const dim3 g((l.maxrows / n + S - 1) / S, l.nseg);
+  const int ngrp = (l.maxrows / n + S - 1) / S;   // groups of the widest segment
+  // about sixteen workgroups per CU over the launch, each walking `per` groups of one segment
+  const int ptarget = int(std::max<long>(1, std::min<long>(ngrp, long(ngrp) * l.nseg / 4096)));
+  const int parts = (ngrp + ptarget - 1) / ptarget;
+  const int per = (ngrp + parts - 1) / parts;
+  const dim3 g(parts, l.nseg);
   const RowSeg* sg = (const RowSeg*)l.segs;
-  const size_t lds = size_t(n) * (S * n + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
-  if (fp32) hipLaunchKernelGGL(k_bd_both<float2>, g, dim3(512), lds, s, sg, b, btab, n, S);
-  else hipLaunchKernelGGL(k_bd_both<double2>, g, dim3(512), lds, s, sg, b, btab, n, S);
+  const size_t lds = 2 * size_t(n) * (S * n + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
+  // n <= 52: n (S n) <= 52 * 52 (S = 1) or 64 * 32 (S >= 2), six elements per thread
+  if (n <= 52) {
+    if (fp32) hipLaunchKernelGGL((k_bd_both<float2, 13, 6>), g, dim3(512), lds, s, sg, b, btab, n, S, per);
+    else hipLaunchKernelGGL((k_bd_both<double2, 13, 6>), g, dim3(512), lds, s, sg, b, btab, n, S, per);
+  } else {
+    if (fp32) hipLaunchKernelGGL((k_bd_both<float2, 16, 8>), g, dim3(512), lds, s, sg, b, btab, n, S, per);
+    else hipLaunchKernelGGL((k_bd_both<double2, 16, 8>), g, dim3(512), lds, s, sg, b, btab, n, S, per);
+  }
 }
 
 }  // namespace gw

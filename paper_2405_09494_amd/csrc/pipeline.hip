@@ -6,8 +6,14 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 #include <cmath>
+#include <atomic>
+#include <thread>
+#include <cstdlib>
+#include <cstdio>
+#include <chrono>
 #include <cstring>
 #include <numeric>
 #include <tuple>
@@ -15,6 +21,20 @@
 #include "kernel_api.hpp"
 
 namespace gw {
+
+namespace {
+// GWSYM_VERBOSE set in the environment: host set-up phases print their wall time to stderr
+struct PhaseClock {
+  bool on = std::getenv("GWSYM_VERBOSE") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[gwsym] %s: %.2f s\n", what, std::chrono::duration<double>(now - t).count());
+    t = now;
+  }
+};
+}  // namespace
 
 namespace {
 
@@ -44,6 +64,14 @@ inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vec
       return std::make_tuple(a.prob, a.batch, a.t0, a.tn, a.tm) < std::make_tuple(b.prob, b.batch, b.t0, b.tn, b.tm);
     });
   using Key = std::array<i64, 5>;
+  struct KeyHash {
+    size_t operator()(const Key& k) const {
+      uint64_t h = 0x9e3779b97f4a7c15ull;
+      for (i64 v : k) h = (h ^ uint64_t(v)) * 0x100000001b3ull + (h >> 29);
+      return size_t(h);
+    }
+  };
+  using Count = std::unordered_map<Key, int, KeyHash>;
   auto keyA = [&](const GemmTile& t) {
     const GemmProblem& p = probs[t.prob];
     return Key{p.abuf, p.aoff + i64(t.batch) * p.sAb, t.tm, t.t0, 0};
@@ -52,12 +80,15 @@ inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vec
     const GemmProblem& p = probs[t.prob];
     return Key{p.bbuf, p.boff + i64(t.batch) * p.sBb, t.tn, t.t0, 1};
   };
-  std::map<Key, int> ca, cb;
+  // hashed counts: the lists reach millions of tiles at the 6x6x6 workloads
+  Count ca, cb;
+  ca.reserve(size_t(n));
+  cb.reserve(size_t(n));
   for (int i = t0; i < int(tiles.size()); ++i) {
     ca[keyA(tiles[i])]++;
     cb[keyB(tiles[i])]++;
   }
-  std::map<Key, int> gid;
+  Count gid;
   std::vector<std::vector<int>> groups;
   // a problem whose operands fit in an L2 comfortably keeps all its tiles on one XCD
   auto small = [&](const GemmTile& t) {
@@ -125,30 +156,50 @@ struct GemmStage {
     pending_bytes += 16.0 * p.batch * (double(p.K) * p.T * (double(p.M) + p.N) + double(p.M) * p.N);
   }
   double pending_macs = 0, pending_bytes = 0;
-  void xcd_order(int t0, int mode = 1) { xcd_order_tiles(tiles, t0, probs, mode); }
-  // Closes a launch: turns its problems into tiles; problems with a long outer loop are
-  // split so that the launch has about `target` workgroups.
+  // Closes a launch: records its problems and the plan settings; the tiles are made later by
+  // finalize(), for every closed launch at once (in parallel), in launch order.
   bool wave = false;   // tiles for the wave-tile kernel: 32-column chunks, more of them
   // wave-tile plan: workgroups a launch aims for, 32-column chunks per tile, XCD order,
   // bfloat16 k depth (0: per launch)
   int target = 8192, per = 1, kdepth = 0, prefetch = 2;
   int xcd = 1;   // 0 plain order, 1 grouped by shared operand rows, 2 grouped by problem
+  struct Deferred {
+    std::vector<int> ids;
+    int target, per, kdepth, prefetch, xcd;
+    bool wave;
+  };
+  std::vector<Deferred> deferred;   // launches [built, launches.size()) not yet made into tiles
+  size_t built = 0;
   void close() {
-    const int target = wave ? this->target : 2048;
     Range r;
-    r.t0 = int(tiles.size());
-    r.r0 = int(reds.size());
-    // tiles of 32 rows (columns), the last one 16 when the remainder allows
-    auto units = [](int n) { return (n + 15) / 16; };
-    long base = 0;
-    for (int id : pending) {
-      const GemmProblem& p = probs[id];
-      base += long(p.batch) * ((units(p.M) + 1) / 2) * ((units(p.N) + 1) / 2);
-    }
     r.macs = pending_macs;
     r.bytes = pending_bytes;
     pending_macs = 0;
     pending_bytes = 0;
+    launches.push_back(r);
+    deferred.push_back({std::move(pending), target, per, kdepth, prefetch, xcd, wave});
+    pending.clear();
+  }
+  // One launch's tiles (problems with a long outer loop split so that the launch has about
+  // `target` workgroups) and split-K reductions, with slot numbers local to the launch.
+  struct Built {
+    std::vector<GemmTile> tiles;
+    std::vector<GemmReduce> reds;
+    int shape[4] = {0, 0, 0, 0};
+    int kdepth = 32, slots = 0;
+  };
+  Built build(const Deferred& L) const {
+    const int target = L.wave ? L.target : 2048;
+    Built out;
+    std::vector<GemmTile>& tiles = out.tiles;
+    std::vector<GemmReduce>& reds = out.reds;
+    // tiles of 32 rows (columns), the last one 16 when the remainder allows
+    auto units = [](int n) { return (n + 15) / 16; };
+    long base = 0;
+    for (int id : L.ids) {
+      const GemmProblem& p = probs[id];
+      base += long(p.batch) * ((units(p.M) + 1) / 2) * ((units(p.N) + 1) / 2);
+    }
     int slots = 0;
     // a tile of rows [16 i, 16 (i + mh)) and columns [16 j, 16 (j + nn)) of a lower-only problem
     // is needed when some row r and column c in it have r >= c mod cdiv
@@ -160,7 +211,7 @@ struct GemmStage {
       const int cmin = (c0 / p.cdiv != (c1 - 1) / p.cdiv) ? 0 : c0 % p.cdiv;
       return rmax >= cmin;
     };
-    for (int id : pending) {
+    for (int id : L.ids) {
       const GemmProblem& p = probs[id];
       const int mu = units(p.M), nu = units(p.N);
       int split = 1;
@@ -171,12 +222,12 @@ struct GemmStage {
         for (int i = 0; i < mu; i += 2) {
           const int mh = std::min(2, mu - i);
           if (split == 1) {
-            if (wave) {
+            if (L.wave) {
               // one full 32-column chunk per wave (a wave can walk several: nn = 2 x chunks),
               // a last 16-column unit on its own
               const int full = nu / 2;
-              for (int j = 0; j < full; j += per) {
-                const int nn = 2 * std::min(per, full - j);
+              for (int j = 0; j < full; j += L.per) {
+                const int nn = 2 * std::min(L.per, full - j);
                 if (keep(id, i, mh, 2 * j, nn)) tiles.push_back({id, b, i, 2 * j, 0, p.T, -1, mh, nn, 0});
               }
               if (nu % 2 && keep(id, i, mh, 2 * full, 1)) tiles.push_back({id, b, i, 2 * full, 0, p.T, -1, mh, 1, 0});
@@ -200,38 +251,64 @@ struct GemmStage {
           }
         }
     }
-    if (wave) {
+    if (L.wave) {
       // sort by shape class (rows 32? columns 32?), each class in XCD order of its own
-      std::vector<GemmTile> all(tiles.begin() + r.t0, tiles.end());
-      tiles.resize(r.t0);
+      std::vector<GemmTile> all(std::move(tiles));
+      tiles.clear();
       for (int sh = 0; sh < 4; ++sh) {
         const int c0 = int(tiles.size());
         for (const GemmTile& t : all)
           if ((t.mh == 2) * 2 + (t.nn >= 2) == sh) tiles.push_back(t);
-        if (xcd) xcd_order(c0, xcd);
-        r.shape[sh] = int(tiles.size()) - c0;
+        if (L.xcd) xcd_order_tiles(tiles, c0, probs, L.xcd);
+        out.shape[sh] = int(tiles.size()) - c0;
       }
     } else {
-      xcd_order(r.t0);
+      xcd_order_tiles(tiles, 0, probs);
     }
-    r.nt = int(tiles.size()) - r.t0;
-    r.nr = int(reds.size()) - r.r0;
     // k depth of the bfloat16 MFMA: a tile walks ceil(K/4) sub-steps per outer index in groups
     // of 8 (32-deep) or 4 (16-deep), the last group padded; 16-deep where 32 would pad more
     // than a quarter of the work
     double sub = 0, pad8 = 0;
-    for (int t = r.t0; t < r.t0 + r.nt; ++t) {
+    for (size_t t = 0; t < tiles.size(); ++t) {
       const GemmTile& tl = tiles[t];
       if (tl.prob < 0) continue;
       const double n = double(tl.t1 - tl.t0) * ((probs[tl.prob].K + 3) / 4);
       sub += n;
       pad8 += 8.0 * std::ceil(n / 8.0);
     }
-    r.kdepth = kdepth ? kdepth : pad8 > 1.25 * sub ? 16 : 32;
-    r.prefetch = prefetch;
-    max_slots = std::max(max_slots, slots);
-    launches.push_back(r);
-    pending.clear();
+    out.kdepth = L.kdepth ? L.kdepth : pad8 > 1.25 * sub ? 16 : 32;
+    out.slots = slots;
+    return out;
+  }
+  void finalize() {
+    const size_t n0 = built, n = launches.size();
+    if (n == n0) return;
+    std::vector<Built> out(n - n0);
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+      for (size_t i; (i = next.fetch_add(1)) < out.size();) out[i] = build(deferred[i]);
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < std::min<size_t>(nth, out.size()); ++t) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    for (size_t i = 0; i < out.size(); ++i) {
+      Range& r = launches[n0 + i];
+      const Deferred& L = deferred[i];
+      r.t0 = int(tiles.size());
+      r.r0 = int(reds.size());
+      tiles.insert(tiles.end(), out[i].tiles.begin(), out[i].tiles.end());
+      reds.insert(reds.end(), out[i].reds.begin(), out[i].reds.end());
+      r.nt = int(tiles.size()) - r.t0;
+      r.nr = int(reds.size()) - r.r0;
+      for (int sh = 0; sh < 4; ++sh) r.shape[sh] = out[i].shape[sh];
+      r.kdepth = out[i].kdepth;
+      r.prefetch = L.prefetch;
+      max_slots = std::max(max_slots, out[i].slots);
+    }
+    deferred.clear();
+    built = n;
   }
 };
 
@@ -398,6 +475,7 @@ int upload(Ctx& c, DevState& d, const std::vector<T>& v, void** p, hipStream_t s
 
 int upload_stage(Ctx& c, DevState& d, GemmStage& g, hipStream_t s) {
   int st;
+  g.finalize();
   if ((st = upload(c, d, g.probs, &g.d_probs, s))) return st;
   if ((st = upload(c, d, g.tiles, &g.d_tiles, s))) return st;
   if ((st = upload(c, d, g.reds, &g.d_reds, s))) return st;
@@ -535,6 +613,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
     if ((st = dalloc(c, d, &d.SCR, size_t(J) * no * no * 16))) return st;
   }
 
+  PhaseClock clk;
   // ---------------- polarization (eq. P0, Alg. 3) ----------------
   Mesh mesh{c.n};
   std::vector<double> sumsq_ao(nib, 0.0);  // sum of squared orbital block sizes
@@ -612,6 +691,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   }
   d.p0_mirror.close();
 
+  clk.mark("polarization work lists");
   // ---------------- self-energy (eq. sigma, Alg. 4) ----------------
   // bins of consecutive orbital blocks, at most 16 rows each (a larger block is a bin alone)
   std::vector<std::vector<std::pair<int, int>>> bins_ao(nib);
@@ -752,6 +832,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
     }
   }
 
+  clk.mark("self-energy work lists");
   for (GemmStage* g : gs)
     if ((st = upload_stage(c, d, *g, s))) return st;
   for (RowStage* r : {&d.p0_both, &d.s_right})
@@ -759,6 +840,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   for (auto* l : {&d.p0_mirror, &d.s_pack})
     if ((st = upload(c, d, l->items, &l->d, s))) return st;
   HIPCHECK(hipStreamSynchronize(s));
+  clk.mark("contraction work lists uploaded");
   return GWSYM_OK;
 }
 
@@ -768,6 +850,7 @@ int init_noalloc_scratch(Ctx& c);
 // device_init: tables, workspaces and the work lists that do not depend on V.
 
 int device_init(Ctx& c, void* stream) {
+  PhaseClock clk;
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevState* dp = new DevState();
   c.dev_state = dp;
@@ -840,7 +923,9 @@ int device_init(Ctx& c, void* stream) {
     c.err = "orbital basis larger than 64 functions";
     return GWSYM_ESHAPE;
   }
+  clk.mark("tables, workspaces");
   if ((st = plan_contractions(c, d, s))) return st;
+  clk.t = std::chrono::steady_clock::now();
 
   // ---------------- exchange (eq. sigma_hf, K term) ----------------
   // K^{k0} = -(1/Nk) sum_{k', Q} V^{k0,k'}(Q) gamma^{k'} V^{k0,k'}(Q)^H with gamma = -G(beta):
@@ -1077,6 +1162,7 @@ int device_init(Ctx& c, void* stream) {
   HIPCHECK(hipMemsetAsync(d.mu_state, 0, 16 * sizeof(double), s));
   HIPCHECK(hipStreamSynchronize(s));
   if ((st = init_noalloc_scratch(c))) return st;
+  clk.mark("exchange, Hartree, Dyson and mu lists");
   c.dev = true;
   return GWSYM_OK;
 }
