@@ -3,7 +3,7 @@
 
 A step is one GW iteration of the hot path: P0 contraction, screened interaction
 (tau -> i Omega, per-block Dyson, back), Sigma contraction, chemical-potential bisection
-and the Dyson equation for G, in the irreducible wedge and isotypic blocks (FP64).  The
+and the Dyson equation for G, in the irreducible wedge and partner-function blocks (FP64).  The
 default workload is the largest single-GPU one: diamond Fd-3m on a 6x6x6 mesh, nao 52,
 naux 300, ntau 128 ("cfg4").  Inputs are seeded synthetic tensors of the workload's shapes,
 resident in HBM before the timed region; each timed iteration is one replay of a HIP graph.
@@ -431,7 +431,7 @@ def main():
            "config": {"workload": f"{wl.name}: {CRYSTAL_NAMES[wl.crystal]}, Gamma-centred {wl.n}^3 k mesh "
                                   f"(Nk={wl.nk}, {blk.ctx.nibz} irreducible), nao={wl.nao}, naux={wl.naux}, "
                                   f"ntau={wl.ntau}, nw={wl.nw}, beta={wl.beta}",
-                      "mode": "irreducible wedge + isotypic blocks, grouped contractions", "precision": "fp64"},
+                      "mode": "irreducible wedge + partner-function blocks, grouped contractions", "precision": "fp64"},
            "contraction_tflops": flops_iter / (contr_ms * 1e-3) / 1e12 if contr_ms > 0 else None,
            "algorithmic_flops_per_iteration": flops_iter,
            "contractions": contr,

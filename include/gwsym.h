@@ -103,6 +103,15 @@ typedef enum {
                                 frequency indices from "freq_f" / "freq_b". */
 } gwsym_grid;
 
+/* Blocks of the symmetry-adapted bases (Sec. 3.4). */
+typedef enum {
+  GWSYM_BLOCKS_ISOTYPIC = 0,  /* one block per irrep of the little group (simultaneous eigenspaces
+                                 of the Dirac characters, Alg. 1): size multiplicity x dimension */
+  GWSYM_BLOCKS_PARTNER = 1    /* each isotypic block of an irrep of dimension d further split into
+                                 d partner-function blocks of the multiplicity's size: operators
+                                 that commute with the group act as X (x) I_d there */
+} gwsym_blocks;
+
 typedef struct {
   double beta;        /* inverse temperature (1/Ha) */
   int ntau;           /* GWSYM_GRID_CHEBYSHEV: tau points on [0, beta], >= 3 */
@@ -118,6 +127,7 @@ typedef struct {
   int grid;           /* gwsym_grid */
   double ir_wmax;     /* GWSYM_GRID_IR: real-frequency cutoff omega_max (Ha) of the basis */
   double ir_eps;      /* GWSYM_GRID_IR: singular values kept above ir_eps times the largest */
+  int blocks;         /* gwsym_blocks */
 } gwsym_params;
 
 typedef struct {

@@ -191,11 +191,14 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
       for (int rt = wave / nct; rt < nrt; rt += rstep) {   // uniform
         const V2* arow = rows + min(16 * rt + li, nr - 1) * ld;
         A4 cr = A4{0, 0, 0, 0}, ci = cr, dr = cr, di = cr;
+        // each step's LDS read is issued one step ahead (addresses clamped into the row)
+        V2 an = arow[min(k0 + kq, n - 1)];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
           if (ks < nks) {   // uniform
             const int k = k0 + 4 * ks + kq;
-            V2 a = arow[min(k, n - 1)];
+            V2 a = an;
+            if (ks + 1 < KS) an = arow[min(k + 4, n - 1)];
             if (k >= n) a = V2{0, 0};
             cmma4<V2>(a, gf[ks], cr, ci);
             if (dual) cmma4<V2>(a, gf2[ks], dr, di);
@@ -356,11 +359,14 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
       const int r = min(16 * rt + li, w - 1), s = r / n, a = r - s * n;
       const V2* arow = X + a * ld + s * n;
       A4 cr = A4{0, 0, 0, 0}, ci = cr, cx = cr;
+      // each step's LDS read is issued one step ahead (addresses clamped into the row)
+      V2 xn = arow[min(k0r + kq, n - 1)];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         if (ks < nksr) {
           const int k = k0r + 4 * ks + kq;
-          V2 x = arow[min(k, n - 1)];
+          V2 x = xn;
+          if (ks + 1 < KS) xn = arow[min(k + 4, n - 1)];
           if (k >= n) x = V2{0, 0};
           cmma<V2>(x, x.x + x.y, gr[ks], gr[ks].x + gr[ks].y, cr, ci, cx);
         }
@@ -388,11 +394,13 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
       if (!act || ct >= nrt) break;   // column tiles of the group: same count as row tiles above
       const int jc = min(16 * ct + li, w - 1);
       A4 cr = A4{0, 0, 0, 0}, ci = cr, cx = cr;
+      V2 yn = Y[min(k0l + kq, n - 1) * ld + jc];   // one step ahead, as above
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         if (ks < nksl) {
           const int k = k0l + 4 * ks + kq;
-          V2 y = Y[min(k, n - 1) * ld + jc];
+          V2 y = yn;
+          if (ks + 1 < KS) yn = Y[min(k + 4, n - 1) * ld + jc];
           if (k >= n) y = V2{0, 0};
           cmma<V2>(gl[ks], gl[ks].x + gl[ks].y, y, y.x + y.y, cr, ci, cx);
         }

@@ -33,6 +33,7 @@ int check_params(const gwsym_params* p, std::string& err) {
   if (p->tau_chunk < 0) return err = "tau_chunk must be >= 0", GWSYM_EINVAL;
   if (!(p->spin > 0)) return err = "spin factor must be positive", GWSYM_EINVAL;
   if (p->sched != GWSYM_SCHED_GROUPED && p->sched != GWSYM_SCHED_UNBATCHED) return err = "unknown schedule", GWSYM_EINVAL;
+  if (p->blocks != GWSYM_BLOCKS_ISOTYPIC && p->blocks != GWSYM_BLOCKS_PARTNER) return err = "unknown block kind", GWSYM_EINVAL;
   return GWSYM_OK;
 }
 

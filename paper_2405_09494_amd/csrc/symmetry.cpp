@@ -114,6 +114,83 @@ CMat orbital_rep(const Ctx& c, bool aux, int a, int k) {
 
 namespace {
 
+// Partner functions (Sec. 3.4).  On the isotypic block of an irrep of dimension d and
+// multiplicity m the little group acts as I_m (x) D(alpha), so a generic Hermitian element of
+// its span, A + A^H with A = sum_alpha w_alpha D(alpha), acts as I_m (x) h with h a d x d
+// Hermitian matrix of d distinct eigenvalues.  Its eigenspaces are d subspaces of dimension m
+// (one partner index each), and every operator that commutes with the little group, being
+// X (x) I_d on the block, maps each of them into itself: the block splits into d blocks of size
+// m.  A block whose eigenvalues do not fall into equal clusters is left whole.  Check: the
+// group average of a fixed generic matrix is block diagonal in the split basis.
+template <class Rnd>
+bool partner_split(Ctx& c, const std::vector<CMat>& Dk, Rnd& rnd, CMat& U, Blocks& B) {
+  const int nb = U.rows, h = int(Dk.size());
+  CMat A(nb, nb);
+  for (int i = 0; i < h; ++i) {
+    const cplx w(rnd() - 1.0, rnd() - 1.0);
+    for (size_t e = 0; e < A.a.size(); ++e) A.a[e] += w * Dk[i].a[e];
+  }
+  CMat H2(nb, nb);
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < nb; ++j) H2(i, j) = A(i, j) + std::conj(A(j, i));
+  const CMat HB = matmul(adjoint(U), matmul(H2, U));
+  Blocks out;
+  CMat Un = U;
+  for (size_t r = 0; r < B.size.size(); ++r) {
+    const int s = B.size[r], o = B.off[r];
+    CMat Hs(s, s);
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) Hs(i, j) = HB(o + i, o + j);
+    std::vector<double> ev;
+    CMat Vs;
+    if (!herm_eig(Hs, ev, Vs)) return c.fail("Jacobi eigen-decomposition did not converge");
+    double emax = 1.0;
+    for (double x : ev) emax = std::max(emax, std::fabs(x));
+    std::vector<int> cl{1};
+    for (int j = 1; j < s; ++j) {
+      if (ev[j] - ev[j - 1] > 1e-7 * emax) cl.push_back(1);
+      else ++cl.back();
+    }
+    const bool equal = std::all_of(cl.begin(), cl.end(), [&](int x) { return x == cl[0]; });
+    if (cl.size() < 2 || !equal) {
+      out.size.push_back(s);
+      out.off.push_back(o);
+      continue;
+    }
+    // U_r <- U_r V, the partner subspaces one after another
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < s; ++j) {
+        cplx x = 0;
+        for (int q = 0; q < s; ++q) x += U(i, o + q) * Vs(q, j);
+        Un(i, o + j) = x;
+      }
+    for (size_t p = 0; p < cl.size(); ++p) {
+      out.size.push_back(cl[0]);
+      out.off.push_back(o + int(p) * cl[0]);
+    }
+  }
+  // group average of a fixed generic matrix: commutes with the little group
+  CMat R(nb, nb), X(nb, nb);
+  for (auto& x : R.a) x = cplx(rnd() - 1.0, rnd() - 1.0);
+  for (int i = 0; i < h; ++i) {
+    const CMat t = matmul(matmul(Dk[i], R), adjoint(Dk[i]));
+    for (size_t e = 0; e < X.a.size(); ++e) X.a[e] += t.a[e];
+  }
+  const CMat XB = matmul(adjoint(Un), matmul(X, Un));
+  std::vector<int> blk_of(nb);
+  for (size_t r = 0; r < out.size.size(); ++r)
+    for (int j = 0; j < out.size[r]; ++j) blk_of[out.off[r] + j] = int(r);
+  double xmax = 0;
+  for (const auto& x : XB.a) xmax = std::max(xmax, std::abs(x));
+  for (int p = 0; p < nb; ++p)
+    for (int q = 0; q < nb; ++q)
+      if (blk_of[p] != blk_of[q] && std::abs(XB(p, q)) > 1e-9 * xmax)
+        return c.fail("partner-function blocks do not block-diagonalise a symmetric operator");
+  U = Un;
+  B = out;
+  return true;
+}
+
 // Simultaneous eigenbasis of the Dirac characters of the little co-group of mesh point k0.
 bool block_basis(Ctx& c, bool aux, int k0, CMat& U, Blocks& B) {
   const int nb = aux ? c.naux : c.nao;
@@ -276,6 +353,7 @@ bool block_basis(Ctx& c, bool aux, int k0, CMat& U, Blocks& B) {
         if (blk_of[p] != blk_of[q] && std::abs(Db(p, q)) > 1e-9)
           return c.fail("Dirac-character basis does not block-diagonalise the little group");
   }
+  if (c.prm.blocks == GWSYM_BLOCKS_PARTNER) return partner_split(c, Dk, rnd, U, B);
   return true;
 }
 

@@ -22,6 +22,7 @@ MODE_FULL, MODE_ROTATE, MODE_BLOCK = 0, 1, 2
 FP64, FP32, BF16X6, BF16X3 = 0, 1, 2, 3
 SCHED_GROUPED, SCHED_UNBATCHED = 0, 1
 GRID_CHEBYSHEV, GRID_IR = 0, 1
+BLOCKS_ISOTYPIC, BLOCKS_PARTNER = 0, 1
 KIND_F, KIND_G, KIND_P = 0, 1, 2
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ESINGULAR", -6: "ENOCONV",
@@ -31,7 +32,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ES
 class Params(C.Structure):
     _fields_ = [("beta", C.c_double), ("ntau", C.c_int), ("nw", C.c_int), ("spin", C.c_double),
                 ("mode", C.c_int), ("precision", C.c_int), ("half_tau", C.c_int), ("tau_chunk", C.c_int),
-                ("sched", C.c_int), ("grid", C.c_int), ("ir_wmax", C.c_double), ("ir_eps", C.c_double)]
+                ("sched", C.c_int), ("grid", C.c_int), ("ir_wmax", C.c_double), ("ir_eps", C.c_double),
+                ("blocks", C.c_int)]
 
 
 class Crystal(C.Structure):
@@ -131,12 +133,13 @@ class Context:
     """One symmetry-adapted GW problem: crystal, mesh, bases, grids, device state."""
 
     def __init__(self, beta, ntau, nw, spin=2.0, mode=MODE_BLOCK, precision=FP64, half_tau=True, tau_chunk=0,
-                 sched=SCHED_GROUPED, ir=None):
+                 sched=SCHED_GROUPED, ir=None, blocks=BLOCKS_PARTNER):
         """ir: None for the Chebyshev grid of ntau points and nw frequencies, or (wmax, eps) for
-        the sparse-sampling IR grid (ntau and nw are then chosen by the library)."""
+        the sparse-sampling IR grid (ntau and nw are then chosen by the library).  blocks:
+        BLOCKS_PARTNER (partner-function blocks) or BLOCKS_ISOTYPIC (one block per irrep)."""
         grid, wmax, eps = (GRID_IR, float(ir[0]), float(ir[1])) if ir else (GRID_CHEBYSHEV, 0.0, 0.0)
         self.params = Params(beta, ntau, nw, spin, mode, precision, int(half_tau), tau_chunk, sched, grid, wmax,
-                             eps)
+                             eps, blocks)
         h = _vp()
         self._check(lib.gwsym_create(C.byref(self.params), C.byref(h)), None)
         self.h = h
@@ -285,7 +288,8 @@ class Context:
         p = self.params
         h.update(repr((p.beta, p.ntau, p.nw, p.mode, p.precision, p.half_tau)
                       + ((p.sched,) if p.sched else ())
-                      + ((p.grid, p.ir_wmax, p.ir_eps) if p.grid else ())).encode())
+                      + ((p.grid, p.ir_wmax, p.ir_eps) if p.grid else ())
+                      + (("isotypic",) if p.blocks == BLOCKS_ISOTYPIC else ())).encode())
         for name in ("dims", "ibz", "rep", "ao_blocks", "aux_blocks"):
             h.update(self.table(name).tobytes())
         return h.hexdigest()

@@ -7,7 +7,7 @@ of that point, its off-block part must vanish (the symmetry the block form relie
 diagonal blocks must match.  (A full-zone readout of P0 would take 40 GB at cfg4.)  The
 Sigma check feeds a seeded symmetric stand-in for P at one tau and its mirror (zero
 elsewhere).  Inputs are drawn once on the GPU and copied to the host for the oracle.  Bars:
-1e-10 relative in FP64, 1e-6 with three-piece bfloat16 contractions (cfg2)."""
+1e-10 relative in FP64, 1e-6 with FP32 or three-piece bfloat16 contractions."""
 import numpy as np
 import pytest
 import torch

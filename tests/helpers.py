@@ -11,14 +11,17 @@ def crystal_arrays(cr):
 
 
 def make_context(wl, mode=None, precision=0, half_tau=True, tau_chunk=0, build=True, identity_only=False, sched=0,
-                 ir=None):
+                 ir=None, blocks=None):
     """identity_only: give the library the trivial group (every block is the whole matrix,
-    every mesh point is irreducible) although the inputs have the crystal's symmetry."""
+    every mesh point is irreducible) although the inputs have the crystal's symmetry.
+    blocks: the library's default (partner-function blocks) unless given."""
     from paper_2405_09494_amd import gwsym
     if mode is None:
         mode = gwsym.MODE_BLOCK
+    if blocks is None:
+        blocks = gwsym.BLOCKS_PARTNER
     nt, nw = (0, 0) if ir else (wl.ntau, wl.nw)
-    ctx = gwsym.Context(wl.beta, nt, nw, wl.spin, mode, precision, half_tau, tau_chunk, sched, ir=ir)
+    ctx = gwsym.Context(wl.beta, nt, nw, wl.spin, mode, precision, half_tau, tau_chunk, sched, ir=ir, blocks=blocks)
     if build:
         cr = crystal(wl.crystal)
         lat, pos, rot, trans = crystal_arrays(cr)

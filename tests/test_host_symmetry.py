@@ -14,6 +14,7 @@ import oracle
 from gwinputs import Inputs, workload, crystal, cubic_point_group, in_td
 from gwinputs.crystals import FCC
 from gwinputs.crystals import Crystal, _ops_from_cart, shells_on_atoms, S, P, D
+from paper_2405_09494_amd import gwsym
 from tests.helpers import make_context, crystal_arrays
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -87,7 +88,7 @@ GAMMA_BLOCKS = {
 
 @pytest.mark.parametrize("name", ["cfg0", "cfg1"])
 def test_gamma_blocks_match_character_theory(name):
-    ctx = make_context(workload(name))
+    ctx = make_context(workload(name), blocks=gwsym.BLOCKS_ISOTYPIC)
     ao, aux = GAMMA_BLOCKS[name]
     assert sorted(ctx.blocks()[0]) == sorted(ao)
     assert sorted(ctx.blocks(aux=True)[0]) == sorted(aux)
@@ -95,18 +96,18 @@ def test_gamma_blocks_match_character_theory(name):
 
 def test_gamma_blocks_rocksalt_and_diamond_small_basis():
     # rocksalt, [s, p, d] on both atoms: A1g 2, T1u 6, Eg 4, T2g 6
-    ctx = make_context(workload("small_rocksalt"))
+    ctx = make_context(workload("small_rocksalt"), blocks=gwsym.BLOCKS_ISOTYPIC)
     assert sorted(ctx.blocks()[0]) == [2, 4, 6, 6]
     # diamond, [s, p, d] on both atoms: s -> A1g + A2u; p -> T1u + T2g; d -> Eg + Eu + T2g + T1u
     # (T_d site irreps induced to O_h): A1g 1, A2u 1, Eg 2, Eu 2, T1u 6, T2g 6
-    ctx = make_context(workload("small_diamond"))
+    ctx = make_context(workload("small_diamond"), blocks=gwsym.BLOCKS_ISOTYPIC)
     assert sorted(ctx.blocks()[0]) == [1, 1, 2, 2, 6, 6]
 
 
 def test_diamond_x_point_blocks_are_even():
     # bands stick together at X of the non-symmorphic group: every isotypic block of the
     # projective little-group representation has even dimension
-    ctx = make_context(workload("small_diamond"))
+    ctx = make_context(workload("small_diamond"), blocks=gwsym.BLOCKS_ISOTYPIC)
     ibz = ctx.table("ibz")
     n = 2
     x_idx = [i for i, k in enumerate(ibz) if (k // (n * n), (k // n) % n, k % n) in [(0, 1, 1), (1, 0, 1), (1, 1, 0)]]
@@ -120,7 +121,7 @@ def test_hexagonal_screw_axis_blocks_are_even():
     # P6_3/mmc: on the zone face k_z = pi/c (the points A and L of the 2x2x2 mesh) the screw axis
     # makes every irrep of the projective little-group representation two-dimensional (bands
     # stick in pairs there), so every isotypic block has even dimension
-    ctx = make_context(workload("small_hbn"))
+    ctx = make_context(workload("small_hbn"), blocks=gwsym.BLOCKS_ISOTYPIC)
     ibz = ctx.table("ibz")
     n = 2
     face = [i for i, k in enumerate(ibz) if k % n == 1]
@@ -128,6 +129,37 @@ def test_hexagonal_screw_axis_blocks_are_even():
     for i in face:
         assert all(b % 2 == 0 for b in ctx.blocks()[i]), ctx.blocks()[i]
         assert all(b % 2 == 0 for b in ctx.blocks(aux=True)[i]), ctx.blocks(aux=True)[i]
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small_diamond", "small_hbn"])
+def test_partner_blocks_follow_the_orthogonality_theorem(name):
+    # Sec. 3.4: on the isotypic block of an irrep of dimension d and multiplicity m the little
+    # group acts as I_m (x) D, so sum over the little group of |tr D_block(alpha)|^2 / h = m^2
+    # (orthogonality of the irreducible characters, projective ones included).  The partner
+    # blocks must cut each isotypic block into s / m pieces of size m.
+    wl = workload(name)
+    iso = make_context(wl, blocks=gwsym.BLOCKS_ISOTYPIC)
+    par = make_context(wl)
+    nk, nop = iso.nk, iso.nop
+    ibz, kmap = iso.table("ibz"), iso.table("kmap").reshape(nop, nk)
+    for aux, n in ((False, iso.nao), (True, iso.naux)):
+        O = iso.table("O_aux" if aux else "O_ao").reshape(nop, nk, n, n)
+        U = iso.table("U_aux" if aux else "U_ao").reshape(nk, n, n)
+        for i, k in enumerate(ibz):
+            little = [a for a in range(nop) if kmap[a, k] == k]
+            expect, o = [], 0
+            for s in iso.blocks(aux)[i]:
+                Ur = U[k][:, o:o + s]
+                chi2 = sum(abs(np.trace(Ur.conj().T @ O[a, k] @ Ur)) ** 2 for a in little) / len(little)
+                m = int(round(np.sqrt(chi2)))
+                assert abs(m * m - chi2) < 1e-8 * max(1.0, chi2) and s % m == 0
+                expect += [m] * (s // m)
+                o += s
+            assert sorted(par.blocks(aux)[i]) == sorted(expect), (name, aux, i)
+            # each partner block lies inside one isotypic block
+            edges = set(np.cumsum([0] + iso.blocks(aux)[i]).tolist())
+            pedges = set(np.cumsum([0] + par.blocks(aux)[i]).tolist())
+            assert edges <= pedges
 
 
 @pytest.mark.parametrize("name", ["small_sc4", "small_rocksalt", "small_diamond", "small_hbn", "small_hbn3"])
