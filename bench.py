@@ -274,9 +274,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg4")
     ap.add_argument("--tau-chunk", type=int, default=0)
-    ap.add_argument("--legs", default="",
+    ap.add_argument("--legs", default=None,
                     help="comma-separated comparison runs: fp32, bf16x6, bf16x3 (reduced-precision contractions), "
-                         "full (no symmetry, all-pair V: cfg0/cfg1 only), unbatched (per-block launches)")
+                         "full (no symmetry, all-pair V: cfg0/cfg1 only), full_sample (the full-matrix form of a "
+                         "6^3 workload timed on a 2^3 mesh of the same crystal and bases, scaled to Nk^2 pairs), "
+                         "unbatched (per-block launches); default: full_sample on the 6^3 workloads, none otherwise")
     ap.add_argument("--graph", type=int, default=1, help="1 (default): replay each iteration from a captured HIP graph; 0: eager launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--autotune", type=int, default=1,
@@ -296,9 +298,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the distributed path is a design "
               "description, not part of this build", file=sys.stderr)
         sys.exit(2)
-    legs = [x for x in args.legs.split(",") if x]
+    legs = [x for x in (args.legs or "").split(",") if x]
     for x in legs:
-        if x not in ("fp32", "bf16x6", "bf16x3", "full", "unbatched"):
+        if x not in ("fp32", "bf16x6", "bf16x3", "full", "full_sample", "unbatched"):
             ap.error(f"unknown leg {x!r}")
 
     import torch
@@ -309,7 +311,9 @@ def main():
     dev = torch.device("cuda:0")
     wl = workload(args.workload)
     if "full" in legs and wl.pairwise:
-        ap.error("the full-matrix leg needs V over every pair, which the 6^3 workloads cannot hold")
+        ap.error("the full-matrix leg needs V over every pair, which the 6^3 workloads cannot hold (full_sample)")
+    if args.legs is None and wl.pairwise:
+        legs = ["full_sample"]
     log(f"[bench] workload {wl.name}: {wl.crystal} n={wl.n} nao={wl.nao} naux={wl.naux} ntau={wl.ntau} beta={wl.beta}")
     t = time.perf_counter()
     inp = Inputs(wl, device=dev)
@@ -456,6 +460,32 @@ def main():
                             "algorithmic_flops_per_iteration": 8.0 * (fp0 + fs), "sigma_rel_err_block_vs_full": err}
         log(f"[bench] full: {s_full:.3f} s/iteration, Sigma block vs full {err:.2e}")
         del full
+    if "full_sample" in legs:
+        # V over every pair of a 6^3 mesh does not fit (606 GB at cfg4): the full-matrix FP64 form
+        # runs on the 2^3 mesh of the same crystal, bases, grid and temperature (64 pairs), and its
+        # contraction time is scaled by the pair count, (Nk / 8)^2, the rest by Nk / 8
+        import dataclasses
+        wls = dataclasses.replace(wl, name=wl.name + "_2x2x2", n=2, pairwise=False)
+        inp_s = Inputs(wls, device=dev)
+        fpath = Path(make_ctx(wls, gwsym.MODE_FULL, tau_chunk=args.tau_chunk), inp_s.fock(),
+                     inp_s.three_index_full(), torch, dev)
+        s_sample = time_steps(fpath, 1, 1, torch)
+        prof_f = profile_step(fpath, torch)
+        cls_c = {c for v in CONTRACTIONS.values() for c in v}
+        c_ms = sum(v[0] for k, v in prof_f.items() if k in cls_c)
+        r_ms = sum(v[0] for k, v in prof_f.items() if k not in cls_c)
+        fk = wl.nk / wls.nk
+        s_est = (c_ms * fk * fk + r_ms * fk) / 1e3
+        out["full_fp64_sample"] = {
+            "s_per_iteration_extrapolated": s_est, "speedup_block_vs_full_extrapolated": s_est / s_blk,
+            "sample": f"full-matrix FP64 iteration on the 2x2x2 mesh ({wls.nk ** 2} pairs) of the same crystal, "
+                      f"bases, tau grid and beta: {s_sample:.3f} s measured, contractions {c_ms:.0f} ms scaled by "
+                      f"(Nk/8)^2 = {fk * fk:.0f}, the rest {r_ms:.0f} ms by Nk/8 = {fk:.0f}",
+            "profile_ms": {k: v[0] for k, v in prof_f.items()}}
+        log(f"[bench] full-matrix form, 2x2x2 sample {s_sample:.3f} s -> {s_est:.0f} s/iteration at Nk = {wl.nk} "
+            f"(block form {s_est / s_blk:.0f}x faster)")
+        del fpath, inp_s
+        torch.cuda.empty_cache()
     if "unbatched" in legs:
         ub = Path(make_ctx(wl, gwsym.MODE_BLOCK, tau_chunk=args.tau_chunk, sched=gwsym.SCHED_UNBATCHED), F_all,
                   V_src, torch, dev)

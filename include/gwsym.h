@@ -184,6 +184,8 @@ int64_t gwsym_table_size(const gwsym_ctx* ctx, const char* name);
  *   "kmap"        int64[nop*nk]: index of alpha k
  *   "ao_blocks"   int64[nibz*(1+nao)]: per i: count, then sizes
  *   "aux_blocks"  int64[nibz*(1+naux)]
+ *   "ao_lead", "aux_lead" int64[nibz*n]: per i and block r, the block whose values block r
+ *                 repeats (aligned partner blocks), r itself if none; -1 past the last block
  *   "g_off","p_off","f_off"  int64[nibz+1]: packed offsets (complex elements)
  *   "U_ao"        complex[nk][nao][nao]: U^k for every mesh point (columns = block basis)
  *   "U_aux"       complex[nk][naux][naux]

@@ -69,6 +69,14 @@ bool table(const Ctx& c, const std::string& name, std::vector<int64_t>& iv, std:
       iv[size_t(i) * (1 + nb)] = int64_t(B.size.size());
       for (size_t r = 0; r < B.size.size(); ++r) iv[size_t(i) * (1 + nb) + 1 + r] = B.size[r];
     }
+  } else if (name == "ao_lead" || name == "aux_lead") {
+    const bool aux = name == "aux_lead";
+    const int nb = aux ? c.naux : c.nao;
+    iv.assign(size_t(c.nibz) * nb, -1);
+    for (int i = 0; i < c.nibz; ++i) {
+      const Blocks& B = aux ? c.baux[i] : c.bao[i];
+      for (size_t r = 0; r < B.lead.size(); ++r) iv[size_t(i) * nb + r] = B.lead[r];
+    }
   } else if (name == "g_off") {
     iv = c.g_off;
   } else if (name == "p_off") {

@@ -46,6 +46,9 @@ struct Blocks {
   std::vector<int> off;     // first basis function of block r (in the block basis)
   std::vector<i64> poff;    // offset of block r in the packed layout
   i64 packed = 0;           // sum n_r^2
+  // lead[r]: the block whose values block r repeats for every operator that commutes with the
+  // group (aligned partner blocks of one irrep), r itself when it has none
+  std::vector<int> lead;
 };
 
 // One problem of the grouped batch-reduce complex GEMM:

@@ -44,7 +44,8 @@ struct RowSegList {
 };
 
 struct CopySeg {
-  int inbuf, outbuf, n, pad_;
+  int inbuf, outbuf, n;
+  int flags;   // k_herm_fill: 1 = the source block is only read (a copy of a leading partner block)
   int64_t in_off, out_off, len;
 };
 

@@ -848,16 +848,18 @@ __global__ __launch_bounds__(256) void k_copy(const CopySeg* __restrict__ segs, 
 }
 
 // Hermitian fill of n x n blocks whose lower triangle holds the result: X[a][b] = conj(X[b][a])
-// for a < b, in place; with out_off >= 0 the whole block is also copied there (the tau mirror).
+// for a < b, in place; with out_off >= 0 the whole block is also copied there (the tau mirror,
+// or an aligned partner block).  flags & 1: the source is only read (its own segment fills it).
 __global__ __launch_bounds__(256) void k_herm_fill(const CopySeg* __restrict__ segs, Bases bases) {
   const CopySeg sg = segs[blockIdx.x];
   double2* X = reinterpret_cast<double2*>(bases.p[sg.inbuf]) + sg.in_off;
   double2* M = sg.out_off >= 0 ? reinterpret_cast<double2*>(bases.p[sg.outbuf]) + sg.out_off : nullptr;
   const int n = sg.n;
+  const bool fill = !(sg.flags & 1);
   for (int e = threadIdx.x; e < n * n; e += 256) {
     const int a = e / n, b = e - a * n;
     const double2 v = a >= b ? X[e] : cconj(X[b * n + a]);
-    if (a < b) X[e] = v;
+    if (a < b && fill) X[e] = v;
     if (M) M[e] = v;
   }
 }

@@ -660,9 +660,11 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
         // tiles on or below the diagonal are computed
         d.p0_gemm.add(p, double(jc) * m * (m + 1) / 2 * no * nkc * no, true);
       };
+      // aligned partner blocks repeat their leading block: only leading blocks are computed
       if (!ub) {
         for (int k = 0; k < nk; ++k) segs(k);
-        for (size_t sg = 0; sg < BA.size.size(); ++sg) gemm(sg, 0, nk, 0);
+        for (size_t sg = 0; sg < BA.size.size(); ++sg)
+          if (BA.lead[sg] == int(sg)) gemm(sg, 0, nk, 0);
         d.p0_both.close();
         d.p0_gemm.close();
         const int l = int(d.p0_gemm.launches.size());
@@ -673,6 +675,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
           d.p0_both.close();
           const int g0 = int(d.p0_gemm.launches.size());
           for (size_t sg = 0; sg < BA.size.size(); ++sg) {
+            if (BA.lead[sg] != int(sg)) continue;
             gemm(sg, k, 1, k > 0);
             d.p0_gemm.close();
           }
@@ -680,13 +683,21 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
         }
       }
     }
-    // upper triangles from the lower ones; with half tau also the mirrored tau
+    // upper triangles from the lower ones; with half tau also the mirrored tau; a partner
+    // block that repeats a leading one is written from the leader's lower triangle
     for (int j = 0; j < nthalf; ++j)
       for (size_t sg = 0; sg < BA.size.size(); ++sg) {
+        const int l = BA.lead[sg];
         const i64 o = c.p_off[i] + i64(j) * BA.packed + BA.poff[sg];
+        const i64 ol = c.p_off[i] + i64(j) * BA.packed + BA.poff[l];
         const bool mir = c.prm.half_tau && nt - 1 - j != j;
-        d.p0_mirror.items.push_back({B_OUT, B_OUT, BA.size[sg], 0, o,
-                                     mir ? c.p_off[i] + i64(nt - 1 - j) * BA.packed + BA.poff[sg] : -1, 0});
+        const i64 om = c.p_off[i] + i64(nt - 1 - j) * BA.packed + BA.poff[sg];
+        if (l == int(sg)) {
+          d.p0_mirror.items.push_back({B_OUT, B_OUT, BA.size[sg], 0, o, mir ? om : -1, 0});
+        } else {
+          d.p0_mirror.items.push_back({B_OUT, B_OUT, BA.size[sg], 1, ol, o, 0});
+          if (mir) d.p0_mirror.items.push_back({B_OUT, B_OUT, BA.size[sg], 1, ol, om, 0});
+        }
       }
   }
   d.p0_mirror.close();
@@ -694,11 +705,18 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   clk.mark("polarization work lists");
   // ---------------- self-energy (eq. sigma, Alg. 4) ----------------
   // bins of consecutive orbital blocks, at most 16 rows each (a larger block is a bin alone)
+  // of the leading blocks only (a block repeating an aligned partner is gathered from it)
   std::vector<std::vector<std::pair<int, int>>> bins_ao(nib);
   for (int i = 0; i < nib; ++i) {
     const Blocks& B = c.bao[i];
     int r0 = 0, nb = 0;
     for (size_t r = 0; r < B.size.size(); ++r) {
+      if (B.lead[r] != int(r)) {
+        if (nb > 0) bins_ao[i].push_back({r0, nb});
+        r0 = B.off[r] + B.size[r];
+        nb = 0;
+        continue;
+      }
       if (nb > 0 && nb + B.size[r] > 16) {
         bins_ao[i].push_back({r0, nb});
         r0 += nb;
@@ -822,7 +840,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
       }
       for (int sl = 0; sl < nslot; ++sl)
         for (size_t rb = 0; rb < BO.size.size(); ++rb) {
-          const int n = BO.size[rb], off = BO.off[rb];
+          const int n = BO.size[rb], off = BO.off[size_t(BO.lead[rb])];
           d.s_pack.items.push_back({B_SCR, B_OUT, n, 0, i64(sl) * no * no + i64(off) * no + off,
                                     c.g_off[i] + i64(slot_tau[sl]) * BO.packed + BO.poff[rb], no});
         }

@@ -155,6 +155,7 @@ bool partner_split(Ctx& c, const std::vector<CMat>& Dk, Rnd& rnd, CMat& U, Block
     if (cl.size() < 2 || !equal) {
       out.size.push_back(s);
       out.off.push_back(o);
+      out.lead.push_back(int(out.size.size()) - 1);
       continue;
     }
     // U_r <- U_r V, the partner subspaces one after another
@@ -164,10 +165,51 @@ bool partner_split(Ctx& c, const std::vector<CMat>& Dk, Rnd& rnd, CMat& U, Block
         for (int q = 0; q < s; ++q) x += U(i, o + q) * Vs(q, j);
         Un(i, o + j) = x;
       }
-    for (size_t p = 0; p < cl.size(); ++p) {
-      out.size.push_back(cl[0]);
-      out.off.push_back(o + int(p) * cl[0]);
+    // align partners p > 1 to partner 1: in coordinates where the block is (multiplicity) x
+    // (partner), E_p = A_p R_p with R_p unitary, and for a generic element B of the group's
+    // span E_p^H B E_1 = c_p R_p^H R_1 with a scalar c_p; E_p <- E_p F_p / |c_p| makes every
+    // commuting operator's partner blocks equal
+    const int m = cl[0], d = int(cl.size()), lead = int(out.size.size());
+    for (int p = 0; p < d; ++p) {
+      out.size.push_back(m);
+      out.off.push_back(o + p * m);
+      out.lead.push_back(lead);
     }
+    CMat Bg(nb, nb);
+    for (int i = 0; i < h; ++i) {
+      const cplx w(rnd() - 1.0, rnd() - 1.0);
+      for (size_t e = 0; e < Bg.a.size(); ++e) Bg.a[e] += w * Dk[i].a[e];
+    }
+    CMat E1(nb, m);
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < m; ++j) E1(i, j) = Un(i, o + j);
+    const CMat BE1 = matmul(Bg, E1);
+    bool aligned = true;
+    std::vector<CMat> Ep(d);
+    for (int p = 1; p < d && aligned; ++p) {
+      CMat E(nb, m);
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < m; ++j) E(i, j) = Un(i, o + p * m + j);
+      const CMat F = matmul(adjoint(E), BE1);
+      const CMat FF = matmul(adjoint(F), F);
+      double c2 = 0, dev = 0;
+      for (int j = 0; j < m; ++j) c2 += FF(j, j).real() / m;
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) dev = std::max(dev, std::abs(FF(i, j) - (i == j ? c2 : 0.0)));
+      if (!(c2 > 1e-12) || dev > 1e-8 * c2) {
+        aligned = false;
+        break;
+      }
+      Ep[p] = matmul(E, F);
+      for (auto& x : Ep[p].a) x /= std::sqrt(c2);
+    }
+    if (!aligned) {
+      for (int p = 0; p < d; ++p) out.lead[lead + p] = lead + p;
+      continue;
+    }
+    for (int p = 1; p < d; ++p)
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < m; ++j) Un(i, o + p * m + j) = Ep[p](i, j);
   }
   // group average of a fixed generic matrix: commutes with the little group
   CMat R(nb, nb), X(nb, nb);
@@ -186,6 +228,15 @@ bool partner_split(Ctx& c, const std::vector<CMat>& Dk, Rnd& rnd, CMat& U, Block
     for (int q = 0; q < nb; ++q)
       if (blk_of[p] != blk_of[q] && std::abs(XB(p, q)) > 1e-9 * xmax)
         return c.fail("partner-function blocks do not block-diagonalise a symmetric operator");
+  // and its aligned partner blocks are equal
+  for (size_t r = 0; r < out.size.size(); ++r) {
+    const int l = out.lead[r];
+    if (l == int(r)) continue;
+    for (int i = 0; i < out.size[r]; ++i)
+      for (int j = 0; j < out.size[r]; ++j)
+        if (std::abs(XB(out.off[r] + i, out.off[r] + j) - XB(out.off[l] + i, out.off[l] + j)) > 1e-9 * xmax)
+          return c.fail("aligned partner blocks of a symmetric operator differ");
+  }
   U = Un;
   B = out;
   return true;
@@ -544,6 +595,10 @@ int build_symmetry(Ctx& c, const gwsym_crystal* cr) {
     for (Blocks* B : {&c.bao[i], &c.baux[i]}) {
       B->poff.clear();
       B->packed = 0;
+      if (B->lead.size() != B->size.size()) {   // no aligned partners: every block leads itself
+        B->lead.resize(B->size.size());
+        std::iota(B->lead.begin(), B->lead.end(), 0);
+      }
       for (int s : B->size) {
         B->poff.push_back(B->packed);
         B->packed += i64(s) * s;

@@ -207,6 +207,12 @@ class Context:
         t = self.table("aux_blocks" if aux else "ao_blocks").reshape(self.nibz, 1 + n)
         return [list(map(int, row[1:1 + row[0]])) for row in t]
 
+    def leads(self, aux=False):
+        """per irreducible point and block: the block whose values it repeats (itself if none)"""
+        n = self.naux if aux else self.nao
+        t = self.table("aux_lead" if aux else "ao_lead").reshape(self.nibz, n)
+        return [list(map(int, row[row >= 0])) for row in t]
+
     # sizes of the packed layouts (complex elements)
     @property
     def g_size(self):

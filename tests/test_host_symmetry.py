@@ -182,13 +182,27 @@ def test_block_basis_diagonalises_symmetric_inputs(name):
             o += s
         return np.abs(M[mask]).max() if mask.any() else 0.0
 
+    lo, lx = ctx.leads(), ctx.leads(aux=True)
+
+    def copies(M, sizes, lead):
+        # largest difference between a block and the block it repeats (aligned partners)
+        offs = np.cumsum([0] + list(sizes))
+        d = 0.0
+        for r, l in enumerate(lead):
+            if l != r:
+                d = max(d, np.abs(M[offs[r]:offs[r + 1], offs[r]:offs[r + 1]]
+                                  - M[offs[l]:offs[l + 1], offs[l]:offs[l + 1]]).max())
+        return d
+
     for k in range(ctx.nk):
         assert np.abs(U[k].conj().T @ U[k] - np.eye(ctx.nao)).max() < 1e-12
         Fb = U[k].conj().T @ F[k] @ U[k]
         assert offdiag(Fb, bo[rep[k]]) < 1e-12 * np.abs(F).max()
+        assert copies(Fb, bo[rep[k]], lo[rep[k]]) < 1e-12 * np.abs(F).max()
         for j in range(2):
             Xb = Ux[k].conj().T @ X[k, j] @ Ux[k]
             assert offdiag(Xb, bx[rep[k]]) < 1e-12 * np.abs(X).max()
+            assert copies(Xb, bx[rep[k]], lx[rep[k]]) < 1e-12 * np.abs(X).max()
     # star consistency: the block form is the same at every point of a star
     ibz = ctx.table("ibz")
     for k in range(ctx.nk):
