@@ -124,9 +124,16 @@ class Path:
         ctx.g0(self.F, 0.0, self.G, self.nfree)
         torch.cuda.synchronize()
         self.n_target = float(self.nfree.item())
+        self.G0 = self.G.clone()
 
-    def step(self, eager=False):
+    def step(self, eager=False, restart=True):
+        """One GW iteration.  restart: from G0 (every timed step is the same iteration: repeated
+        undamped iterations on the synthetic inputs do not settle, and at the diamond 6^3
+        workload the chemical potential leaves its bracket within 25 of them); the cost of an
+        iteration does not depend on the values.  restart=False continues from the current G."""
         c = self.ctx
+        if restart:
+            self.G.copy_(self.G0)
         if self.graph is not None and not eager:
             # the whole iteration replayed from one captured HIP graph on a side stream
             self.torch.cuda.current_stream().synchronize()
@@ -158,7 +165,7 @@ def iteration_errors(ref, red, n, torch):
     hist = []
     for _ in range(n):
         for pth in (ref, red):
-            pth.step(eager=True)
+            pth.step(eager=True, restart=False)
         torch.cuda.synchronize()
         a, b = red.full(2, red.P0), ref.full(2, ref.P0)
         e0 = float((a - b).abs().max() / b.abs().max())
@@ -172,12 +179,20 @@ def iteration_errors(ref, red, n, torch):
 
 
 def time_steps(path, steps, warmup, torch):
-    for _ in range(warmup):
+    """Seconds per step over `steps` timed steps after `warmup` untimed ones.  Each step ends
+    with its stream synchronised, so a progress line per finished step (stderr, microseconds)
+    keeps a long run visibly alive without adding device work."""
+    for w in range(warmup):
         path.step()
+        torch.cuda.synchronize()
+        log(f"[bench] warm-up step {w + 1} of {warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         path.step()
+        if path.graph is None:
+            torch.cuda.synchronize()
+        log(f"[bench] step {k + 1} of {steps} done ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / max(steps, 1)
 
@@ -207,8 +222,9 @@ def cpu_baseline(wl, F_all, vpairs, ibz_rep_q, torch):
     one iteration at the workload's shapes and scaled to a full iteration (Nk x ntau outputs of
     each contraction, Nk screened-interaction momenta, 65 Dyson solves for the bisection):
     with every BLAS thread, up to 32 P0 outputs (one q, every k) and 32 Sigma outputs (one k,
-    every q) within about 6 s each, the screened interaction of 4 momenta and one Dyson solve
-    over every k; and with one BLAS thread, one output of each contraction."""
+    every q) within about 6 s each, the screened interaction of 4 momenta (1 at the 6^3 sizes)
+    and one Dyson solve over every k (8 of the k at the 6^3 sizes, scaled); and with one BLAS
+    thread, one output of each contraction where that takes seconds."""
     import oracle
     from gwinputs import add_k, minus_k
     from threadpoolctl import threadpool_info, threadpool_limits
@@ -241,27 +257,36 @@ def cpu_baseline(wl, F_all, vpairs, ibz_rep_q, torch):
         return t_p0, n_p0, (time.perf_counter() - t) / n_s, n_s
 
     t_p0, n_p0, t_s, n_s = contractions(ns, 6.0)
-    nq = min(4, nk)
+    # the screened interaction per momentum and the Dyson solve per k scale linearly: a few of
+    # each at the 6^3 sizes (one momentum takes seconds there, one Dyson solve over all k minutes)
+    nq = 1 if wl.pairwise else min(4, nk)
     X = rng.standard_normal((nq, nt, wl.naux, wl.naux)) * 1e-3
     X = X + X.transpose(0, 1, 3, 2)
     t = time.perf_counter()
     oracle.screened(X.astype(complex), wl.beta, wl.nw)
     t_scr = (time.perf_counter() - t) / nq
-    S0 = np.zeros((nk, nt, wl.nao, wl.nao), complex)
+    nkd = min(8, nk) if wl.pairwise else nk
+    S0 = np.zeros((nkd, nt, wl.nao, wl.nao), complex)
     t = time.perf_counter()
-    oracle.dyson(F, S0, 0.0, wl.beta, wl.nw)
-    t_dys = time.perf_counter() - t
+    oracle.dyson(F[:nkd], S0, 0.0, wl.beta, wl.nw)
+    t_dys = (time.perf_counter() - t) * nk / nkd
     total = (t_p0 + t_s) * nk * nt + t_scr * nk + 65 * t_dys
     sample = (f"measured: {n_p0} P0 outputs (q={q}, all {nk} k) at {t_p0:.3f} s each, {n_s} Sigma outputs (k={k}, "
-              f"all {nk} q) at {t_s:.3f} s each, screened interaction for {nq} momenta at {t_scr:.2f} s each, one "
-              f"Dyson solve over all k {t_dys:.3f} s; scaled to {nk * nt} outputs of each contraction, {nk} "
-              f"momenta and 65 Dyson solves")
-    # one BLAS thread: one output of each contraction (the bulk of the work)
-    with threadpool_limits(limits=1):
-        t1_p0, _, t1_s, _ = contractions(1, 0.0)
-    single = {"value": (t1_p0 + t1_s) * nk * nt, "unit": "s/iteration (contractions only)", "cores": 1,
-              "sample": f"one BLAS thread: one P0 output ({t1_p0:.2f} s) and one Sigma output ({t1_s:.2f} s), "
-                        f"scaled to {nk * nt} outputs of each"}
+              f"all {nk} q) at {t_s:.3f} s each, screened interaction for {nq} momenta at {t_scr:.2f} s each, "
+              f"Dyson solve for {nkd} of the {nk} k (scaled to all k: {t_dys:.2f} s); scaled to {nk * nt} outputs "
+              f"of each contraction, {nk} momenta and 65 Dyson solves over all k")
+    # one BLAS thread: one output of each contraction (the bulk of the work), where that stays
+    # within about 15 s (at the 6^3 sizes one output alone would take a minute or more)
+    if (t_p0 + t_s) * cores <= 15.0:
+        with threadpool_limits(limits=1):
+            t1_p0, _, t1_s, _ = contractions(1, 0.0)
+        single = {"value": (t1_p0 + t1_s) * nk * nt, "unit": "s/iteration (contractions only)", "cores": 1,
+                  "sample": f"one BLAS thread: one P0 output ({t1_p0:.2f} s) and one Sigma output ({t1_s:.2f} s), "
+                            f"scaled to {nk * nt} outputs of each"}
+    else:
+        single = {"value": None, "unit": "s/iteration (contractions only)", "cores": 1,
+                  "sample": f"not measured: one output of each contraction took {t_p0 + t_s:.1f} s on {cores} "
+                            f"threads"}
     return {"value": total, "unit": "s/iteration", "cores": int(cores), "kind": "oracle", "sample": sample,
             "extrapolated": True, "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
             "single_thread": single}
@@ -278,7 +303,7 @@ def main():
                     help="comma-separated comparison runs: fp32, bf16x6, bf16x3 (reduced-precision contractions), "
                          "full (no symmetry, all-pair V: cfg0/cfg1 only), full_sample (the full-matrix form of a "
                          "6^3 workload timed on a 2^3 mesh of the same crystal and bases, scaled to Nk^2 pairs), "
-                         "unbatched (per-block launches); default: full_sample on the 6^3 workloads, none otherwise")
+                         "unbatched (per-block launches), none; default: full_sample on the 6^3 workloads, none otherwise")
     ap.add_argument("--graph", type=int, default=1, help="1 (default): replay each iteration from a captured HIP graph; 0: eager launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--autotune", type=int, default=1,
@@ -298,7 +323,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the distributed path is a design "
               "description, not part of this build", file=sys.stderr)
         sys.exit(2)
-    legs = [x for x in (args.legs or "").split(",") if x]
+    legs = [x for x in (args.legs or "").split(",") if x and x != "none"]
     for x in legs:
         if x not in ("fp32", "bf16x6", "bf16x3", "full", "full_sample", "unbatched"):
             ap.error(f"unknown leg {x!r}")

@@ -158,13 +158,20 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
   V2* out2 = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + (dual ? sg.out_off2 : sg.out_off);
   R pfx[PF], pfy[PF];   // real and imaginary parts apart: arrays of scalars stay in registers
   auto height = [&](int ch) { return min(64, sg.nrows - 64 * ch); };
+  // physical element offset of logical row r (rows in groups of rw, ld apart, when rw > 0)
+  const int rw = sg.rw;
+  const int64_t gstride = int64_t(sg.ld) * n;
+  auto prow = [&](int r) -> int64_t {
+    if (rw <= 0) return int64_t(r) * n;
+    const int g = r / rw;
+    return g * gstride + int64_t(r - g * rw) * n;
+  };
   auto fetch = [&](int ch) {   // past the chunk's end every lane reloads element 0: no branches
     const int ne = height(ch) * n;
-    const V2* src = in + int64_t(ch) * 64 * n;
 #pragma unroll
     for (int t = 0; t < PF; ++t) {
-      const int e = tid + 512 * t;
-      const V2 v = src[e < ne ? e : 0];
+      const int e = tid + 512 * t, ec = e < ne ? e : 0, r = ec / n;
+      const V2 v = in[prow(64 * ch + r) + (ec - r * n)];
       pfx[t] = v.x;
       pfy[t] = v.y;
     }
@@ -186,7 +193,6 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
   __syncthreads();
   for (int ch = c0; ch < c1; ++ch) {
     const int nr = height(ch), nrt = (nr + 15) / 16;
-    const int64_t obase = int64_t(ch) * 64 * n;
     if (act) {
       for (int rt = wave / nct; rt < nrt; rt += rstep) {   // uniform
         const V2* arow = rows + min(16 * rt + li, nr - 1) * ld;
@@ -208,8 +214,9 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
         for (int j = 0; j < 4; ++j) {
           const int r = 16 * rt + M::row(lane, j);
           if (c < n && r < nr) {
-            out[obase + int64_t(r) * n + c] = V2{R(cr[j]), R(ci[j])};
-            if (dual) out2[obase + int64_t(r) * n + c] = V2{R(dr[j]), R(di[j])};
+            const int64_t o = prow(64 * ch + r) + c;
+            out[o] = V2{R(cr[j]), R(ci[j])};
+            if (dual) out2[o] = V2{R(dr[j]), R(di[j])};
           }
         }
       }
@@ -262,8 +269,9 @@ __global__ __launch_bounds__(512) void k_bd_both(const RowSeg* __restrict__ segs
   using A4 = typename M::A4;
   extern __shared__ double2 lds_both[];
   const RowSeg sg = segs[blockIdx.y];
-  const int ncols = sg.nrows;   // slab width: na matrices of n columns side by side
-  const int nmat = ncols / n, ngrp = (nmat + S - 1) / S;
+  const int wseg = sg.nrows;   // matrices of n columns side by side; row stride ncols
+  const int64_t ncols = sg.ld > 0 ? sg.ld : wseg;
+  const int nmat = wseg / n, ngrp = (nmat + S - 1) / S;
   const int g0 = blockIdx.x * per;
   if (g0 >= ngrp) return;
   const int g1 = min(ngrp, g0 + per);

@@ -36,6 +36,10 @@ struct RowSeg {
   int nrows, blk2;
   int64_t g_off2;
   int64_t out_off2;   // right multiply: >= 0 writes a second product, by the matrix at g_off2
+  // Sub-ranges of a slab (0: the whole slab).  Both-sided multiply: ld = row stride of the
+  // slab when nrows (the width taken) is less.  Right multiply: logical row r is the physical
+  // row (r / rw) ld + r % rw (groups of rw rows ld apart).
+  int ld, rw;
 };
 
 struct RowSegList {

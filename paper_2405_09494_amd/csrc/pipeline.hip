@@ -614,6 +614,17 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   }
 
   PhaseClock clk;
+  // maximal runs (first index, length) of consecutive leading blocks: the functions whose
+  // values are computed (the others repeat an aligned partner block and are copied)
+  auto lead_runs = [](const Blocks& B) {
+    std::vector<std::pair<int, int>> runs;
+    for (size_t r = 0; r < B.size.size(); ++r) {
+      if (B.lead[r] != int(r)) continue;
+      if (!runs.empty() && runs.back().first + runs.back().second == B.off[r]) runs.back().second += B.size[r];
+      else runs.push_back({B.off[r], B.size[r]});
+    }
+    return runs;
+  };
   // ---------------- polarization (eq. P0, Alg. 3) ----------------
   Mesh mesh{c.n};
   std::vector<double> sumsq_ao(nib, 0.0);  // sum of squared orbital block sizes
@@ -630,17 +641,23 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
     for (int k = 0; k < nk; ++k) kq[k] = mesh.add(k, q0);
     for (int j0 = 0; j0 < nthalf; j0 += J) {
       const int j1 = std::min(nthalf, j0 + J), jc = j1 - j0;
+      // W is needed only for the auxiliary functions of leading blocks (the GEMM reads no other)
+      const auto qruns = lead_runs(BA);
       auto segs = [&](int k) {
         const int ik = c.rep[k], ikq = c.rep[kq[k]];
         for (int j = j0; j < j1; ++j) {
           const i64 vp = (i64(i) * nk + k) * na * no * no;
           const i64 wo = (i64(j - j0) * nk + k) * na * no * no;
-          RowSeg r{};
-          r.inbuf = B_VP; r.outbuf = B_W2; r.gbuf = B_G;
-          r.blk = d.bt_ao[ik]; r.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed;
-          r.blk2 = d.bt_ao[ikq]; r.g_off2 = c.g_off[ikq] + i64(j) * c.bao[ikq].packed;
-          r.in_off = vp; r.out_off = wo; r.nrows = na * no;
-          d.p0_both.add(r, double(na) * no * (sumsq_ao[ik] + sumsq_ao[ikq]), double(na) * no * no);
+          for (const auto& run : qruns) {
+            RowSeg r{};
+            r.inbuf = B_VP; r.outbuf = B_W2; r.gbuf = B_G;
+            r.blk = d.bt_ao[ik]; r.g_off = c.g_off[ik] + i64(nt - 1 - j) * c.bao[ik].packed;
+            r.blk2 = d.bt_ao[ikq]; r.g_off2 = c.g_off[ikq] + i64(j) * c.bao[ikq].packed;
+            r.in_off = vp + i64(run.first) * no; r.out_off = wo + i64(run.first) * no;
+            r.nrows = run.second * no;
+            r.ld = na * no;
+            d.p0_both.add(r, double(run.second) * no * (sumsq_ao[ik] + sumsq_ao[ikq]), double(run.second) * no * no);
+          }
         }
       };
       // one problem per auxiliary block for all tau of the chunk: the columns are (tau, Q'), so
@@ -741,6 +758,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   for (int i = 0; i < nib; ++i) {
     const int k0 = c.ibz[i];
     const Blocks& BO = c.bao[i];
+    const auto aruns = lead_runs(BO);
     for (size_t u0 = 0; u0 < units.size();) {
       // units of this chunk: at most J tau (workspace slabs) in all
       size_t u1 = u0;
@@ -759,19 +777,24 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
       }
       // Y = P_blk^T Vs with the rows (unit, s') in one problem per (k', auxiliary block): the Vs
       // rows are read once for every tau of the chunk
+      // Y's columns (a, b) only for the orbital functions a of k0's leading blocks: the orbital
+      // GEMM reads no other rows of Z = Y G
       auto gemmA = [&](int kp, bool each) {
         const int q = mesh.sub(k0, kp), iq = c.rep[q];
         const Blocks& BQ = c.baux[iq];
         const i64 vs = (i64(i) * nk + kp) * na * no * no;
         for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
           const int m = BQ.size[sg], off = BQ.off[sg];
-          GemmProblem p = gp(nu * m, no * no, m, 1, 1, B_P, c.p_off[iq] + i64(j0) * BQ.packed + BQ.poff[sg], m, 0, 0,
-                             OP_T, B_VS, vs + i64(off) * no * no, i64(no) * no, 0, 0, OP_N, B_W1,
-                             i64(kp) * na * no * no + i64(off) * no * no, i64(no) * no, 0);
-          p.rdiv = m;
-          p.sArb = BQ.packed;
-          p.sCrb = slab;
-          d.s_gemmA.add(p);
+          for (const auto& run : aruns) {
+            const i64 ca = i64(run.first) * no;
+            GemmProblem p = gp(nu * m, run.second * no, m, 1, 1, B_P, c.p_off[iq] + i64(j0) * BQ.packed + BQ.poff[sg],
+                               m, 0, 0, OP_T, B_VS, vs + i64(off) * no * no + ca, i64(no) * no, 0, 0, OP_N, B_W1,
+                               i64(kp) * na * no * no + i64(off) * no * no + ca, i64(no) * no, 0);
+            p.rdiv = m;
+            p.sArb = BQ.packed;
+            p.sCrb = slab;
+            d.s_gemmA.add(p);
+          }
           if (each) d.s_gemmA.close();
         }
       };
@@ -792,8 +815,18 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
             r.out_off2 = (i64(sl + 1) * nk + kp) * na * no * no;
             r.g_off2 = c.g_off[ik] + i64(slot_tau[sl + 1]) * c.bao[ik].packed;
           }
-          r.nrows = na * no;
-          d.s_right.add(r, double(na) * no * sumsq_ao[ik] * (pair ? 2 : 1), double(na) * no * no * (pair ? 1.5 : 1));
+          // rows (s', a) for the leading runs of a only: groups of the run's width, nao apart
+          for (const auto& run : aruns) {
+            RowSeg rr = r;
+            rr.in_off += i64(run.first) * no;
+            rr.out_off += i64(run.first) * no;
+            if (pair) rr.out_off2 += i64(run.first) * no;
+            rr.rw = run.second;
+            rr.ld = no;
+            rr.nrows = na * run.second;
+            d.s_right.add(rr, double(na) * run.second * sumsq_ao[ik] * (pair ? 2 : 1),
+                          double(na) * run.second * no * (pair ? 1.5 : 1));
+          }
         }
       };
       // only the diagonal blocks of Sigma are kept: consecutive orbital blocks are grouped into
