@@ -525,7 +525,9 @@ def main():
                if k in legs]
     ibz_blk = blk.ctx.table("ibz")
     if wl.pairwise and reduced:
-        del blk    # the 6^3 workloads hold one path at a time
+        # the 6^3 workloads hold one path at a time: free the FP64 path's device state now
+        blk.ctx.close()
+        del blk
         torch.cuda.empty_cache()
         blk = None
     for key, prec in reduced:
@@ -548,6 +550,7 @@ def main():
         out[key + "_contractions"] = entry
         log(f"[bench] {key}: {s_red:.4f} s/iteration; profile " + ", ".join(f"{k} {v[0]:.1f} ms"
                                                                             for k, v in prof_red.items()))
+        red.ctx.close()
         del red
         torch.cuda.empty_cache()
 

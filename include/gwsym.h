@@ -332,7 +332,8 @@ typedef struct {
   int cols[3];        /* output columns per wave tile: 32 or 64 */
   int xcd_order[3];   /* 1: tiles sharing operand rows queued on one XCD in sequence; 2: all
                          tiles of a problem on one XCD, the row tiles of a column chunk
-                         together; 0: plain order */
+                         together; 3: bands of 256 rows of a problem, each on one XCD and
+                         swept column chunk by column chunk; 0: plain order */
   int kdepth[3];      /* split-bfloat16 modes: k values per bfloat16 MFMA, 16 or 32; 0 picks
                          per launch (16 where 32 would pad more than a quarter of the sums) */
   int prefetch[3];    /* FP64 / FP32 modes: K steps of 4 fetched ahead per wave, 2 or 4 */

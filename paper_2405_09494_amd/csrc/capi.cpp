@@ -361,7 +361,7 @@ int gwsym_set_tuning(gwsym_ctx* ctx, const gwsym_tuning* t, void* stream) {
   for (int g = 0; g < 3; ++g) {
     NEED(t->wg_target[g] >= 256 && t->wg_target[g] <= (1 << 20), GWSYM_EINVAL, "wg_target out of [256, 2^20]");
     NEED(t->cols[g] == 32 || t->cols[g] == 64, GWSYM_EINVAL, "cols must be 32 or 64");
-    NEED(t->xcd_order[g] >= 0 && t->xcd_order[g] <= 2, GWSYM_EINVAL, "xcd_order must be 0, 1 or 2");
+    NEED(t->xcd_order[g] >= 0 && t->xcd_order[g] <= 3, GWSYM_EINVAL, "xcd_order must be 0, 1, 2 or 3");
     NEED(t->kdepth[g] == 0 || t->kdepth[g] == 16 || t->kdepth[g] == 32, GWSYM_EINVAL, "kdepth must be 0, 16 or 32");
     NEED(t->prefetch[g] == 2 || t->prefetch[g] == 4, GWSYM_EINVAL, "prefetch must be 2 or 4");
   }

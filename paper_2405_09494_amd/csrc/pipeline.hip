@@ -59,9 +59,18 @@ inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vec
   constexpr int NX = 8;
   const int n = int(tiles.size()) - t0;
   if (n <= NX) return;
+  // mode 3: a band of BAND row tiles of one problem (and outer range) is one group, swept column
+  // chunk by column chunk: the band's row panels of A stay in L2 while each column panel of B
+  // is read once for the whole band
+  constexpr int BAND = 8;
   if (mode == 2)
     std::stable_sort(tiles.begin() + t0, tiles.end(), [](const GemmTile& a, const GemmTile& b) {
       return std::make_tuple(a.prob, a.batch, a.t0, a.tn, a.tm) < std::make_tuple(b.prob, b.batch, b.t0, b.tn, b.tm);
+    });
+  if (mode == 3)
+    std::stable_sort(tiles.begin() + t0, tiles.end(), [](const GemmTile& a, const GemmTile& b) {
+      return std::make_tuple(a.prob, a.batch, a.t0, a.tm / (2 * BAND), a.tn, a.tm) <
+             std::make_tuple(b.prob, b.batch, b.t0, b.tm / (2 * BAND), b.tn, b.tm);
     });
   using Key = std::array<i64, 5>;
   struct KeyHash {
@@ -97,8 +106,9 @@ inline void xcd_order_tiles(std::vector<GemmTile>& tiles, int t0, const std::vec
   };
   for (int i = t0; i < int(tiles.size()); ++i) {
     const Key ka = keyA(tiles[i]), kb = keyB(tiles[i]);
-    const Key k = mode == 2 || small(tiles[i]) ? Key{tiles[i].prob, tiles[i].batch, mode == 2 ? tiles[i].t0 : 0, 0, 2}
-                                               : (ca[ka] >= cb[kb] ? ka : kb);
+    const Key k = mode == 3 ? Key{tiles[i].prob, tiles[i].batch, tiles[i].t0, tiles[i].tm / (2 * BAND), 3}
+                  : mode == 2 || small(tiles[i]) ? Key{tiles[i].prob, tiles[i].batch, mode == 2 ? tiles[i].t0 : 0, 0, 2}
+                                                 : (ca[ka] >= cb[kb] ? ka : kb);
     auto it = gid.find(k);
     if (it == gid.end()) {
       it = gid.emplace(k, int(groups.size())).first;
@@ -1968,7 +1978,7 @@ int device_autotune(Ctx& c, void* stream) {
       t.cols[g] = t.cols[g] == 32 ? 64 : 32;
       if ((st = trial(t, which))) return st;
     }
-    for (int v : {0, 1, 2}) {
+    for (int v : {0, 1, 2, 3}) {
       gwsym_tuning t = best;
       if (v == t.xcd_order[g]) continue;
       t.xcd_order[g] = v;
