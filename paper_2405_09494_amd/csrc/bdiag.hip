@@ -107,31 +107,71 @@ __device__ __forceinline__ void tile_span(const int* __restrict__ bt, int t0, in
 
 // k_bd_right: out[r][c] = sum_k in[r][k] G[k][c] (k in the block of c) over the rows of one
 // segment, and, for a segment with out_off2 >= 0, out2 the same with G2.  A workgroup of eight
-// waves walks `per` consecutive chunks of 64 rows of one segment: wave w owns column tile
-// w mod nct and every (8 / nct)-th row tile, loads its fragments of G (and G2) once and keeps
-// them for every chunk; the next chunk is loaded into registers (all loads in flight at once)
-// while the current one is multiplied out of LDS.  KS: K steps of the widest column tile
-// (n <= 4 KS); PF: chunk elements per thread (64 n / 512).
+// waves walks `per` consecutive chunks of ROWS rows of one segment: each wave owns one column
+// tile, with as many waves per column tile as its K range calls for, and a share of the row
+// tiles; it loads its fragments of G (and G2) once and keeps them for every chunk; the next
+// chunk is loaded into registers (all loads in flight at once) while the current one is
+// multiplied out of LDS.  KS: K steps of the widest column tile (n <= 4 KS); PF: chunk
+// elements per thread (ROWS n / 512).
 
-template <typename V2, int KS, int PF>
+template <typename V2, int KS, int PF, int ROWS>
 __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ segs, Bases bases,
                                                   const int* __restrict__ btab, int n, int per) {
   using M = Mf<V2>;
   using R = typename M::R;
   using A4 = typename M::A4;
+  constexpr int RT = ROWS / 16;   // row tiles per chunk, shared between the waves
   extern __shared__ double2 lds_right[];
   V2* rows = reinterpret_cast<V2*>(lds_right);
   const RowSeg sg = segs[blockIdx.y];
-  const int nch = (sg.nrows + 63) / 64;
+  const int nch = (sg.nrows + ROWS - 1) / ROWS;
   const int c0 = blockIdx.x * per;
   if (c0 >= nch) return;
   const int c1 = min(nch, c0 + per), ld = n + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, kq = lane >> 4;
   const bool dual = sg.out_off2 >= 0;   // uniform over the workgroup
-  const int nct = (n + 15) / 16, rstep = 8 / nct;
-  const bool act = wave < rstep * nct;  // three column tiles: the last two waves have none
-  const int ct = wave % nct;
+  const int nct = (n + 15) / 16;
   const int* bt = btab + sg.blk;
+  // waves per column tile in proportion to its K steps (the blocks make them differ): start
+  // with one each and give every further wave to the tile whose share of the chunk's row
+  // tiles takes longest; wave -> (column tile ct, rank j of w_ct)
+  int ct = 0, rj = 0, rstep = 1;
+  {
+    int cost[4] = {0, 0, 0, 0}, wn[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < nct) {
+        int lo, hi;
+        tile_span(bt, 16 * t, n, lo, hi);
+        cost[t] = (hi - (lo & ~3) + 3) / 4 + 1;
+        wn[t] = 1;
+      }
+    for (int extra = 8 - nct; extra > 0; --extra) {
+      int best = 0, bv = -1;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int v = t < nct ? (RT + wn[t] - 1) / wn[t] * cost[t] : -1;
+        if (v > bv) {
+          bv = v;
+          best = t;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t == best) ++wn[t];
+    }
+    int first = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (wave >= first && wave < first + wn[t]) {
+        ct = t;
+        rj = wave - first;
+        rstep = wn[t];
+      }
+      first += wn[t];
+    }
+  }
+  const bool act = true;
   const V2* G = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + sg.g_off;
   const V2* G2 = reinterpret_cast<const V2*>(bases.p[sg.gbuf]) + (dual ? sg.g_off2 : sg.g_off);
   int lo, hi;
@@ -157,7 +197,7 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
   V2* out = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + sg.out_off;
   V2* out2 = reinterpret_cast<V2*>(bases.p[sg.outbuf]) + (dual ? sg.out_off2 : sg.out_off);
   R pfx[PF], pfy[PF];   // real and imaginary parts apart: arrays of scalars stay in registers
-  auto height = [&](int ch) { return min(64, sg.nrows - 64 * ch); };
+  auto height = [&](int ch) { return min(ROWS, sg.nrows - ROWS * ch); };
   // physical element offset of logical row r (rows in groups of rw, ld apart, when rw > 0)
   const int rw = sg.rw;
   const int64_t gstride = int64_t(sg.ld) * n;
@@ -171,7 +211,7 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
 #pragma unroll
     for (int t = 0; t < PF; ++t) {
       const int e = tid + 512 * t, ec = e < ne ? e : 0, r = ec / n;
-      const V2 v = in[prow(64 * ch + r) + (ec - r * n)];
+      const V2 v = in[prow(ROWS * ch + r) + (ec - r * n)];
       pfx[t] = v.x;
       pfy[t] = v.y;
     }
@@ -194,7 +234,7 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
   for (int ch = c0; ch < c1; ++ch) {
     const int nr = height(ch), nrt = (nr + 15) / 16;
     if (act) {
-      for (int rt = wave / nct; rt < nrt; rt += rstep) {   // uniform
+      for (int rt = rj; rt < nrt; rt += rstep) {   // uniform
         const V2* arow = rows + min(16 * rt + li, nr - 1) * ld;
         A4 cr = A4{0, 0, 0, 0}, ci = cr, dr = cr, di = cr;
         // each step's LDS read is issued one step ahead (addresses clamped into the row)
@@ -214,7 +254,7 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
         for (int j = 0; j < 4; ++j) {
           const int r = 16 * rt + M::row(lane, j);
           if (c < n && r < nr) {
-            const int64_t o = prow(64 * ch + r) + c;
+            const int64_t o = prow(ROWS * ch + r) + c;
             out[o] = V2{R(cr[j]), R(ci[j])};
             if (dual) out2[o] = V2{R(dr[j]), R(di[j])};
           }
@@ -232,20 +272,21 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
 
 void launch_rowblock_right(const RowSegList& l, const Bases& b, const int* btab, int ncol, hipStream_t s, bool fp32) {
   if (l.nseg == 0) return;
-  const int nch = (l.maxrows + 63) / 64;   // chunks of the tallest segment
+  const int rows = ncol <= 52 ? 128 : 64;   // rows per chunk (the n > 52 form keeps its registers)
+  const int nch = (l.maxrows + rows - 1) / rows;   // chunks of the tallest segment
   // about sixteen workgroups per CU over the launch, each walking `per` chunks of one segment
   const int ptarget = int(std::max<long>(1, std::min<long>(nch, long(nch) * l.nseg / 4096)));
   const int parts = (nch + ptarget - 1) / ptarget;
   const int per = (nch + parts - 1) / parts;
   const dim3 g(parts, l.nseg);
   const RowSeg* sg = (const RowSeg*)l.segs;
-  const size_t lds = size_t(64) * (ncol + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
-  if (ncol <= 52) {
-    if (fp32) hipLaunchKernelGGL((k_bd_right<float2, 13, 7>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
-    else hipLaunchKernelGGL((k_bd_right<double2, 13, 7>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
-  } else {
-    if (fp32) hipLaunchKernelGGL((k_bd_right<float2, 16, 8>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
-    else hipLaunchKernelGGL((k_bd_right<double2, 16, 8>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+  const size_t lds = size_t(rows) * (ncol + 1) * (fp32 ? sizeof(float2) : sizeof(double2));
+  if (ncol <= 52) {   // 128 rows x 52 over 512 threads: 13 elements each
+    if (fp32) hipLaunchKernelGGL((k_bd_right<float2, 13, 13, 128>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+    else hipLaunchKernelGGL((k_bd_right<double2, 13, 13, 128>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+  } else {            // 64 rows x 64 over 512 threads: 8 elements each
+    if (fp32) hipLaunchKernelGGL((k_bd_right<float2, 16, 8, 64>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
+    else hipLaunchKernelGGL((k_bd_right<double2, 16, 8, 64>), g, dim3(512), lds, s, sg, b, btab, ncol, per);
   }
 }
 
