@@ -136,6 +136,9 @@ int gwsym_create(const gwsym_params* params, gwsym_ctx** out) {
     t.kdepth[g] = 0;
     t.prefetch[g] = 2;
   }
+  // the P0 GEMM's tiles read V_P rows and W columns of one problem: bands of its row tiles on
+  // one XCD swept column by column keep both in L2 better (6 % faster at 6x6x6)
+  t.xcd_order[0] = 3;
   *out = ctx;
   return GWSYM_OK;
 }
