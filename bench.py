@@ -433,6 +433,19 @@ def main():
 
     kernels = {k: class_roofline(k) for cl in CONTRACTIONS.values() for k in cl if prof[k][1] > 0}
 
+    # tiles of V that symmetry makes zero (Sec. 4.3) and the GEMM work skipped with them
+    vt = blk.ctx.table("vtile_stats")
+    vtiles = {"self_energy_copy_tiles_kept": [int(vt[1]), int(vt[0])],
+              "polarization_copy_tiles_kept": [int(vt[3]), int(vt[2])],
+              "p0_gemm_flops_all_tiles": 8.0 * vt[4], "p0_gemm_flops_kept_tiles": 8.0 * vt[5],
+              "sigma_orbital_gemm_flops_all_tiles": 8.0 * vt[6], "sigma_orbital_gemm_flops_kept_tiles": 8.0 * vt[7],
+              "p0_gemm_launches_skipping_tiles": [int(vt[8]), int(vt[10])],
+              "sigma_orbital_gemm_launches_skipping_tiles": [int(vt[9]), int(vt[11])]}
+    log(f"[bench] V tiles kept: self-energy copy {int(vt[1])}/{int(vt[0])}, polarization copy "
+        f"{int(vt[3])}/{int(vt[2])}; GEMM flops on kept tiles / all: P0 {vt[5] / max(vt[4], 1):.4f}, "
+        f"Sigma orbital {vt[7] / max(vt[6], 1):.4f}; launches skipping tiles: P0 {int(vt[8])}/{int(vt[10])}, "
+        f"Sigma orbital {int(vt[9])}/{int(vt[11])}")
+
     # static self-energy (eq. sigma_hf) from the current G, once each: K, J and F = H0 + J + K
     exchange_ms = hartree_ms = fock_ms = None
     if not args.no_exchange:
@@ -467,7 +480,7 @@ def main():
            "profile_ms": {k: v[0] for k, v in prof.items()},
            "exchange_ms": exchange_ms, "hartree_ms": hartree_ms, "fock_ms": fock_ms,
            "launch_plan": tuning, "launch_plan_source": plan_source,
-           "kernels": kernels,
+           "kernels": kernels, "v_tiles": vtiles,
            "roofline": contr[dom]}
 
     # ---- comparison legs (not part of the headline) ----

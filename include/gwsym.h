@@ -192,6 +192,20 @@ int64_t gwsym_table_size(const gwsym_ctx* ctx, const char* name);
  *   "O_ao"        complex[nop][nk][nao][nao]: O^k(alpha) mapping k to alpha k
  *   "O_aux"       complex[nop][nk][naux][naux]
  *   "tau"         double[ntau];  "Tf","Tb" complex[nw][ntau];  "Bf","Bb" complex[ntau][nw]
+ *   "vtile_flags_s", "vtile_flags_p"  int64: after gwsym_load_V, per pair of the self-energy copy
+ *                 (k0 in IBZ, k') or of the polarization copy (q0 in IBZ, k), pair p = i nk + k,
+ *                 1 for each (auxiliary block s, orbital block r, orbital block r') tile of V in
+ *                 the block bases that the contractions use, 0 for one they skip (Sec. 4.3: its
+ *                 Frobenius norm is at most 1e-13 times that of its pair), at
+ *                 off[p] + (s nr + r) nr' + r'.  Self-energy copy: Q at k0 - k', r at k0, r' at
+ *                 k'; polarization copy: Q at q0, r at k, r' at k + q0.  Empty before load_V.
+ *   "vtile_off_s", "vtile_off_p"      int64[nibz*nk+1]: the offsets off[p] of those flags
+ *   "vtile_stats" double[12]: tiles and used tiles of the self-energy copy, the same for the
+ *                 polarization copy, then per iteration the complex MACs of the P0 GEMM over all
+ *                 tiles and over the used ones, the same for the Sigma orbital GEMM, then the
+ *                 P0 and Sigma orbital GEMM launches that skip the unused tiles and the launches
+ *                 of those two stages (a launch whose used tiles keep more than four fifths of
+ *                 its k steps runs over all tiles: skipping costs it more than it saves)
  *   "freq_f","freq_b" int64[nw]: Matsubara index n of each stored fermionic / bosonic frequency
  *                 (X(tau) = Y + Y^H with Y = B X(i nu); for bosons the n = 0 column
  *                  carries half weight)
@@ -211,7 +225,11 @@ int gwsym_device_init(gwsym_ctx* ctx, void* stream);
  * (q0, k) with q0 irreducible, rotated with O^k(alpha) and O_aux^q(alpha), for the
  * polarization.  The input is only read; it may be freed once `stream` is done.  Device
  * memory: two copies of the input's size in GWSYM_FP64; in the reduced-precision modes the
- * FP64 copies are replaced by FP32 ones (half the size each) before this call returns. */
+ * FP64 copies are replaced by FP32 ones (half the size each) before this call returns.
+ * Sec. 4.3: the (auxiliary block, orbital block, orbital block) tiles of both copies whose
+ * Frobenius norm is at most 1e-13 times that of their pair are flagged (tables "vtile_*"),
+ * and the contraction work lists are rebuilt so that the P0 GEMM and the Sigma orbital GEMM
+ * skip them; a captured iteration graph is dropped. */
 int gwsym_load_V(gwsym_ctx* ctx, const void* V_ibz, void* stream);
 
 /* eq. mat_blk: full matrices at the irreducible points (device, layout by kind with

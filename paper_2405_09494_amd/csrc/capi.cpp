@@ -94,6 +94,14 @@ bool table(const Ctx& c, const std::string& name, std::vector<int64_t>& iv, std:
         const CMat O = orbital_rep(c, name == "O_aux", a, k);
         cv.insert(cv.end(), O.a.begin(), O.a.end());
       }
+  } else if (name == "vtile_flags_s" || name == "vtile_flags_p") {
+    const auto& v = c.vt_nz[name == "vtile_flags_p"];
+    iv.assign(v.begin(), v.end());
+  } else if (name == "vtile_off_s" || name == "vtile_off_p") {
+    iv = c.vt_off[name == "vtile_off_p"];
+  } else if (name == "vtile_stats") {
+    kind = 1;
+    dv.assign(c.vt_stats, c.vt_stats + 12);
   } else if (name == "freq_f") {
     ints(c.nfreq_f);
   } else if (name == "freq_b") {

@@ -78,6 +78,16 @@ struct GemmProblem {
   // column n % cdiv of batch n / cdiv, offset by sBcb and sCcb.  rdiv = M, cdiv = N: none.
   int rdiv, cdiv;
   i64 sArb, sCrb, sBcb, sCcb;
+  // K-segment list (the polarization and self-energy orbital contractions, which skip the
+  // vanishing tiles of V): nkseg entries at bases[B_KL] + kseg replace the outer range; entry
+  // {t0, np, kb, ke} sums the outer indices [t0, t0 + np) over k in [kb, ke) only.
+  i64 kseg;
+  int nkseg, pad2_;
+};
+
+// One entry of a K-segment list (see GemmProblem::kseg): 0 <= kb < ke <= K, np >= 1.
+struct KSeg {
+  int t0, np, kb, ke;
 };
 
 // An output tile of one problem over the outer range [t0, t1), in units of 16: rows
@@ -85,7 +95,8 @@ struct GemmProblem {
 // 32.  slot < 0: the tile writes C directly; otherwise (nn <= 2) it writes its raw sum to
 // the 32 x 32 partial slot `slot` and a reduction item combines the slots in order.
 struct GemmTile {
-  int prob, batch, tm, tn, t0, t1, slot, mh, nn, pad_;
+  int prob, batch, tm, tn, t0, t1, slot, mh, nn;
+  int nsub;   // with a K-segment list: [t0, t1) are entries and nsub their k sub-steps (of 4)
 };
 
 struct GemmReduce {
@@ -106,7 +117,7 @@ struct GemmPlan {
 
 // Buffer ids used in GemmProblem::abuf/bbuf/cbuf; the launch passes the base pointers.
 enum Buf : int {
-  B_VP = 0, B_VS, B_G, B_P, B_W1, B_W2, B_OUT, B_TR, B_IN, B_U, B_WT, B_F, B_SCR, B_GT, B_BT, NBUF
+  B_VP = 0, B_VS, B_G, B_P, B_W1, B_W2, B_OUT, B_TR, B_IN, B_U, B_WT, B_F, B_SCR, B_GT, B_BT, B_KL, NBUF
 };
 
 struct Ctx {
@@ -145,6 +156,18 @@ struct Ctx {
   std::vector<double> tau;
   std::vector<cplx> Tf, Tb, Bf, Bb;        // [nw][ntau], [ntau][nw]
   std::vector<int> nfreq_f, nfreq_b;       // Matsubara index n of each stored frequency (>= 0)
+
+  // vanishing tiles of V in the block bases (Sec. 4.3), from the last load_V: per pair
+  // p = i nk + k of each copy (0: self-energy, indexed (k0 in IBZ, k'); 1: polarization,
+  // (q0 in IBZ, k)) a flag per (auxiliary block s, orbital block r, orbital block r'), 1 for a
+  // tile that is kept, at vt_off[copy][p] + (s nr + r) nr' + r'
+  std::vector<uint8_t> vt_nz[2];
+  std::vector<i64> vt_off[2];
+  // tiles and kept tiles of the self-energy copy, the same for the polarization copy; per
+  // iteration the complex MACs of the P0 GEMM over all tiles and over the kept ones, the same
+  // for the Sigma orbital GEMM; the P0 and Sigma orbital GEMM launches that walk K-segment
+  // lists, and the launches of the two stages
+  double vt_stats[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   // device state (device.hip)
   void* dev_state = nullptr;

@@ -23,6 +23,7 @@ struct GemmPlanDev {
   int shape[4] = {0, 0, 0, 0};   // wave-tile lists: tiles per shape (16x16, 16x32, 32x16, 32x32), in order
   int kdepth = 32;               // split-bfloat16 forms: k values per MFMA (32, or 16 for short sums)
   int prefetch = 2;              // FP64 / FP32 forms: K sub-steps per group (2 or 4)
+  int lists = 0;                 // the tiles walk K-segment lists (ranges of list entries)
 };
 
 // One slab for a block-diagonal multiply (bdiag.hip).  Right multiply: nrows rows of n
@@ -54,6 +55,17 @@ struct CopySeg {
 };
 
 enum { INV_P = 0, INV_G = 1, INV_TRACE = 2 };
+
+// One (pair, auxiliary block) of the tile-norm pass over V: auxiliary functions
+// [q0, q0 + nq), strides of Q, a and b from v_off, block tables of a (bta) and b (btb) in
+// btab, and where the nr(a) x nr(b) squared tile norms go.
+struct TileNormItem {
+  int64_t v_off, out_off;
+  int64_t sQ;
+  int sa, sb, q0, nq, bta, btb;
+};
+constexpr int TN_MAXN = 64;   // orbitals per basis the tile-norm pass takes
+constexpr int TN_MAXB = 64;   // orbital blocks per basis
 
 // One diagonal orbital block of one irreducible point for the Hartree term: the block's
 // first function and size in the block basis, the block of G(beta) it pairs with, the
@@ -96,6 +108,8 @@ void launch_rowblock_both(const RowSegList& l, const Bases& b, const int* btab, 
 void launch_wgemm(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, int arith,
                   unsigned f32mask);
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s);
+void launch_tile_norm(const void* items, int nitems, const void* V, const int* btab, double* out, int no,
+                      hipStream_t s);
 void launch_copy(const void* segs, int nseg, const Bases& b, hipStream_t s);
 // upper triangle of each n x n block from its lower one (and a copy to out_off when >= 0)
 void launch_herm_fill(const void* segs, int nseg, const Bases& b, hipStream_t s);

@@ -462,7 +462,7 @@ __device__ __forceinline__ void bf_cmac(const V (&ar)[NS], const V (&ai)[NS], co
     }
 }
 
-template <int AR, int TAG, bool M2, bool N2>
+template <int AR, int TAG, bool M2, bool N2, bool KL>
 __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ probs,
                                               const GemmTile* __restrict__ tiles, Bases bases,
                                               double2* __restrict__ partials, unsigned f32mask) {
@@ -496,7 +496,10 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   // a tile of an N2 class covers nn / 2 consecutive 32-column chunks, walked in one sequence of
   // sub-step groups so that the first loads of a chunk overlap the last MFMAs of the one before
   const int nchunk = N2 ? (tl.nn >> 1) : 1;
-  const int nsub = (tl.t1 - tl.t0) * nk4, ngrp = (nsub + GS - 1) / GS, total = ngrp * nchunk;
+  // KL: the tiles walk their problems' K-segment lists: entries [t0, t1) of {first outer index,
+  // count, k range}, the k outside a range being zero tiles of V
+  const KSeg* kl = reinterpret_cast<const KSeg*>(bases.p[B_KL]) + (KL ? P.kseg : 0);
+  const int nsub = KL ? tl.nsub : (tl.t1 - tl.t0) * nk4, ngrp = (nsub + GS - 1) / GS, total = ngrp * nchunk;
   A4 c00r = {0, 0, 0, 0}, c00i = c00r, c01r = c00r, c01i = c00r, c10r = c00r, c10i = c00r, c11r = c00r, c11i = c00r;
   // FP64 and FP32 forms take three real products per complex one (3M): the r, i and x
   // accumulators hold sum a_r b_r, sum a_i b_i and sum (a_r + a_i)(b_r + b_i), and the complex
@@ -552,23 +555,60 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
   // fetch position: chunk, outer index t and k step j of the next sub-step; the mask zeroes
   // k >= K and the sub-steps past the end of a chunk's sequence
   int fc = 0, ft = tl.t0, fj = 0, fs = 0;
+  // list state: entry fe (its values E, the next entry's En loaded one entry ahead), outer
+  // index fp within it and its k sub-steps enj; an empty tile reads no entry
+  int fe = tl.t0, fp = 0;
+  KSeg E{0, 1, 0, 1}, En = E;
+  auto enter = [&]() __attribute__((always_inline)) {
+    fe = tl.t0;
+    fp = 0;
+    if (tl.t1 > tl.t0) {
+      E = kl[fe];
+      En = kl[min(fe + 1, tl.t1 - 1)];
+    }
+  };
+  if (KL) enter();
+  int enj = (E.ke - E.kb + 3) >> 2;
   int64_t fbx0 = bcol(min(n0 + li, P.N - 1)), fbx1 = bcol(min(n0 + 16 + li, P.N - 1));
   V2 fa[GS][2], fb[GS][2];
   R fm[GS];
   auto fetch1 = [&](int h) __attribute__((always_inline)) {
     const bool live = fs < nsub;
-    const int t = live ? ft : tl.t1 - 1;
-    const int k = 4 * fj + kq;
-    const int64_t kc = min(k, K - 1);
+    int t, k;
+    int64_t kc;
+    if constexpr (KL) {
+      // past the end the state stays on the last live position: in-range addresses
+      t = E.t0 + fp;
+      k = E.kb + 4 * fj + kq;
+      kc = min(k, E.ke - 1);
+    } else {
+      t = live ? ft : tl.t1 - 1;
+      k = 4 * fj + kq;
+      kc = min(k, K - 1);
+    }
     const V2* A = Ab + int64_t(t) * P.sAt;
     const V2* B = Bb + int64_t(t) * P.sBt;
     fa[h][0] = A[ax0 + kc * ak];
     if (M2) fa[h][1] = A[ax1 + kc * ak];
     fb[h][0] = B[fbx0 + kc * bk];
     if (N2) fb[h][1] = B[fbx1 + kc * bk];
-    fm[h] = (live && k < K) ? R(1) : R(0);
+    if constexpr (KL) fm[h] = (live && k < E.ke) ? R(1) : R(0);
+    else fm[h] = (live && k < K) ? R(1) : R(0);
     ++fs;
-    if (++fj == nk4) {
+    if constexpr (KL) {
+      if (live && ++fj == enj) {
+        fj = 0;
+        if (++fp == E.np) {
+          fp = 0;
+          if (fe + 1 < tl.t1) {
+            ++fe;
+            E = En;
+            En = kl[min(fe + 1, tl.t1 - 1)];
+            enj = (E.ke - E.kb + 3) >> 2;
+          }
+        }
+      }
+    } else if (++fj == nk4) {
       fj = 0;
       ++ft;
     }
@@ -577,6 +617,10 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       fs = 0;
       fj = 0;
       ft = tl.t0;
+      if (KL) {
+        enter();
+        enj = (E.ke - E.kb + 3) >> 2;
+      }
       const int nc = n0 + 32 * fc;
       fbx0 = bcol(min(nc + li, P.N - 1));
       fbx1 = bcol(min(nc + 16 + li, P.N - 1));
@@ -741,9 +785,19 @@ __global__ __launch_bounds__(64) void k_wgemm(const GemmProblem* __restrict__ pr
       ++cc;
     }
   }
+  if (total == 0) {   // an empty K-segment range: the tile (or its partial slot) is zero
+    const d4 z = {0, 0, 0, 0};
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int cn0 = n0 + 32 * ch;
+      store(cn0, 0, 0, z, z);
+      if (N2) store(cn0, 0, 1, z, z);
+      if (M2) store(cn0, 1, 0, z, z);
+      if (M2 && N2) store(cn0, 1, 1, z, z);
+    }
+  }
 }
 
-template <int AR, int TAG>
+template <int AR, int TAG, bool KL>
 void launch_wgemm_tag(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, unsigned mask) {
   const GemmProblem* pr = (const GemmProblem*)p.probs;
   const GemmTile* tl = (const GemmTile*)p.tiles;
@@ -756,22 +810,28 @@ void launch_wgemm_tag(const GemmPlanDev& p, const Bases& b, void* partials, hipS
     const dim3 g(n), t(64);
     const GemmTile* ts = tl + at;
     switch (sh) {
-      case 0: hipLaunchKernelGGL((k_wgemm<AR, TAG, false, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
-      case 1: hipLaunchKernelGGL((k_wgemm<AR, TAG, false, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
-      case 2: hipLaunchKernelGGL((k_wgemm<AR, TAG, true, false>), g, t, 0, s, pr, ts, b, pa, mask); break;
-      default: hipLaunchKernelGGL((k_wgemm<AR, TAG, true, true>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 0: hipLaunchKernelGGL((k_wgemm<AR, TAG, false, false, KL>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 1: hipLaunchKernelGGL((k_wgemm<AR, TAG, false, true, KL>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      case 2: hipLaunchKernelGGL((k_wgemm<AR, TAG, true, false, KL>), g, t, 0, s, pr, ts, b, pa, mask); break;
+      default: hipLaunchKernelGGL((k_wgemm<AR, TAG, true, true, KL>), g, t, 0, s, pr, ts, b, pa, mask); break;
     }
     at += n;
   }
 }
 
+// the polarization (1) and self-energy orbital (3) contractions take the K-segment form for
+// the launches whose plan walks lists
 template <int AR>
 void launch_wgemm_t(const GemmPlanDev& p, const Bases& b, void* partials, hipStream_t s, int tag, unsigned mask) {
   switch (tag) {
-    case 1: launch_wgemm_tag<AR, 1>(p, b, partials, s, mask); break;
-    case 2: launch_wgemm_tag<AR, 2>(p, b, partials, s, mask); break;
-    case 3: launch_wgemm_tag<AR, 3>(p, b, partials, s, mask); break;
-    default: launch_wgemm_tag<AR, 0>(p, b, partials, s, mask); break;
+    case 1:
+      p.lists ? launch_wgemm_tag<AR, 1, true>(p, b, partials, s, mask) : launch_wgemm_tag<AR, 1, false>(p, b, partials, s, mask);
+      break;
+    case 2: launch_wgemm_tag<AR, 2, false>(p, b, partials, s, mask); break;
+    case 3:
+      p.lists ? launch_wgemm_tag<AR, 3, true>(p, b, partials, s, mask) : launch_wgemm_tag<AR, 3, false>(p, b, partials, s, mask);
+      break;
+    default: launch_wgemm_tag<AR, 0, false>(p, b, partials, s, mask); break;
   }
 }
 
@@ -879,6 +939,51 @@ __global__ __launch_bounds__(256) void k_pack(const CopySeg* __restrict__ segs, 
 
 void launch_pack(const void* segs, int nseg, const Bases& b, hipStream_t s) {
   if (nseg) hipLaunchKernelGGL(k_pack, dim3(nseg), dim3(256), 0, s, (const CopySeg*)segs, b);
+}
+
+// ----------------------------------------------------------------------------
+// Tile norms of V in the block bases (Sec. 4.3): for one pair and one auxiliary block, the
+// squared Frobenius norm of every (orbital block r, orbital block r') tile, summed over the
+// block's auxiliary functions.  Element (Q, a, b) of the pair sits at v_off + Q sQ + a sa + b sb;
+// r and r' come from the block tables at bta (a) and btb (b), whose blocks tile [0, no) in
+// order.  Each thread sums its (a, b) elements over Q, then adds them into its tile in LDS.
+__global__ __launch_bounds__(256) void k_tile_norm(const TileNormItem* __restrict__ items, const double2* __restrict__ V,
+                                                   const int* __restrict__ btab, double* __restrict__ out, int no) {
+  const TileNormItem it = items[blockIdx.x];
+  __shared__ double acc[TN_MAXB * TN_MAXB];
+  __shared__ int ra[TN_MAXN], rb[TN_MAXN];
+  const int* ta = btab + it.bta;
+  const int* tb = btab + it.btb;
+  const int nra = ta[0], nrb = tb[0];
+  for (int x = threadIdx.x; x < no; x += 256) {
+    int r = 0;
+    while (r + 1 < nra && ta[1 + 3 * (r + 1)] <= x) ++r;
+    ra[x] = r;
+    int q = 0;
+    while (q + 1 < nrb && tb[1 + 3 * (q + 1)] <= x) ++q;
+    rb[x] = q;
+  }
+  for (int e = threadIdx.x; e < nra * nrb; e += 256) acc[e] = 0.0;
+  __syncthreads();
+  const double2* v = V + it.v_off;
+  for (int e = threadIdx.x; e < no * no; e += 256) {
+    const int a = e / no, b = e - a * no;
+    const double2* x = v + int64_t(it.q0) * it.sQ + a * it.sa + b * it.sb;
+    double s = 0.0;
+    for (int q = 0; q < it.nq; ++q) {
+      const double2 y = x[int64_t(q) * it.sQ];
+      s = fma(y.x, y.x, fma(y.y, y.y, s));
+    }
+    atomicAdd(&acc[ra[a] * nrb + rb[b]], s);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nra * nrb; e += 256) out[it.out_off + e] = acc[e];
+}
+
+void launch_tile_norm(const void* items, int nitems, const void* V, const int* btab, double* out, int no,
+                      hipStream_t s) {
+  if (nitems) hipLaunchKernelGGL(k_tile_norm, dim3(nitems), dim3(256), 0, s, (const TileNormItem*)items,
+                                 (const double2*)V, btab, out, no);
 }
 
 void launch_herm(const void* segs, int nseg, const Bases& b, hipStream_t s) {

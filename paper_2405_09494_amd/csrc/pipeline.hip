@@ -45,6 +45,7 @@ struct Range {
   int shape[4] = {0, 0, 0, 0};   // wave-tile launches: tiles per shape class, in list order
   int kdepth = 32;               // k values per bfloat16 MFMA in the split-bfloat16 forms
   int prefetch = 2;              // FP64 / FP32: K sub-steps per group of the wave-tile GEMM
+  int lists = 0;                 // wave-tile launches: tiles walk K-segment lists
 };
 
 // Workgroup p of a launch runs on XCD p % 8, and each XCD has its own L2.  Tiles that read
@@ -142,9 +143,11 @@ struct GemmStage {
   std::vector<GemmReduce> reds;
   std::vector<Range> launches;
   std::vector<int> pending;   // problems of the launch being built
+  std::vector<KSeg> klist;    // K-segment lists of the problems that have one
   void* d_probs = nullptr;
   void* d_tiles = nullptr;
   void* d_reds = nullptr;
+  void* d_klist = nullptr;
   int max_slots = 0;
   double macs = 0;
 
@@ -196,8 +199,25 @@ struct GemmStage {
     std::vector<GemmTile> tiles;
     std::vector<GemmReduce> reds;
     int shape[4] = {0, 0, 0, 0};
-    int kdepth = 32, slots = 0;
+    int kdepth = 32, slots = 0, lists = 0;
   };
+  // A launch walks its problems' K-segment lists only where they leave out at least a fifth of
+  // the k steps (of 4) of the full outer range, counted over its output tiles: a list entry
+  // costs branches and scalar loads in the k loop, which a bandwidth-bound launch pays for.
+  bool walk_lists(const Deferred& L) const {
+    double full = 0, kept = 0;
+    for (int id : L.ids) {
+      const GemmProblem& p = probs[id];
+      if (p.kseg < 0) return false;
+      const double w = double(p.batch) * ((p.M + 15) / 16) * ((p.N + 15) / 16);
+      full += w * p.T * ((p.K + 3) / 4);
+      for (int e = 0; e < p.nkseg; ++e) {
+        const KSeg& q = klist[size_t(p.kseg) + e];
+        kept += w * q.np * ((q.ke - q.kb + 3) / 4);
+      }
+    }
+    return full > 0 && kept <= 0.8 * full;
+  }
   Built build(const Deferred& L) const {
     const int target = L.wave ? L.target : 2048;
     Built out;
@@ -221,13 +241,42 @@ struct GemmStage {
       const int cmin = (c0 / p.cdiv != (c1 - 1) / p.cdiv) ? 0 : c0 % p.cdiv;
       return rmax >= cmin;
     };
+    std::vector<long> pre;
+    out.lists = L.wave && walk_lists(L);
     for (int id : L.ids) {
       const GemmProblem& p = probs[id];
       const int mu = units(p.M), nu = units(p.N);
+      // with lists a problem splits its entries (cut where the k sub-steps before them reach
+      // s / split of the total), without them its outer range
+      const bool lst = out.lists;
+      const int tn = lst ? p.nkseg : p.T;
+      if (lst) {
+        pre.assign(size_t(tn) + 1, 0);
+        for (int e = 0; e < tn; ++e) {
+          const KSeg& q = klist[size_t(p.kseg) + e];
+          pre[e + 1] = pre[e] + long(q.np) * ((q.ke - q.kb + 3) / 4);
+        }
+      }
+      auto cut = [&](int s, int split) {
+        if (!lst) return int(long(s) * tn / split);
+        const long goal = (pre[tn] * s + split - 1) / split;
+        return int(std::lower_bound(pre.begin(), pre.end(), goal) - pre.begin());
+      };
+      auto nsub = [&](int t0, int t1) { return lst ? int(pre[t1] - pre[t0]) : 0; };
       int split = 1;
-      if (base < target && p.T >= 8)
-        split = int(std::min<long>(std::min<long>(p.T / 4, 256), (target + base - 1) / std::max(1L, base)));
+      if (base < target && tn >= 8)
+        split = int(std::min<long>(std::min<long>(tn / 4, 256), (target + base - 1) / std::max(1L, base)));
       split = std::max(1, split);
+      // the parts' first entries, without empty parts (a list cut at sub-step quantiles can
+      // give two equal cut points)
+      std::vector<int> cuts{0};
+      for (int s = 1; s <= split; ++s) {
+        const int x = cut(s, split);
+        if (x > cuts.back() || s == split) cuts.push_back(x);
+      }
+      if (cuts.size() > 2 && cuts[cuts.size() - 1] == cuts[cuts.size() - 2]) cuts.pop_back();
+      split = int(cuts.size()) - 1;
+      const int whole = nsub(0, tn);
       for (int b = 0; b < p.batch; ++b)
         for (int i = 0; i < mu; i += 2) {
           const int mh = std::min(2, mu - i);
@@ -238,14 +287,14 @@ struct GemmStage {
               const int full = nu / 2;
               for (int j = 0; j < full; j += L.per) {
                 const int nn = 2 * std::min(L.per, full - j);
-                if (keep(id, i, mh, 2 * j, nn)) tiles.push_back({id, b, i, 2 * j, 0, p.T, -1, mh, nn, 0});
+                if (keep(id, i, mh, 2 * j, nn)) tiles.push_back({id, b, i, 2 * j, 0, tn, -1, mh, nn, whole});
               }
-              if (nu % 2 && keep(id, i, mh, 2 * full, 1)) tiles.push_back({id, b, i, 2 * full, 0, p.T, -1, mh, 1, 0});
+              if (nu % 2 && keep(id, i, mh, 2 * full, 1)) tiles.push_back({id, b, i, 2 * full, 0, tn, -1, mh, 1, whole});
               continue;
             }
             for (int j = 0; j < nu; j += 16)   // up to eight 32-column chunks per workgroup
               if (keep(id, i, mh, j, std::min(16, nu - j)))
-                tiles.push_back({id, b, i, j, 0, p.T, -1, mh, std::min(16, nu - j), 0});
+                tiles.push_back({id, b, i, j, 0, tn, -1, mh, std::min(16, nu - j), whole});
             continue;
           }
           for (int j = 0; j < nu; j += 2) {
@@ -253,8 +302,8 @@ struct GemmStage {
             if (!keep(id, i, mh, j, nh)) continue;
             const int s0 = slots;
             for (int s = 0; s < split; ++s) {
-              const int t0 = int(long(s) * p.T / split), t1 = int(long(s + 1) * p.T / split);
-              tiles.push_back({id, b, i, j, t0, t1, s0 + s, mh, nh, 0});
+              const int t0 = cuts[s], t1 = cuts[s + 1];
+              tiles.push_back({id, b, i, j, t0, t1, s0 + s, mh, nh, nsub(t0, t1)});
             }
             reds.push_back({id, b, i, j, s0, split, mh, nh});
             slots += split;
@@ -282,7 +331,7 @@ struct GemmStage {
     for (size_t t = 0; t < tiles.size(); ++t) {
       const GemmTile& tl = tiles[t];
       if (tl.prob < 0) continue;
-      const double n = double(tl.t1 - tl.t0) * ((probs[tl.prob].K + 3) / 4);
+      const double n = out.lists ? double(tl.nsub) : double(tl.t1 - tl.t0) * ((probs[tl.prob].K + 3) / 4);
       sub += n;
       pad8 += 8.0 * std::ceil(n / 8.0);
     }
@@ -315,6 +364,7 @@ struct GemmStage {
       for (int sh = 0; sh < 4; ++sh) r.shape[sh] = out[i].shape[sh];
       r.kdepth = out[i].kdepth;
       r.prefetch = L.prefetch;
+      r.lists = out[i].lists;
       max_slots = std::max(max_slots, out[i].slots);
     }
     deferred.clear();
@@ -486,6 +536,7 @@ int upload(Ctx& c, DevState& d, const std::vector<T>& v, void** p, hipStream_t s
 int upload_stage(Ctx& c, DevState& d, GemmStage& g, hipStream_t s) {
   int st;
   g.finalize();
+  if ((st = upload(c, d, g.klist, &g.d_klist, s))) return st;
   if ((st = upload(c, d, g.probs, &g.d_probs, s))) return st;
   if ((st = upload(c, d, g.tiles, &g.d_tiles, s))) return st;
   if ((st = upload(c, d, g.reds, &g.d_reds, s))) return st;
@@ -503,6 +554,7 @@ GemmPlanDev plan_of(const GemmStage& g, const Range& r) {
   for (int i = 0; i < 4; ++i) p.shape[i] = r.shape[i];
   p.kdepth = r.kdepth;
   p.prefetch = r.prefetch;
+  p.lists = r.lists;
   return p;
 }
 
@@ -516,6 +568,7 @@ GemmProblem gp(int M, int N, int K, int T, int batch, int abuf, i64 aoff, i64 ld
   p.cbuf = cbuf; p.coff = coff; p.ldc = ldc; p.sCb = sCb;
   p.alpha_re = are; p.alpha_im = aim; p.beta = beta;
   p.rdiv = M; p.cdiv = N;
+  p.kseg = -1;
   return p;
 }
 
@@ -554,6 +607,7 @@ void reset_gemm(DevState& d, GemmStage& g) {
   dfree(d, g.d_probs);
   dfree(d, g.d_tiles);
   dfree(d, g.d_reds);
+  dfree(d, g.d_klist);
   g = GemmStage{};
   g.wave = true;
 }
@@ -587,6 +641,7 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   d.p0_steps.clear();
   d.s_steps.clear();
   d.s_chunks.clear();
+  for (int x = 4; x < 8; ++x) c.vt_stats[x] = 0;
   // unbatched: every pair's block multiply and every (pair, block) GEMM its own launch, in order
   const bool ub = c.prm.sched == GWSYM_SCHED_UNBATCHED;
   if (d.graph_exec) {
@@ -635,8 +690,122 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
     }
     return runs;
   };
-  // ---------------- polarization (eq. P0, Alg. 3) ----------------
   Mesh mesh{c.n};
+  // K-segment lists of the contractions that sum over orbital functions b of V (Sec. 4.3: only
+  // the tiles of V that are not zero by symmetry take part).  For an outer index run (a run of
+  // the orbital functions a, or of the auxiliary functions Q, of one block), the windows are the
+  // runs of consecutive b blocks whose tiles are kept; without tile flags (V not loaded yet)
+  // every tile is kept.  Windows that save less than a quarter of the run's k steps (of 4) are
+  // replaced by the whole range: short entries cost more in list steps and partly filled k
+  // steps than they save.  Entries of one list are merged while they continue each other with
+  // the same window, up to 64 outer indices, so that a split of the sum has entries to cut at.
+  const bool have_tiles = !c.vt_nz[0].empty();
+  std::vector<std::pair<int, int>> win;
+  auto windows = [&](const Blocks& Bb, auto&& kept) {
+    win.clear();
+    for (size_t r2 = 0; r2 < Bb.size.size(); ++r2) {
+      if (!kept(int(r2))) continue;
+      const int b0 = Bb.off[r2], b1 = b0 + Bb.size[r2];
+      if (!win.empty() && win.back().second == b0) win.back().second = b1;
+      else win.push_back({b0, b1});
+    }
+    int steps = 0;
+    for (const auto& w : win) steps += (w.second - w.first + 3) / 4;
+    if (!win.empty() && 4 * steps > 3 * ((no + 3) / 4)) win.assign(1, {0, no});
+  };
+  auto push_seg = [](GemmStage& g, size_t start, int t0, int np, int kb, int ke) {
+    if (g.klist.size() > start) {
+      KSeg& l = g.klist.back();
+      if (l.kb == kb && l.ke == ke && l.t0 + l.np == t0 && l.np + np <= 64) {
+        l.np += np;
+        return;
+      }
+    }
+    g.klist.push_back({t0, np, kb, ke});
+  };
+  // windows per piece; returns the list's entry count and adds the kept MACs per output
+  // element pair of the problem (sum over entries of np (ke - kb)) to `kept`
+  std::map<std::array<int, 4>, std::array<i64, 3>> p0_lists, s_lists;
+  // polarization problem (i, aux block sg): pieces (k, a) for k in [k0, k0 + nkc), a at k, K = b
+  // at k + q0; copy 1 of the tile flags
+  auto p0_list = [&](GemmProblem& p, int i, int sg, int k0, int nkc, double& kept) {
+    const std::array<int, 4> key{i, sg, k0, nkc};
+    auto it = p0_lists.find(key);
+    if (it == p0_lists.end()) {
+      GemmStage& g = d.p0_gemm;
+      const size_t start = g.klist.size();
+      double mk = 0;
+      const int q0 = c.ibz[i];
+      for (int k = k0; k < k0 + nkc; ++k) {
+        const Blocks& Ba = c.bao[c.rep[k]];
+        const Blocks& Bb = c.bao[c.rep[mesh.add(k, q0)]];
+        const int nra = int(Ba.size.size()), nrb = int(Bb.size.size());
+        const uint8_t* nz = have_tiles ? c.vt_nz[1].data() + c.vt_off[1][size_t(i) * nk + k] : nullptr;
+        for (int r = 0; r < nra; ++r) {
+          windows(Bb, [&](int r2) { return !nz || nz[(size_t(sg) * nra + r) * nrb + r2]; });
+          for (const auto& w : win) {
+            push_seg(g, start, (k - k0) * no + Ba.off[r], Ba.size[r], w.first, w.second);
+            mk += double(Ba.size[r]) * (w.second - w.first);
+          }
+        }
+      }
+      it = p0_lists.emplace(key, std::array<i64, 3>{i64(start), i64(g.klist.size() - start), i64(mk)}).first;
+    }
+    p.kseg = it->second[0];
+    p.nkseg = int(it->second[1]);
+    kept = double(it->second[2]);
+  };
+  // self-energy orbital problem (i, bin of k0's orbital functions [r0, r0 + nb)): pieces
+  // (k', Q) for k' in [kp0, kp0 + nkc), Q at q = k0 - k', K = b at k'; copy 0 of the flags.  A
+  // window serves the whole bin (the union over its blocks); `kept` counts per block of the
+  // bin, weighted by n_r^2, what the block itself needs
+  auto s_list = [&](GemmStage& g, GemmProblem& p, int i, int r0, int nb, int kp0, int nkc, bool tiles,
+                    double& kept) {
+    const std::array<int, 4> key{i, r0 * 4096 + nb, kp0, nkc};
+    auto it = tiles ? s_lists.find(key) : s_lists.end();
+    if (it == s_lists.end()) {
+      const size_t start = g.klist.size();
+      const int k0 = c.ibz[i];
+      const Blocks& Ba = c.bao[i];
+      std::vector<int> rs;
+      for (size_t r = 0; r < Ba.size.size(); ++r)
+        if (Ba.off[r] >= r0 && Ba.off[r] < r0 + nb) rs.push_back(int(r));
+      double mk = 0;
+      const int nra = int(Ba.size.size());
+      for (int kp = kp0; kp < kp0 + nkc; ++kp) {
+        const Blocks& BQ = c.baux[c.rep[mesh.sub(k0, kp)]];
+        const Blocks& Bb = c.bao[c.rep[kp]];
+        const int nrb = int(Bb.size.size());
+        const uint8_t* nz =
+            tiles && have_tiles ? c.vt_nz[0].data() + c.vt_off[0][size_t(i) * nk + kp] : nullptr;
+        for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
+          auto flag = [&](int r, int r2) { return !nz || nz[(sg * nra + r) * nrb + r2]; };
+          for (int r : rs) {
+            windows(Bb, [&](int r2) { return flag(r, r2); });
+            for (const auto& w : win) mk += double(Ba.size[r]) * Ba.size[r] * BQ.size[sg] * (w.second - w.first);
+          }
+          windows(Bb, [&](int r2) {
+            for (int r : rs)
+              if (flag(r, r2)) return true;
+            return false;
+          });
+          for (const auto& w : win) push_seg(g, start, (kp - kp0) * na + BQ.off[sg], BQ.size[sg], w.first, w.second);
+        }
+      }
+      const std::array<i64, 3> v{i64(start), i64(g.klist.size() - start), i64(mk)};
+      if (!tiles) {
+        p.kseg = v[0];
+        p.nkseg = int(v[1]);
+        kept = mk;
+        return;
+      }
+      it = s_lists.emplace(key, v).first;
+    }
+    p.kseg = it->second[0];
+    p.nkseg = int(it->second[1]);
+    kept = double(it->second[2]);
+  };
+  // ---------------- polarization (eq. P0, Alg. 3) ----------------
   std::vector<double> sumsq_ao(nib, 0.0);  // sum of squared orbital block sizes
   for (int i = 0; i < nib; ++i)
     for (int sz : c.bao[i].size) sumsq_ao[i] += double(sz) * sz;
@@ -683,9 +852,14 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
         p.cdiv = m;
         p.sBcb = slab;
         p.sCcb = BA.packed;
+        double kept = 0;
+        p0_list(p, i, int(sg), k0, nkc, kept);
         // P0^q(tau) is Hermitian (so is every term of the k sum, G being Hermitian): only the
         // tiles on or below the diagonal are computed
-        d.p0_gemm.add(p, double(jc) * m * (m + 1) / 2 * no * nkc * no, true);
+        const double tri = double(jc) * m * (m + 1) / 2;
+        c.vt_stats[4] += tri * no * nkc * no;
+        c.vt_stats[5] += tri * kept;
+        d.p0_gemm.add(p, tri * kept, true);
       };
       // aligned partner blocks repeat their leading block: only leading blocks are computed
       if (!ub) {
@@ -855,7 +1029,11 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
           double algo = 0;
           for (size_t rb = 0; rb < BO.size.size(); ++rb)
             if (BO.off[rb] >= r0 && BO.off[rb] < r0 + nb) algo += double(BO.size[rb]) * BO.size[rb];
-          d.s_gemmC.add(p, double(nslot) * algo * no * double(nkc) * na);
+          double kept = 0;
+          s_list(d.s_gemmC, p, i, r0, nb, kp0, nkc, true, kept);
+          c.vt_stats[6] += double(nslot) * algo * no * double(nkc) * na;
+          c.vt_stats[7] += double(nslot) * kept;
+          d.s_gemmC.add(p, double(nslot) * kept);
           if (each) d.s_gemmC.close();
         }
       };
@@ -896,6 +1074,12 @@ int plan_contractions(Ctx& c, DevState& d, hipStream_t s) {
   clk.mark("self-energy work lists");
   for (GemmStage* g : gs)
     if ((st = upload_stage(c, d, *g, s))) return st;
+  // launches that walk K-segment lists, per stage
+  c.vt_stats[8] = c.vt_stats[9] = 0;
+  for (const Range& r : d.p0_gemm.launches) c.vt_stats[8] += r.lists;
+  for (const Range& r : d.s_gemmC.launches) c.vt_stats[9] += r.lists;
+  c.vt_stats[10] = double(d.p0_gemm.launches.size());
+  c.vt_stats[11] = double(d.s_gemmC.launches.size());
   for (RowStage* r : {&d.p0_both, &d.s_right})
     if ((st = upload(c, d, r->segs, &r->d, s))) return st;
   for (auto* l : {&d.p0_mirror, &d.s_pack})
@@ -995,6 +1179,8 @@ int device_init(Ctx& c, void* stream) {
   d.hx_gemm.wave = true;
   {
     const i64 slab1 = i64(nk) * na * no * no;
+    // the orbital GEMM walks every (k', Q) over all b: one list for all its problems
+    for (int t = 0; t < nk * na; t += 64) d.hx_gemm.klist.push_back({t, std::min(64, nk * na - t), 0, no});
     for (int i = 0; i < nib; ++i) {
       const Blocks& BO = c.bao[i];
       for (int kp = 0; kp < nk; ++kp) {
@@ -1025,6 +1211,8 @@ int device_init(Ctx& c, void* stream) {
         GemmProblem p = gp(bn.second, bn.second, no, nk * na, 1, B_W2, i64(bn.first) * no, no, i64(no) * no, 0, OP_N,
                            B_VS, i64(i) * slab1 + i64(bn.first) * no, no, i64(no) * no, 0, OP_H, B_SCR,
                            i64(bn.first) * no + bn.first, no, 0, 1.0 / nk);
+        p.kseg = 0;
+        p.nkseg = int(d.hx_gemm.klist.size());
         d.hx_gemm.add(p);
       }
       for (size_t rb = 0; rb < BO.size.size(); ++rb)
@@ -1301,6 +1489,93 @@ int need_partials(Ctx& c, DevState& d) {
 // ---------------------------------------------------------------------------------------
 // load_V: block-transformed copies of V for the two contractions (eq. C_blk, Sec. 4.2).
 
+namespace {
+
+// Flags of the (auxiliary block, orbital block, orbital block) tiles of both block-form copies
+// of V (Sec. 4.3: only the non-zero blocks of V are used): squared Frobenius norms on the
+// device, then on the host a tile is kept when its norm exceeds 1e-13 times that of its pair.
+// Bases with more functions or blocks than the tile-norm pass takes keep every tile.
+int vtile_flags(Ctx& c, DevState& d, hipStream_t s) {
+  const int nk = c.nk, no = c.nao, na = c.naux, nib = c.nibz;
+  const i64 pe = i64(na) * no * no;
+  Mesh mesh{c.n};
+  for (int cp = 0; cp < 2; ++cp) {
+    c.vt_nz[cp].clear();
+    c.vt_off[cp].clear();
+  }
+  for (int x = 0; x < 4; ++x) c.vt_stats[x] = 0;
+  bool fits = no <= TN_MAXN;
+  for (const Blocks& B : c.bao) fits &= B.size.size() <= size_t(TN_MAXB);
+  if (!fits) return GWSYM_OK;
+  std::vector<TileNormItem> items;
+  std::vector<i64> off[2];
+  size_t nitems0 = 0;
+  i64 total = 0;
+  for (int cp = 0; cp < 2; ++cp) {
+    off[cp].assign(size_t(nib) * nk + 1, 0);
+    for (int i = 0; i < nib; ++i)
+      for (int k = 0; k < nk; ++k) {
+        const size_t p = size_t(i) * nk + k;
+        off[cp][p] = total;
+        // self-energy copy [i][k'][Q][a][b]: a at k0, b at k', Q at k0 - k'; polarization copy
+        // [i][k][a][Q][b]: a at k, b at k + q0, Q at q0
+        const int ia = cp == 0 ? i : c.rep[k];
+        const int ib = cp == 0 ? c.rep[k] : c.rep[mesh.add(k, c.ibz[i])];
+        const Blocks& BQ = cp == 0 ? c.baux[c.rep[mesh.sub(c.ibz[i], k)]] : c.baux[i];
+        const i64 nt = i64(c.bao[ia].size.size()) * i64(c.bao[ib].size.size());
+        for (size_t sg = 0; sg < BQ.size.size(); ++sg) {
+          TileNormItem it{};
+          it.v_off = i64(p) * pe;
+          it.out_off = total;
+          it.sQ = cp == 0 ? i64(no) * no : no;
+          it.sa = cp == 0 ? no : na * no;
+          it.sb = 1;
+          it.q0 = BQ.off[sg];
+          it.nq = BQ.size[sg];
+          it.bta = d.bt_ao[ia];
+          it.btb = d.bt_ao[ib];
+          items.push_back(it);
+          total += nt;
+        }
+      }
+    off[cp][size_t(nib) * nk] = total;
+    if (cp == 0) nitems0 = items.size();
+  }
+  void *ditems = nullptr, *dout = nullptr;
+  int st;
+  if ((st = upload(c, d, items, &ditems, s))) return st;
+  if ((st = dalloc(c, d, &dout, size_t(total) * 8))) return st;
+  launch_tile_norm(ditems, int(nitems0), d.VS, d.btab, static_cast<double*>(dout), no, s);
+  launch_tile_norm(static_cast<TileNormItem*>(ditems) + nitems0, int(items.size() - nitems0), d.VP, d.btab,
+                   static_cast<double*>(dout), no, s);
+  HIPCHECK(hipGetLastError());
+  std::vector<double> nrm(static_cast<size_t>(total), 0.0);
+  HIPCHECK(hipMemcpyAsync(nrm.data(), dout, size_t(total) * 8, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  dfree(d, ditems);
+  dfree(d, dout);
+  for (int cp = 0; cp < 2; ++cp) {
+    std::vector<uint8_t>& nz = c.vt_nz[cp];
+    nz.assign(size_t(off[cp][size_t(nib) * nk] - off[cp][0]), 0);
+    for (size_t p = 0; p < size_t(nib) * nk; ++p) {
+      double pair = 0;
+      for (i64 t = off[cp][p]; t < off[cp][p + 1]; ++t) pair += nrm[size_t(t)];
+      for (i64 t = off[cp][p]; t < off[cp][p + 1]; ++t) {
+        const bool kept = nrm[size_t(t)] > 1e-26 * pair;
+        nz[size_t(t - off[cp][0])] = kept;
+        c.vt_stats[2 * cp + 1] += kept;
+      }
+      c.vt_stats[2 * cp] += double(off[cp][p + 1] - off[cp][p]);
+    }
+    c.vt_off[cp].assign(off[cp].begin(), off[cp].end());
+    const i64 base = c.vt_off[cp][0];
+    for (i64& o : c.vt_off[cp]) o -= base;
+  }
+  return GWSYM_OK;
+}
+
+}  // namespace
+
 int device_load_V(Ctx& c, const void* Vin, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevState& d = *static_cast<DevState*>(c.dev_state);
@@ -1420,6 +1695,8 @@ int device_load_V(Ctx& c, const void* Vin, void* stream) {
     launch_brgemm(plan_of(g2, g2.launches[l]), b, d.partials, s);
     launch_brgemm(plan_of(g3, g3.launches[l]), b, d.partials, s);
   }
+  // the vanishing tiles, then the contraction lists that skip them
+  if ((st = vtile_flags(c, d, s)) || (st = plan_contractions(c, d, s))) return st;
   if (c.prm.precision != GWSYM_FP64) {
     const size_t n = size_t(nib) * nk * pe;
     if (!d.VP32) {
@@ -1494,6 +1771,7 @@ int device_polarization(Ctx& c, const void* G, void* P0, void* stream) {
   Bases b = bases_of(d);
   b.p[B_G] = const_cast<void*>(G);
   b.p[B_OUT] = P0;
+  b.p[B_KL] = d.p0_gemm.d_klist;
   // FP32 and split-bfloat16 contractions: FP32 copies of V (made once) and of G (here); W2
   // holds float2
   const bool f32 = c.prm.precision != GWSYM_FP64;
@@ -1531,6 +1809,7 @@ int device_self_energy(Ctx& c, const void* G, const void* P, void* S, void* stre
   b.p[B_G] = const_cast<void*>(G);
   b.p[B_P] = const_cast<void*>(P);
   b.p[B_OUT] = S;
+  b.p[B_KL] = d.s_gemmC.d_klist;
   const bool f32 = c.prm.precision != GWSYM_FP64;
   const int arith = c.prm.precision;
   unsigned mask = 0;
@@ -1579,6 +1858,7 @@ int device_exchange(Ctx& c, const void* G, void* K, void* stream) {
   Bases b = bases_of(d);
   b.p[B_G] = const_cast<void*>(G);
   b.p[B_OUT] = K;
+  b.p[B_KL] = d.hx_gemm.d_klist;
   for (size_t l = 0; l < d.hx_gemm.launches.size(); ++l) {
     const Range& rr = d.hx_right.launches[l];
     RowSegList R{static_cast<RowSeg*>(d.hx_right.d) + rr.t0, rr.nt, rr.r0};

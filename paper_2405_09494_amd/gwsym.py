@@ -187,7 +187,7 @@ class Context:
         return self
 
     _COMPLEX = {"U_ao", "U_aux", "O_ao", "O_aux", "Tf", "Tb", "Bf", "Bb"}
-    _REAL = {"tau"}
+    _REAL = {"tau", "vtile_stats"}
 
     def table(self, name):
         nb = lib.gwsym_table_size(self.h, name.encode())
