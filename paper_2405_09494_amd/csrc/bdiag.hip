@@ -3,7 +3,7 @@
 // The Green's function factors of eq. P0 and eq. sigma are block-diagonal in the symmetry
 // adapted basis (eq. mat_blk): each orbital block r of size n_r multiplies only the n_r
 // matching rows or columns of the three-index slabs.  Both kernels here form these products
-// as 16 x 16 output tiles on the MFMA (16 x 16 x 4 per instruction, four real instructions
+// as 16 x 16 output tiles on the MFMA (16 x 16 x 4 per instruction, three real instructions
 // per complex K step), with the K range of a tile cut to the blocks that touch it: an output
 // column c only sums over the k of its own block, and the entries of the block-diagonal
 // factor outside the blocks are zeros fed to the MFMA.
@@ -59,15 +59,6 @@ __device__ __forceinline__ void cmma(const V2 a, typename Mf<V2>::R as, const V2
   cr = Mf<V2>::mma(a.x, b.x, cr);
   ci = Mf<V2>::mma(a.y, b.y, ci);
   cx = Mf<V2>::mma(as, bs, cx);
-}
-
-// the same with four real MFMAs (4M), for kernels whose registers cannot hold a third accumulator
-template <typename V2>
-__device__ __forceinline__ void cmma4(const V2 a, const V2 b, typename Mf<V2>::A4& cr, typename Mf<V2>::A4& ci) {
-  cr = Mf<V2>::mma(a.x, b.x, cr);
-  ci = Mf<V2>::mma(a.x, b.y, ci);
-  cr = Mf<V2>::mma(-a.y, b.y, cr);
-  ci = Mf<V2>::mma(a.y, b.x, ci);
 }
 
 template <typename V2>
@@ -236,29 +227,31 @@ __global__ __launch_bounds__(512) void k_bd_right(const RowSeg* __restrict__ seg
     if (act) {
       for (int rt = rj; rt < nrt; rt += rstep) {   // uniform
         const V2* arow = rows + min(16 * rt + li, nr - 1) * ld;
-        A4 cr = A4{0, 0, 0, 0}, ci = cr, dr = cr, di = cr;
-        // each step's LDS read is issued one step ahead (addresses clamped into the row)
-        V2 an = arow[min(k0 + kq, n - 1)];
+        // one output at a time with three real products each (3M): the two outputs of a dual
+        // segment read the chunk's rows from LDS twice, which costs less than a fourth
+        // product and a second set of accumulators
+        auto product = [&](const V2 (&g)[KS], V2* o) __attribute__((always_inline)) {
+          A4 cr = A4{0, 0, 0, 0}, ci = cr, cx = cr;
+          // each step's LDS read is issued one step ahead (addresses clamped into the row)
+          V2 an = arow[min(k0 + kq, n - 1)];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          if (ks < nks) {   // uniform
-            const int k = k0 + 4 * ks + kq;
-            V2 a = an;
-            if (ks + 1 < KS) an = arow[min(k + 4, n - 1)];
-            if (k >= n) a = V2{0, 0};
-            cmma4<V2>(a, gf[ks], cr, ci);
-            if (dual) cmma4<V2>(a, gf2[ks], dr, di);
+          for (int ks = 0; ks < KS; ++ks) {
+            if (ks < nks) {   // uniform
+              const int k = k0 + 4 * ks + kq;
+              V2 a = an;
+              if (ks + 1 < KS) an = arow[min(k + 4, n - 1)];
+              if (k >= n) a = V2{0, 0};
+              cmma<V2>(a, a.x + a.y, g[ks], g[ks].x + g[ks].y, cr, ci, cx);
+            }
           }
-        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = 16 * rt + M::row(lane, j);
-          if (c < n && r < nr) {
-            const int64_t o = prow(ROWS * ch + r) + c;
-            out[o] = V2{R(cr[j]), R(ci[j])};
-            if (dual) out2[o] = V2{R(dr[j]), R(di[j])};
+          for (int j = 0; j < 4; ++j) {
+            const int r = 16 * rt + M::row(lane, j);
+            if (c < n && r < nr) o[prow(ROWS * ch + r) + c] = cval<V2>(cr, ci, cx, j);
           }
-        }
+        };
+        product(gf, out);
+        if (dual) product(gf2, out2);
       }
     }
     if (ch + 1 < c1) {
