@@ -320,8 +320,9 @@ def main():
                          "of known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the distributed path is a design "
-              "description, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is "
+              "designed (pairs split by flops, one all-reduce of P0 and Sigma per iteration) but not "
+              "implemented", file=sys.stderr)
         sys.exit(2)
     legs = [x for x in (args.legs or "").split(",") if x and x != "none"]
     for x in legs:

@@ -254,7 +254,7 @@ def ir_transform_matrices(grid, boson):
 
 
 # ----------------------------------------------------------------------------
-# free Green's function (spec closed form; Sec. 4.1 definition of G)
+# free Green's function (closed form from the eigen-decomposition of F; Sec. 4.1 definition of G)
 
 
 def fermi_factor_parts(eps: np.ndarray, tau: np.ndarray, beta: float) -> np.ndarray:
