@@ -40,11 +40,11 @@ CRYSTAL_NAMES = {"sc": "simple cubic Pm-3m", "rocksalt": "rocksalt Fm-3m (two at
 
 
 def source_digest():
-    """sha256 over the kernel and launch-plan sources and the stored launch plans: measured
-    counters apply only to the code and plans they were taken from."""
+    """sha256 over the kernel and launch-plan sources, the default launch plan and the stored
+    launch plans: measured counters apply only to the code and plans they were taken from."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("csrc/kernels.hip", "csrc/bdiag.hip", "csrc/pipeline.hip", "plans.json"):
+    for f in ("csrc/kernels.hip", "csrc/bdiag.hip", "csrc/pipeline.hip", "csrc/capi.cpp", "plans.json"):
         path = os.path.join(ROOT, "paper_2405_09494_amd", f)
         if os.path.exists(path):
             with open(path, "rb") as fh:

@@ -260,7 +260,7 @@ def test_tuning_defaults_and_state_errors():
     from paper_2405_09494_amd import gwsym
     ctx = gwsym.Context(10.0, 8, 17, tau_chunk=3)
     t = ctx.get_tuning()
-    assert t == {"tau_chunk": 3, "wg_target": [8192] * 3, "cols": [32] * 3, "xcd_order": [3, 1, 1], "kdepth": [0] * 3,
+    assert t == {"tau_chunk": 3, "wg_target": [16384, 8192, 8192], "cols": [32] * 3, "xcd_order": [3, 1, 1], "kdepth": [0] * 3,
                  "prefetch": [2] * 3}
     with pytest.raises(gwsym.GwsymError, match="ESTATE"):
         ctx.set_tuning(t, stream=0)
